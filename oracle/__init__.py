@@ -1,0 +1,133 @@
+"""bsort oracle -- TEST INFRASTRUCTURE ONLY.
+
+ctypes loader for the plain single-threaded C oracle in ``bsort_oracle.c``
+(written from Algorithms 1-5 of the bsort paper).  Only the tests, the
+smoke check and the benchmark's CPU-baseline leg may import this package;
+the GPU library never does.
+
+Key interpretation: every key is a raw w-bit pattern carried in a uint64.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "bsort_oracle.c")
+
+UNSIGNED, SIGNED, FLOAT = 0, 1, 2
+LOMUTO, STABLE = 0, 1
+
+_libs = {}
+
+
+def lib_path(mutant: int = 0) -> str:
+    name = "libbsort_oracle.so" if mutant == 0 else f"libbsort_oracle_mut{mutant}.so"
+    return os.path.join(_HERE, name)
+
+
+def build(mutant: int = 0) -> str:
+    """Compile the oracle (or a deliberately wrong mutant of it) with gcc."""
+    out = lib_path(mutant)
+    cmd = ["gcc", "-O3", "-std=c11", "-Wall", "-Wextra", "-shared", "-fPIC",
+           f"-DBSO_MUTANT={mutant}", "-o", out + ".tmp", _SRC]
+    subprocess.run(cmd, check=True, cwd=_HERE)
+    os.replace(out + ".tmp", out)
+    return out
+
+
+def _load(mutant: int = 0) -> ctypes.CDLL:
+    if mutant in _libs:
+        return _libs[mutant]
+    path = lib_path(mutant)
+    if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC):
+        build(mutant)
+    lib = ctypes.CDLL(path)
+    u64p = ctypes.POINTER(ctypes.c_uint64)
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    dp = ctypes.POINTER(ctypes.c_double)
+    lib.bso_sort.argtypes = [u64p, i64p, ctypes.c_uint64, ctypes.c_int, ctypes.c_int,
+                             ctypes.c_int, ctypes.c_int, ctypes.c_int, u64p, i64p]
+    lib.bso_sort.restype = ctypes.c_int
+    lib.bso_select.argtypes = [u64p, ctypes.c_uint64, ctypes.c_int, ctypes.c_int,
+                               ctypes.c_int, ctypes.c_int, ctypes.c_uint64, u64p, i64p]
+    lib.bso_select.restype = ctypes.c_int
+    lib.bso_permute_backward.argtypes = [dp, i64p, ctypes.c_uint64, ctypes.c_uint64, dp]
+    lib.bso_permute_backward.restype = ctypes.c_int
+    _libs[mutant] = lib
+    return lib
+
+
+def _ptr(a: Optional[np.ndarray], ctype):
+    if a is None:
+        return None
+    return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+def sort(keys, w: int, mode: int, asc: bool = True, mant_bits: int = 0,
+         flavour: int = STABLE, with_idx: bool = True, snapshots: bool = False,
+         mutant: int = 0):
+    """Sort w-bit patterns.  Returns (keys, idx) or, with snapshots=True,
+    (keys, idx, snap, snap_idx) where snap has shape (w+1, n)."""
+    lib = _load(mutant)
+    k = np.ascontiguousarray(np.asarray(keys, dtype=np.uint64)).copy()
+    n = k.size
+    idx = np.arange(n, dtype=np.int64) if with_idx else None
+    snap = np.zeros((w + 1, n), dtype=np.uint64) if snapshots else None
+    snap_i = np.zeros((w + 1, n), dtype=np.int64) if (snapshots and with_idx) else None
+    rc = lib.bso_sort(_ptr(k, ctypes.c_uint64), _ptr(idx, ctypes.c_int64), n, w, mode,
+                      mant_bits, int(bool(asc)), flavour, _ptr(snap, ctypes.c_uint64),
+                      _ptr(snap_i, ctypes.c_int64))
+    if rc != 0:
+        raise ValueError(f"bso_sort rejected its arguments (rc={rc})")
+    if snapshots:
+        return k, idx, snap, snap_i
+    return k, idx
+
+
+def select(keys, w: int, mode: int, asc: bool, j: int, mant_bits: int = 0) -> Tuple[int, int]:
+    """(key, source index) at sorted position j of a stable sort."""
+    lib = _load()
+    k = np.ascontiguousarray(np.asarray(keys, dtype=np.uint64))
+    ko = ctypes.c_uint64(0)
+    io = ctypes.c_int64(0)
+    rc = lib.bso_select(_ptr(k, ctypes.c_uint64), k.size, w, mode, mant_bits,
+                        int(bool(asc)), j, ctypes.byref(ko), ctypes.byref(io))
+    if rc != 0:
+        raise ValueError(f"bso_select rejected its arguments (rc={rc})")
+    return int(ko.value), int(io.value)
+
+
+def permute_backward(grad_out: np.ndarray, idx: np.ndarray) -> np.ndarray:
+    """grad_in[r, idx[r, j]] = grad_out[r, j] (float64)."""
+    lib = _load()
+    g = np.ascontiguousarray(grad_out, dtype=np.float64)
+    ix = np.ascontiguousarray(idx, dtype=np.int64)
+    rows, cols = g.shape
+    out = np.zeros_like(g)
+    rc = lib.bso_permute_backward(_ptr(g, ctypes.c_double), _ptr(ix, ctypes.c_int64),
+                                  rows, cols, _ptr(out, ctypes.c_double))
+    if rc != 0:
+        raise ValueError("idx is not a permutation of each row")
+    return out
+
+
+# Key interpretation per dtype name: (w, mode, mantissa bits).
+DTYPES = {
+    "u8": (8, UNSIGNED, 0), "u16": (16, UNSIGNED, 0), "u32": (32, UNSIGNED, 0),
+    "u64": (64, UNSIGNED, 0),
+    "i8": (8, SIGNED, 0), "i16": (16, SIGNED, 0), "i32": (32, SIGNED, 0),
+    "i64": (64, SIGNED, 0),
+    "e4m3": (8, FLOAT, 3), "e5m2": (8, FLOAT, 2), "f16": (16, FLOAT, 10),
+    "bf16": (16, FLOAT, 7), "f32": (32, FLOAT, 23), "f64": (64, FLOAT, 52),
+}
+
+
+def sort_dtype(bits: np.ndarray, dtype: str, asc: bool = True, flavour: int = STABLE):
+    """Sort raw bit patterns of a named dtype; returns (bits, idx)."""
+    w, mode, mant = DTYPES[dtype]
+    return sort(bits, w, mode, asc=asc, mant_bits=mant, flavour=flavour)
