@@ -1,0 +1,165 @@
+/*
+ * bsort.h -- C ABI of libbsort, an MI355X (gfx950) implementation of the
+ * bsort bit-partition sort (Guzman, arXiv 2603.08929).
+ *
+ * The operation (Section II, Algorithms 1-2; Section III, Algorithms 3-5):
+ * keys are split, most significant bit first, into a front and a back part
+ * on one bit at a time; every part is split again on the next lower bit.
+ * Ascending puts the 0-side first (Algorithm 1).  Two's-complement keys run
+ * the sign-bit pass in the inverse direction (Algorithm 3); IEEE-754 style
+ * keys (sign | exponent | mantissa) do the same and also sort the negative
+ * half in the inverse direction on all lower bits (Section III-B's three-pass
+ * procedure and the Fig. 3 trace).  Resulting order, ascending:
+ *   unsigned: numeric;  signed: numeric;
+ *   float: -NaN (largest payload first) < -inf < ... < -0 < +0 < ... < +inf
+ *          < +NaN (smallest payload first)   (Section III-C special values)
+ * Descending is the exact reverse on distinct keys.  Keys are compared as
+ * raw bit patterns only -- never loaded as floating point -- so subnormals
+ * and NaN payloads keep their bits.
+ *
+ * Every split is stable (both parts keep input order, as in the traces of
+ * Figs. 1 and 2), so the optional index output is THE stable permutation:
+ * equal bit patterns keep their input order in both directions.
+ *
+ * Common conventions
+ * ------------------
+ * - All pointers except `stream` are DEVICE pointers owned by the caller.
+ * - `stream` is a hipStream_t (NULL = the default stream).  Calls are
+ *   asynchronous on that stream: they enqueue kernels and return; they never
+ *   allocate device memory and never synchronize.  Calls on one scratch
+ *   buffer must not overlap; distinct scratch buffers may run concurrently.
+ * - `keys` is sorted in place (the result lands in the caller's buffer).
+ * - `indices` (nullable): receives the gather permutation out[j] = in[idx[j]],
+ *   0-based and local to each segment (as torch.sort returns it).  uint32
+ *   by default; int64 with BSORT_IDX64.
+ * - `scratch` of at least bsort_scratch_bytes(...) bytes; 256-byte aligned.
+ *   Its contents are undefined afterwards.
+ * - Arguments are validated before anything is enqueued; on an error
+ *   nothing is written to any buffer.
+ */
+#ifndef BSORT_H
+#define BSORT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---- */
+#define BSORT_OK 0
+#define BSORT_EINVAL (-1)   /* null pointer with n > 0, unknown flag bits, bad key type */
+#define BSORT_ESCRATCH (-2) /* scratch smaller than bsort_scratch_bytes()                */
+#define BSORT_ETOOBIG (-3)  /* a segment of 2^32 keys or more with uint32 indices        */
+#define BSORT_EHIP (-4)     /* the HIP runtime refused a launch (see bsort_strerror)     */
+#define BSORT_ENODEV (-5)   /* the current device is not a gfx950 GPU                    */
+
+/* ---- flags ---- */
+#define BSORT_DESCENDING 1u /* non-increasing order                                       */
+#define BSORT_NO_SKIP 2u    /* partition on every bit; no AND/OR skip of constant bits     */
+#define BSORT_NO_FINISH 4u  /* no in-LDS finish of small parts: every bit is a global pass */
+#define BSORT_PLAIN (BSORT_NO_SKIP | BSORT_NO_FINISH) /* the paper's w full passes         */
+#define BSORT_IDX64 8u      /* indices are int64 instead of uint32                         */
+
+/* ---- key types (for bsort_scratch_bytes and the generic entry point) ---- */
+#define BSORT_KEY_U 0 /* unsigned integer                     */
+#define BSORT_KEY_I 1 /* two's-complement integer             */
+#define BSORT_KEY_F 2 /* sign | exponent | mantissa float      */
+
+/*
+ * Bytes of device scratch a call needs.  key_bytes in {1,2,4,8};
+ * num_segments = 1 for the single-array entry points.  with_indices != 0
+ * when `indices` will be non-NULL.  The figure is O(n): a second key buffer
+ * (n * key_bytes), a second index buffer (4n, or 8n with BSORT_IDX64), and
+ * O(n/4096 + num_segments) bytes of work lists; BSORT_NO_FINISH raises the
+ * work-list part to O(n).  Returns 0 for invalid arguments.
+ */
+size_t bsort_scratch_bytes(int key_bytes, uint64_t n, uint64_t num_segments,
+                           int with_indices, uint32_t flags);
+
+/*
+ * Single-array sort of keys[0, n) (Algorithms 2, 3 and 4 of the paper for
+ * the U, I and F families).  f8 serves both e4m3 and e5m2 and f16 serves
+ * both fp16 and bfloat16: the order only needs "sign bit first, then a
+ * magnitude in sign-magnitude form", not the exponent width (Section III-C).
+ * n = 0 is a no-op; n = 1 writes index 0.
+ */
+int bsort_u8(uint8_t *keys, uint64_t n, uint32_t flags, void *indices, void *scratch,
+             size_t scratch_bytes, void *stream);
+int bsort_u16(uint16_t *keys, uint64_t n, uint32_t flags, void *indices, void *scratch,
+              size_t scratch_bytes, void *stream);
+int bsort_u32(uint32_t *keys, uint64_t n, uint32_t flags, void *indices, void *scratch,
+              size_t scratch_bytes, void *stream);
+int bsort_u64(uint64_t *keys, uint64_t n, uint32_t flags, void *indices, void *scratch,
+              size_t scratch_bytes, void *stream);
+int bsort_i8(int8_t *keys, uint64_t n, uint32_t flags, void *indices, void *scratch,
+             size_t scratch_bytes, void *stream);
+int bsort_i16(int16_t *keys, uint64_t n, uint32_t flags, void *indices, void *scratch,
+              size_t scratch_bytes, void *stream);
+int bsort_i32(int32_t *keys, uint64_t n, uint32_t flags, void *indices, void *scratch,
+              size_t scratch_bytes, void *stream);
+int bsort_i64(int64_t *keys, uint64_t n, uint32_t flags, void *indices, void *scratch,
+              size_t scratch_bytes, void *stream);
+int bsort_f8(uint8_t *keys, uint64_t n, uint32_t flags, void *indices, void *scratch,
+             size_t scratch_bytes, void *stream);
+int bsort_f16(uint16_t *keys, uint64_t n, uint32_t flags, void *indices, void *scratch,
+              size_t scratch_bytes, void *stream);
+int bsort_f32(float *keys, uint64_t n, uint32_t flags, void *indices, void *scratch,
+              size_t scratch_bytes, void *stream);
+int bsort_f64(double *keys, uint64_t n, uint32_t flags, void *indices, void *scratch,
+              size_t scratch_bytes, void *stream);
+
+/*
+ * Segmented (batched) sort: num_segments independent arrays stored back to
+ * back in keys[0, n), segment s being [offsets[s], offsets[s+1]).  offsets is
+ * a DEVICE array of num_segments+1 int64 with offsets[0] = 0,
+ * non-decreasing, offsets[num_segments] = n.  Each segment is sorted as by
+ * the single-array call (the same result, bit for bit), in one pass over
+ * all of them.  Indices are local to each segment.  Offsets are read on the
+ * device; values outside [0, n] or decreasing are clamped so that no access
+ * leaves keys[0, n) (the result is then unspecified but memory-safe).
+ * key_type is BSORT_KEY_U/I/F, key_bytes in {1,2,4,8}.
+ */
+int bsort_segmented(void *keys, int key_type, int key_bytes, const int64_t *offsets,
+                    uint64_t num_segments, uint64_t n, uint32_t flags, void *indices,
+                    void *scratch, size_t scratch_bytes, void *stream);
+
+/* Same as bsort_segmented, typed for float32 and int32 keys. */
+int bsort_segmented_f32(float *keys, const int64_t *offsets, uint64_t num_segments,
+                        uint64_t n, uint32_t flags, void *indices, void *scratch,
+                        size_t scratch_bytes, void *stream);
+int bsort_segmented_i32(int32_t *keys, const int64_t *offsets, uint64_t num_segments,
+                        uint64_t n, uint32_t flags, void *indices, void *scratch,
+                        size_t scratch_bytes, void *stream);
+
+/* Generic single-array form of the typed entry points above. */
+int bsort_sort(void *keys, int key_type, int key_bytes, uint64_t n, uint32_t flags,
+               void *indices, void *scratch, size_t scratch_bytes, void *stream);
+
+/*
+ * Backward of values = x.gather(-1, idx) for rows of length cols (the
+ * derivative of a sort is the inverse permutation of its gradient):
+ *   grad_in[r, idx[r, j]] = grad_sorted[r, j]     for r < rows, j < cols.
+ * elem_bytes 2 (fp16 / bf16, moved bit for bit), 4 (f32) or 8 (f64);
+ * indices uint32, or int64 with BSORT_IDX64 in flags.  idx must hold a
+ * permutation of 0..cols-1 in every row (as a sort returns it); entries
+ * outside [0, cols) are skipped.  No arithmetic is done on the values.
+ */
+int bsort_backward_scatter(const void *grad_sorted, const void *indices, uint64_t rows,
+                           uint64_t cols, int elem_bytes, void *grad_in, uint32_t flags,
+                           void *stream);
+
+/* Text for a status code (for BSORT_EHIP, the last HIP error seen). */
+const char *bsort_strerror(int status);
+
+/* Device status word written by the last call that used this scratch:
+ * 0 = fine; bit 0 = a cross-tile wait gave up (result invalid).  Reads it
+ * synchronously on `stream`.  Returns the word, or a negative status. */
+int bsort_device_status(const void *scratch, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BSORT_H */

@@ -1,0 +1,14 @@
+"""bsort on MI355X: MSB-first stable bit-partition sort (arXiv 2603.08929)
+as HIP kernels for gfx950 behind a C ABI (include/bsort.h).
+
+    import paper_2603_08929_amd as bsort
+    values, indices = bsort.sort(x)               # 1-D, stable
+    idx = bsort.sort_(x, descending=True)         # in place
+    idx = bsort.segmented_sort_(x, offsets)       # many arrays, one pass
+    y = bsort.BSortFunction.apply(x, -1, False)   # differentiable
+"""
+from ._lib import (DESCENDING, IDX64, NO_FINISH, NO_SKIP, PLAIN, KEY_F, KEY_I,  # noqa: F401
+                   KEY_U, lib, strerror)
+from .api import (backward_scatter, device_status, scratch_bytes, segmented_sort_,  # noqa: F401
+                  sort, sort_, key_type)
+from .autograd import BSortFunction, sort_along  # noqa: F401

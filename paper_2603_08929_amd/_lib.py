@@ -1,0 +1,78 @@
+"""ctypes binding of libbsort.so: the C ABI of include/bsort.h, same names,
+argument marshalling only.  Every step of the sort runs in the library's
+HIP kernels; there is no fallback: if the library is missing this module
+raises on import."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+# torch ships its own HIP runtime (soname libamdhip64.so.7).  Loading torch
+# first makes libbsort.so bind to that already-loaded copy, so the process
+# has exactly one HIP runtime and torch's streams and memory are valid here.
+import torch  # noqa: F401
+
+from .build import LIB
+
+if not os.path.exists(LIB):
+    raise ImportError(
+        f"libbsort.so not found at {LIB}; build it with "
+        "`python -m paper_2603_08929_amd.build` (hipcc, gfx950)")
+
+lib = ctypes.CDLL(LIB)
+
+# status codes and flags (include/bsort.h)
+OK, EINVAL, ESCRATCH, ETOOBIG, EHIP, ENODEV = 0, -1, -2, -3, -4, -5
+DESCENDING, NO_SKIP, NO_FINISH, IDX64 = 1, 2, 4, 8
+PLAIN = NO_SKIP | NO_FINISH
+KEY_U, KEY_I, KEY_F = 0, 1, 2
+
+_vp, _u64, _u32, _i, _sz = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int, ctypes.c_size_t
+
+TYPED = ["u8", "u16", "u32", "u64", "i8", "i16", "i32", "i64", "f8", "f16", "f32", "f64"]
+SYMBOLS = ["bsort_scratch_bytes", "bsort_sort", "bsort_segmented", "bsort_segmented_f32",
+           "bsort_segmented_i32", "bsort_backward_scatter", "bsort_strerror",
+           "bsort_device_status"] + [f"bsort_{t}" for t in TYPED]
+
+lib.bsort_scratch_bytes.argtypes = [_i, _u64, _u64, _i, _u32]
+lib.bsort_scratch_bytes.restype = _sz
+for t in TYPED:
+    fn = getattr(lib, f"bsort_{t}")
+    fn.argtypes = [_vp, _u64, _u32, _vp, _vp, _sz, _vp]
+    fn.restype = _i
+lib.bsort_sort.argtypes = [_vp, _i, _i, _u64, _u32, _vp, _vp, _sz, _vp]
+lib.bsort_sort.restype = _i
+lib.bsort_segmented.argtypes = [_vp, _i, _i, _vp, _u64, _u64, _u32, _vp, _vp, _sz, _vp]
+lib.bsort_segmented.restype = _i
+for t in ("f32", "i32"):
+    fn = getattr(lib, f"bsort_segmented_{t}")
+    fn.argtypes = [_vp, _vp, _u64, _u64, _u32, _vp, _vp, _sz, _vp]
+    fn.restype = _i
+lib.bsort_backward_scatter.argtypes = [_vp, _vp, _u64, _u64, _i, _vp, _u32, _vp]
+lib.bsort_backward_scatter.restype = _i
+lib.bsort_strerror.argtypes = [_i]
+lib.bsort_strerror.restype = ctypes.c_char_p
+lib.bsort_device_status.argtypes = [_vp, _vp]
+lib.bsort_device_status.restype = _i
+
+
+def strerror(rc: int) -> str:
+    return lib.bsort_strerror(rc).decode()
+
+
+def check(rc: int, what: str) -> None:
+    if rc != OK:
+        raise RuntimeError(f"{what} failed: {strerror(rc)} (status {rc})")
+
+
+# the same names as the C ABI
+bsort_scratch_bytes = lib.bsort_scratch_bytes
+bsort_sort = lib.bsort_sort
+bsort_segmented = lib.bsort_segmented
+bsort_segmented_f32 = lib.bsort_segmented_f32
+bsort_segmented_i32 = lib.bsort_segmented_i32
+bsort_backward_scatter = lib.bsort_backward_scatter
+bsort_strerror = lib.bsort_strerror
+bsort_device_status = lib.bsort_device_status
+for _t in TYPED:
+    globals()[f"bsort_{_t}"] = getattr(lib, f"bsort_{_t}")

@@ -1,0 +1,124 @@
+"""PyTorch-facing calls: torch supplies device memory and the current HIP
+stream; the sort itself is the library's kernels (see _lib.py)."""
+from __future__ import annotations
+
+from typing import Optional, Tuple
+
+import torch
+
+from . import _lib
+from ._lib import DESCENDING, IDX64, KEY_F, KEY_I, KEY_U, NO_FINISH, NO_SKIP, PLAIN  # noqa
+
+# torch dtype -> (key family, key bytes)
+KEY_TYPES = {
+    torch.uint8: (KEY_U, 1), torch.int8: (KEY_I, 1),
+    torch.int16: (KEY_I, 2), torch.int32: (KEY_I, 4), torch.int64: (KEY_I, 8),
+    torch.float16: (KEY_F, 2), torch.bfloat16: (KEY_F, 2),
+    torch.float32: (KEY_F, 4), torch.float64: (KEY_F, 8),
+}
+for _name, _kt in (("uint16", (KEY_U, 2)), ("uint32", (KEY_U, 4)), ("uint64", (KEY_U, 8)),
+                   ("float8_e4m3fn", (KEY_F, 1)), ("float8_e5m2", (KEY_F, 1)),
+                   ("float8_e4m3fnuz", (KEY_F, 1)), ("float8_e5m2fnuz", (KEY_F, 1))):
+    if hasattr(torch, _name):
+        KEY_TYPES[getattr(torch, _name)] = _kt
+
+
+def key_type(dtype: torch.dtype) -> Tuple[int, int]:
+    try:
+        return KEY_TYPES[dtype]
+    except KeyError:
+        raise TypeError(f"bsort: unsupported key dtype {dtype}") from None
+
+
+def scratch_bytes(dtype: torch.dtype, n: int, num_segments: int = 1,
+                  with_indices: bool = True, flags: int = 0) -> int:
+    _, kb = key_type(dtype)
+    return int(_lib.bsort_scratch_bytes(kb, n, num_segments, int(with_indices), flags))
+
+
+def _stream(device: torch.device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _flags(descending: bool, flags: int, idx64: bool) -> int:
+    return flags | (DESCENDING if descending else 0) | (IDX64 if idx64 else 0)
+
+
+def sort_(keys: torch.Tensor, descending: bool = False, return_indices: bool = True,
+          idx64: bool = False, flags: int = 0, scratch: Optional[torch.Tensor] = None
+          ) -> Optional[torch.Tensor]:
+    """Sorts a contiguous 1-D device tensor in place; returns the stable
+    permutation (uint32 as int32 storage, or int64 with idx64) or None."""
+    if not keys.is_cuda or keys.dim() != 1 or not keys.is_contiguous():
+        raise ValueError("bsort.sort_: need a contiguous 1-D GPU tensor")
+    kt, kb = key_type(keys.dtype)
+    n = keys.numel()
+    fl = _flags(descending, flags, idx64 and return_indices)
+    idx = None
+    if return_indices:
+        idx = torch.empty(n, dtype=torch.int64 if idx64 else torch.int32, device=keys.device)
+    need = _lib.bsort_scratch_bytes(kb, n, 1, int(return_indices), fl)
+    if scratch is None or scratch.numel() < need:
+        scratch = torch.empty(max(need, 256), dtype=torch.uint8, device=keys.device)
+    rc = _lib.bsort_sort(keys.data_ptr(), kt, kb, n, fl,
+                         idx.data_ptr() if idx is not None else None,
+                         scratch.data_ptr(), scratch.numel(), _stream(keys.device))
+    _lib.check(rc, "bsort_sort")
+    return idx
+
+
+def sort(x: torch.Tensor, descending: bool = False, idx64: bool = True, flags: int = 0
+         ) -> Tuple[torch.Tensor, torch.Tensor]:
+    """torch.sort-like on a 1-D tensor: (values, indices), stable."""
+    v = x.contiguous().clone()
+    idx = sort_(v, descending=descending, return_indices=True, idx64=idx64, flags=flags)
+    return v, idx
+
+
+def segmented_sort_(keys: torch.Tensor, offsets: torch.Tensor, descending: bool = False,
+                    return_indices: bool = True, idx64: bool = False, flags: int = 0,
+                    scratch: Optional[torch.Tensor] = None) -> Optional[torch.Tensor]:
+    """Sorts the segments [offsets[s], offsets[s+1]) of a 1-D tensor in place,
+    all in one pass.  offsets: int64 device tensor of num_segments + 1."""
+    if not keys.is_cuda or keys.dim() != 1 or not keys.is_contiguous():
+        raise ValueError("bsort.segmented_sort_: need a contiguous 1-D GPU tensor")
+    if offsets.dtype != torch.int64 or not offsets.is_cuda or not offsets.is_contiguous():
+        raise ValueError("bsort.segmented_sort_: offsets must be a contiguous int64 GPU tensor")
+    kt, kb = key_type(keys.dtype)
+    n = keys.numel()
+    B = offsets.numel() - 1
+    fl = _flags(descending, flags, idx64 and return_indices)
+    idx = None
+    if return_indices:
+        idx = torch.empty(n, dtype=torch.int64 if idx64 else torch.int32, device=keys.device)
+    need = _lib.bsort_scratch_bytes(kb, n, max(B, 1), int(return_indices), fl)
+    if scratch is None or scratch.numel() < need:
+        scratch = torch.empty(max(need, 256), dtype=torch.uint8, device=keys.device)
+    rc = _lib.bsort_segmented(keys.data_ptr(), kt, kb, offsets.data_ptr(), B, n, fl,
+                              idx.data_ptr() if idx is not None else None,
+                              scratch.data_ptr(), scratch.numel(), _stream(keys.device))
+    _lib.check(rc, "bsort_segmented")
+    return idx
+
+
+def backward_scatter(grad_sorted: torch.Tensor, indices: torch.Tensor) -> torch.Tensor:
+    """grad_in[r, idx[r, j]] = grad_sorted[r, j] along the last dim."""
+    g = grad_sorted.contiguous()
+    ix = indices.contiguous()
+    cols = g.shape[-1] if g.dim() else 1
+    rows = g.numel() // cols if cols else 0
+    out = torch.zeros_like(g)
+    if ix.dtype == torch.int64:
+        fl = IDX64
+    elif ix.dtype == torch.int32:
+        fl = 0
+    else:
+        raise TypeError("indices must be int32 (uint32 payload) or int64")
+    rc = _lib.bsort_backward_scatter(g.data_ptr(), ix.data_ptr(), rows, cols,
+                                     g.element_size(), out.data_ptr(), fl, _stream(g.device))
+    _lib.check(rc, "bsort_backward_scatter")
+    return out
+
+
+def device_status(scratch: torch.Tensor) -> int:
+    return int(_lib.bsort_device_status(scratch.data_ptr(), _stream(scratch.device)))

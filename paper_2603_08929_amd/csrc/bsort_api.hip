@@ -1,0 +1,440 @@
+// Host side of libbsort: argument validation, scratch layout and the launch
+// sequence behind the C ABI declared in include/bsort.h.
+//
+// One call enqueues, on the caller's stream and without any host readback:
+//   init   -- zero the work-list counters and look-back words
+//   (validate offsets, segmented calls only)
+//   seed   -- level-0 work lists: each user segment is split on its top bit
+//             (the first pass of Algorithms 2-4) or finished in LDS
+//   w x { level, plan } -- one breadth-first level of the recursion each
+//   copy   -- large retired segments not yet in the caller's buffer
+//   finish -- small segments: all remaining bits in LDS, final write
+// Grids are sized from upper bounds; the kernels read their real work from
+// device memory and loop until it is exhausted.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstring>
+
+#include "bsort.h"
+#include "bsort_kernels.hpp"
+
+using namespace bsort;
+
+namespace {
+
+thread_local char g_hip_err[256] = "";
+
+int hip_fail(hipError_t e, const char *what) {
+  snprintf(g_hip_err, sizeof g_hip_err, "%s: %s", what, hipGetErrorString(e));
+  return BSORT_EHIP;
+}
+
+struct DevState {
+  int checked;
+  int ok;
+  int cus;
+};
+DevState g_dev[64];
+
+int device_check(int *cus) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev < 0 || dev >= 64) return BSORT_ENODEV;
+  DevState &d = g_dev[dev];
+  if (!d.checked) {
+    hipDeviceProp_t p;
+    e = hipGetDeviceProperties(&p, dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+    d.ok = strncmp(p.gcnArchName, "gfx950", 6) == 0;
+    d.cus = p.multiProcessorCount;
+    d.checked = 1;
+  }
+  if (!d.ok) return BSORT_ENODEV;
+  *cus = d.cus;
+  return BSORT_OK;
+}
+
+// Launch shapes per key width: level tile = LB * LIPT keys, finish
+// threshold T = FB * FIPT keys.
+template <typename KT>
+struct Tune {
+  static constexpr int LB = 256;
+  static constexpr int LIPT = sizeof(KT) == 8 ? 8 : 16;
+  static constexpr int FB = 256;
+  static constexpr int FIPT = 16;
+  static constexpr uint32_t TILE = LB * LIPT;
+  static constexpr uint32_t TFIN = FB * FIPT;
+};
+
+void shape_for(int key_bytes, uint32_t *tile, uint32_t *tfin) {
+  switch (key_bytes) {
+    case 1: *tile = Tune<uint8_t>::TILE; *tfin = Tune<uint8_t>::TFIN; break;
+    case 2: *tile = Tune<uint16_t>::TILE; *tfin = Tune<uint16_t>::TFIN; break;
+    case 4: *tile = Tune<uint32_t>::TILE; *tfin = Tune<uint32_t>::TFIN; break;
+    default: *tile = Tune<uint64_t>::TILE; *tfin = Tune<uint64_t>::TFIN; break;
+  }
+}
+
+constexpr uint32_t ALL_FLAGS =
+    BSORT_DESCENDING | BSORT_NO_SKIP | BSORT_NO_FINISH | BSORT_IDX64;
+
+size_t up256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Scratch layout.  The header sits at offset 0 (bsort_device_status reads
+// it there).  Bounds: a live segment holds more than T keys (at least 2
+// with BSORT_NO_FINISH); a level's tiles are at most n/TILE + segments;
+// every parent yields at most two finish entries per level; copy entries
+// hold more than T keys each.
+struct Layout {
+  size_t hdr, flags, segs[2], acc[2], tmap[2], fin, cpy, keys1, idx0, idx1, total;
+  uint64_t smax, tmax, fmax, cmax;
+};
+
+bool make_layout(int key_bytes, uint64_t n, uint64_t B, bool with_idx, uint32_t flags,
+                 Layout *L) {
+  if (key_bytes != 1 && key_bytes != 2 && key_bytes != 4 && key_bytes != 8) return false;
+  uint32_t tile, tfin;
+  shape_for(key_bytes, &tile, &tfin);
+  const uint64_t w = 8ull * key_bytes;
+  const bool no_finish = (flags & BSORT_NO_FINISH) != 0;
+  L->smax = (no_finish ? n / 2 : n / (tfin + 1ull)) + 1;
+  L->tmax = n / tile + L->smax + 1;
+  const uint64_t fb = B + 2 * w * L->smax + 1;
+  L->fmax = (fb < n + 1 ? fb : n + 1);
+  L->cmax = n / (tfin + 1ull) + 1;
+  size_t off = 0;
+  L->hdr = off; off = up256(off + sizeof(Header));
+  L->flags = off; off = up256(off + L->tmax * 8);
+  for (int i = 0; i < 2; ++i) { L->segs[i] = off; off = up256(off + L->smax * sizeof(Seg)); }
+  for (int i = 0; i < 2; ++i) { L->acc[i] = off; off = up256(off + L->smax * sizeof(Acc)); }
+  for (int i = 0; i < 2; ++i) { L->tmap[i] = off; off = up256(off + L->tmax * 4); }
+  L->fin = off; off = up256(off + L->fmax * sizeof(Seg));
+  L->cpy = off; off = up256(off + L->cmax * sizeof(Seg));
+  L->keys1 = off; off = up256(off + n * (size_t)key_bytes);
+  L->idx0 = L->idx1 = 0;
+  if (with_idx) {
+    if (flags & BSORT_IDX64) { L->idx0 = off; off = up256(off + n * 4); }
+    L->idx1 = off; off = up256(off + n * 4);
+  }
+  L->total = off;
+  return true;
+}
+
+template <typename K>
+int occupancy(K kernel, int block) {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, block, 0) != hipSuccess ||
+      nb < 1)
+    nb = 1;
+  return nb;
+}
+
+uint32_t clamp_grid(uint64_t want, uint64_t cap) {
+  if (want < 1) want = 1;
+  return (uint32_t)(want < cap ? want : cap);
+}
+
+template <typename KT, bool IDX>
+int launch_all(KT *keys, uint64_t n, const int64_t *offsets, uint64_t B, int mode,
+               uint32_t flags, void *indices, char *scr, const Layout &L, int cus,
+               hipStream_t st) {
+  using TU = Tune<KT>;
+  const int w = 8 * (int)sizeof(KT);
+  const int desc = (flags & BSORT_DESCENDING) ? 1 : 0;
+  const int idx64 = (IDX && (flags & BSORT_IDX64)) ? 1 : 0;
+  const int no_skip = (flags & BSORT_NO_SKIP) ? 1 : 0;
+  const int no_finish = (flags & BSORT_NO_FINISH) ? 1 : 0;
+
+  Header *hdr = reinterpret_cast<Header *>(scr + L.hdr);
+  uint64_t *lb = reinterpret_cast<uint64_t *>(scr + L.flags);
+  Seg *segs[2] = {reinterpret_cast<Seg *>(scr + L.segs[0]),
+                  reinterpret_cast<Seg *>(scr + L.segs[1])};
+  Acc *acc[2] = {reinterpret_cast<Acc *>(scr + L.acc[0]),
+                 reinterpret_cast<Acc *>(scr + L.acc[1])};
+  uint32_t *tmap[2] = {reinterpret_cast<uint32_t *>(scr + L.tmap[0]),
+                       reinterpret_cast<uint32_t *>(scr + L.tmap[1])};
+  Seg *fin = reinterpret_cast<Seg *>(scr + L.fin);
+  Seg *cpy = reinterpret_cast<Seg *>(scr + L.cpy);
+  KT *kbuf[2] = {keys, reinterpret_cast<KT *>(scr + L.keys1)};
+  uint32_t *ibuf[2] = {nullptr, nullptr};
+  if (IDX) {
+    ibuf[0] = idx64 ? reinterpret_cast<uint32_t *>(scr + L.idx0)
+                    : static_cast<uint32_t *>(indices);
+    ibuf[1] = reinterpret_cast<uint32_t *>(scr + L.idx1);
+  }
+
+  const uint64_t cap = (uint64_t)cus * 16;
+  hipLaunchKernelGGL(init_kernel, dim3(clamp_grid((L.tmax + 255) / 256, 1024)), dim3(256), 0,
+                     st, hdr, lb, (uint64_t)L.tmax);
+  if (offsets)
+    hipLaunchKernelGGL(validate_kernel, dim3(clamp_grid((B + 256) / 256, 1024)), dim3(256), 0,
+                       st, offsets, B, n, hdr);
+
+  ListArgs la;
+  la.hdr = hdr;
+  la.fin = fin;
+  la.cpy = cpy;
+  la.tile = TU::TILE;
+  la.t_fin = TU::TFIN;
+
+  SeedArgs sa;
+  sa.l = la;
+  sa.l.live_next = segs[0];
+  sa.l.acc_next = acc[0];
+  sa.l.tile_map_next = tmap[0];
+  sa.l.next_level = 0;
+  sa.offsets = offsets;
+  sa.B = B;
+  sa.n = n;
+  sa.w = w;
+  sa.with_idx = IDX ? 1 : 0;
+  sa.no_finish = no_finish;
+  hipLaunchKernelGGL(seed_kernel, dim3(clamp_grid((B + 255) / 256, cap)), dim3(256), 0, st, sa);
+
+  auto lk = level_kernel<KT, IDX, TU::LB, TU::LIPT>;
+  static const int occ_level = occupancy(lk, TU::LB);
+  const uint32_t lgrid = clamp_grid(L.tmax, (uint64_t)cus * occ_level);
+  const uint32_t pgrid = clamp_grid((L.smax + 255) / 256, cap);
+  for (int lvl = 0; lvl < w; ++lvl) {
+    LevelArgs<KT> a;
+    a.keys_in = kbuf[lvl & 1];
+    a.keys_out = kbuf[(lvl + 1) & 1];
+    a.idx_in = ibuf[lvl & 1];
+    a.idx_out = ibuf[(lvl + 1) & 1];
+    a.segs = segs[lvl & 1];
+    a.acc = acc[lvl & 1];
+    a.tile_map = tmap[lvl & 1];
+    a.lookback = lb;
+    a.hdr = hdr;
+    a.w = w;
+    a.mode = mode;
+    a.desc = desc;
+    a.level = lvl;
+    hipLaunchKernelGGL(lk, dim3(lgrid), dim3(TU::LB), 0, st, a);
+
+    PlanArgs pa;
+    pa.l = la;
+    pa.l.live_next = segs[(lvl + 1) & 1];
+    pa.l.acc_next = acc[(lvl + 1) & 1];
+    pa.l.tile_map_next = tmap[(lvl + 1) & 1];
+    pa.l.next_level = lvl + 1;
+    pa.live = segs[lvl & 1];
+    pa.acc = acc[lvl & 1];
+    pa.level = lvl;
+    pa.w = w;
+    pa.with_idx = IDX ? 1 : 0;
+    pa.idx64 = idx64;
+    pa.no_skip = no_skip;
+    pa.no_finish = no_finish;
+    hipLaunchKernelGGL(plan_kernel, dim3(pgrid), dim3(256), 0, st, pa);
+  }
+
+  CopyArgs<KT> ca;
+  ca.keys_buf[0] = kbuf[0];
+  ca.keys_buf[1] = kbuf[1];
+  ca.idx_buf[0] = ibuf[0];
+  ca.idx_buf[1] = ibuf[1];
+  ca.keys_final = keys;
+  ca.idx_final = indices;
+  ca.list = cpy;
+  ca.hdr = hdr;
+  ca.idx64 = idx64;
+  hipLaunchKernelGGL((copy_kernel<KT, IDX>), dim3(clamp_grid(cus * 4, cap)), dim3(256), 0, st,
+                     ca);
+
+  FinishArgs<KT> fa;
+  fa.keys_buf[0] = kbuf[0];
+  fa.keys_buf[1] = kbuf[1];
+  fa.idx_buf[0] = ibuf[0];
+  fa.idx_buf[1] = ibuf[1];
+  fa.keys_final = keys;
+  fa.idx_final = indices;
+  fa.list = fin;
+  fa.hdr = hdr;
+  fa.w = w;
+  fa.mode = mode;
+  fa.desc = desc;
+  fa.idx64 = idx64;
+  fa.no_skip = no_skip;
+  auto fk = finish_kernel<KT, IDX, TU::FB, TU::FIPT>;
+  static const int occ_fin = occupancy(fk, TU::FB);
+  hipLaunchKernelGGL(fk, dim3(clamp_grid(L.fmax, (uint64_t)cus * occ_fin)), dim3(TU::FB), 0, st,
+                     fa);
+
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  return BSORT_OK;
+}
+
+template <typename KT>
+int run(void *keys, uint64_t n, const int64_t *offsets, uint64_t B, bool segmented, int mode,
+        uint32_t flags, void *indices, void *scratch, size_t scratch_bytes, void *stream) {
+  if (flags & ~ALL_FLAGS) return BSORT_EINVAL;
+  if (segmented && B > 0 && !offsets) return BSORT_EINVAL;
+  if (segmented && B == 0 && n != 0) return BSORT_EINVAL;
+  if (n == 0) return BSORT_OK;
+  if (!keys || !scratch) return BSORT_EINVAL;
+  const bool with_idx = indices != nullptr;
+  if (with_idx && n >= (1ull << 32)) return BSORT_ETOOBIG;
+  if (n >= (1ull << 47)) return BSORT_ETOOBIG;
+  Layout L;
+  if (!make_layout((int)sizeof(KT), n, segmented ? B : 1, with_idx, flags, &L))
+    return BSORT_EINVAL;
+  if (scratch_bytes < L.total) return BSORT_ESCRATCH;
+  if (reinterpret_cast<uintptr_t>(scratch) & 255) return BSORT_EINVAL;
+  int cus = 0;
+  const int rc = device_check(&cus);
+  if (rc != BSORT_OK) return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char *scr = static_cast<char *>(scratch);
+  KT *k = static_cast<KT *>(keys);
+  const int64_t *off = segmented ? offsets : nullptr;
+  const uint64_t b = segmented ? B : 1;
+  if (with_idx)
+    return launch_all<KT, true>(k, n, off, b, mode, flags, indices, scr, L, cus, st);
+  return launch_all<KT, false>(k, n, off, b, mode, flags, indices, scr, L, cus, st);
+}
+
+int dispatch(void *keys, int key_type, int key_bytes, uint64_t n, const int64_t *offsets,
+             uint64_t B, bool segmented, uint32_t flags, void *indices, void *scratch,
+             size_t scratch_bytes, void *stream) {
+  if (key_type != BSORT_KEY_U && key_type != BSORT_KEY_I && key_type != BSORT_KEY_F)
+    return BSORT_EINVAL;
+  switch (key_bytes) {
+    case 1:
+      return run<uint8_t>(keys, n, offsets, B, segmented, key_type, flags, indices, scratch,
+                          scratch_bytes, stream);
+    case 2:
+      return run<uint16_t>(keys, n, offsets, B, segmented, key_type, flags, indices, scratch,
+                           scratch_bytes, stream);
+    case 4:
+      return run<uint32_t>(keys, n, offsets, B, segmented, key_type, flags, indices, scratch,
+                           scratch_bytes, stream);
+    case 8:
+      return run<uint64_t>(keys, n, offsets, B, segmented, key_type, flags, indices, scratch,
+                           scratch_bytes, stream);
+    default:
+      return BSORT_EINVAL;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t bsort_scratch_bytes(int key_bytes, uint64_t n, uint64_t num_segments, int with_indices,
+                           uint32_t flags) {
+  if (flags & ~ALL_FLAGS) return 0;
+  Layout L;
+  if (!make_layout(key_bytes, n, num_segments ? num_segments : 1, with_indices != 0, flags, &L))
+    return 0;
+  return L.total;
+}
+
+int bsort_sort(void *keys, int key_type, int key_bytes, uint64_t n, uint32_t flags,
+               void *indices, void *scratch, size_t scratch_bytes, void *stream) {
+  return dispatch(keys, key_type, key_bytes, n, nullptr, 1, false, flags, indices, scratch,
+                  scratch_bytes, stream);
+}
+
+int bsort_segmented(void *keys, int key_type, int key_bytes, const int64_t *offsets,
+                    uint64_t num_segments, uint64_t n, uint32_t flags, void *indices,
+                    void *scratch, size_t scratch_bytes, void *stream) {
+  return dispatch(keys, key_type, key_bytes, n, offsets, num_segments, true, flags, indices,
+                  scratch, scratch_bytes, stream);
+}
+
+#define BSORT_TYPED(name, T, kt, kb)                                                        \
+  int name(T *keys, uint64_t n, uint32_t flags, void *indices, void *scratch,               \
+           size_t scratch_bytes, void *stream) {                                            \
+    return dispatch(keys, kt, kb, n, nullptr, 1, false, flags, indices, scratch,            \
+                    scratch_bytes, stream);                                                 \
+  }
+BSORT_TYPED(bsort_u8, uint8_t, BSORT_KEY_U, 1)
+BSORT_TYPED(bsort_u16, uint16_t, BSORT_KEY_U, 2)
+BSORT_TYPED(bsort_u32, uint32_t, BSORT_KEY_U, 4)
+BSORT_TYPED(bsort_u64, uint64_t, BSORT_KEY_U, 8)
+BSORT_TYPED(bsort_i8, int8_t, BSORT_KEY_I, 1)
+BSORT_TYPED(bsort_i16, int16_t, BSORT_KEY_I, 2)
+BSORT_TYPED(bsort_i32, int32_t, BSORT_KEY_I, 4)
+BSORT_TYPED(bsort_i64, int64_t, BSORT_KEY_I, 8)
+BSORT_TYPED(bsort_f8, uint8_t, BSORT_KEY_F, 1)
+BSORT_TYPED(bsort_f16, uint16_t, BSORT_KEY_F, 2)
+BSORT_TYPED(bsort_f32, float, BSORT_KEY_F, 4)
+BSORT_TYPED(bsort_f64, double, BSORT_KEY_F, 8)
+#undef BSORT_TYPED
+
+int bsort_segmented_f32(float *keys, const int64_t *offsets, uint64_t num_segments, uint64_t n,
+                        uint32_t flags, void *indices, void *scratch, size_t scratch_bytes,
+                        void *stream) {
+  return dispatch(keys, BSORT_KEY_F, 4, n, offsets, num_segments, true, flags, indices,
+                  scratch, scratch_bytes, stream);
+}
+
+int bsort_segmented_i32(int32_t *keys, const int64_t *offsets, uint64_t num_segments,
+                        uint64_t n, uint32_t flags, void *indices, void *scratch,
+                        size_t scratch_bytes, void *stream) {
+  return dispatch(keys, BSORT_KEY_I, 4, n, offsets, num_segments, true, flags, indices,
+                  scratch, scratch_bytes, stream);
+}
+
+int bsort_backward_scatter(const void *grad_sorted, const void *indices, uint64_t rows,
+                           uint64_t cols, int elem_bytes, void *grad_in, uint32_t flags,
+                           void *stream) {
+  if (flags & ~(uint32_t)BSORT_IDX64) return BSORT_EINVAL;
+  if (elem_bytes != 2 && elem_bytes != 4 && elem_bytes != 8) return BSORT_EINVAL;
+  if (rows == 0 || cols == 0) return BSORT_OK;
+  if (!grad_sorted || !indices || !grad_in) return BSORT_EINVAL;
+  int cus = 0;
+  const int rc = device_check(&cus);
+  if (rc != BSORT_OK) return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const bool i64 = (flags & BSORT_IDX64) != 0;
+  const uint64_t bx = (cols + 255) / 256;
+  dim3 grid(clamp_grid(bx, 4096), clamp_grid(rows, 65535));
+#define BS_LAUNCH(ET)                                                                       \
+  do {                                                                                      \
+    if (i64)                                                                                \
+      hipLaunchKernelGGL((backward_scatter_kernel<ET, true>), grid, dim3(256), 0, st,       \
+                         static_cast<const ET *>(grad_sorted), indices, rows, cols,         \
+                         static_cast<ET *>(grad_in));                                       \
+    else                                                                                    \
+      hipLaunchKernelGGL((backward_scatter_kernel<ET, false>), grid, dim3(256), 0, st,      \
+                         static_cast<const ET *>(grad_sorted), indices, rows, cols,         \
+                         static_cast<ET *>(grad_in));                                       \
+  } while (0)
+  if (elem_bytes == 2) BS_LAUNCH(uint16_t);
+  else if (elem_bytes == 4) BS_LAUNCH(uint32_t);
+  else BS_LAUNCH(uint64_t);
+#undef BS_LAUNCH
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  return BSORT_OK;
+}
+
+const char *bsort_strerror(int status) {
+  switch (status) {
+    case BSORT_OK: return "ok";
+    case BSORT_EINVAL: return "invalid argument";
+    case BSORT_ESCRATCH: return "scratch buffer too small";
+    case BSORT_ETOOBIG: return "too many keys for the index type";
+    case BSORT_EHIP: return g_hip_err[0] ? g_hip_err : "HIP runtime error";
+    case BSORT_ENODEV: return "current device is not a gfx950 GPU";
+    default: return "unknown status";
+  }
+}
+
+int bsort_device_status(const void *scratch, void *stream) {
+  if (!scratch) return BSORT_EINVAL;
+  uint32_t v = 0;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const char *p = static_cast<const char *>(scratch) + offsetof(Header, status);
+  hipError_t e = hipMemcpyAsync(&v, p, sizeof v, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "bsort_device_status");
+  return (int)v;
+}
+
+}  // extern "C"
