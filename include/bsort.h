@@ -158,6 +158,26 @@ const char *bsort_strerror(int status);
  * synchronously on `stream`.  Returns the word, or a negative status. */
 int bsort_device_status(const void *scratch, void *stream);
 
+/* ---- instrumentation (benchmarks and tests; not needed to sort) ---- */
+
+/* Work statistics of the last call that used this scratch, read
+ * synchronously on `stream`: per level, the keys in live segments, the live
+ * segments and the tiles; keys handed to the LDS finish and keys of retired
+ * segments copied back.  Any output may be NULL.  Returns the number of
+ * levels filled (<= max_levels), or a negative status. */
+int bsort_level_stats(const void *scratch, void *stream, uint64_t *live_keys,
+                      uint32_t *live_segments, uint32_t *tiles, int max_levels,
+                      uint64_t *finish_keys, uint64_t *copy_keys);
+
+/* While armed, each launch of the global-level kernel (by any call of this
+ * process) is bracketed by a pair of hipEvents recorded on the call's
+ * stream, for the first `capacity` launches.  bsort_timing_read waits for
+ * them, writes each launch's elapsed milliseconds and level index, and
+ * restarts the count.  Host-side event objects only; not thread-safe. */
+int bsort_timing_arm(int capacity);
+int bsort_timing_read(float *ms, int *levels, int capacity);
+void bsort_timing_disarm(void);
+
 #ifdef __cplusplus
 }
 #endif

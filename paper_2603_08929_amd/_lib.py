@@ -32,7 +32,8 @@ _vp, _u64, _u32, _i, _sz = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ct
 TYPED = ["u8", "u16", "u32", "u64", "i8", "i16", "i32", "i64", "f8", "f16", "f32", "f64"]
 SYMBOLS = ["bsort_scratch_bytes", "bsort_sort", "bsort_segmented", "bsort_segmented_f32",
            "bsort_segmented_i32", "bsort_backward_scatter", "bsort_strerror",
-           "bsort_device_status"] + [f"bsort_{t}" for t in TYPED]
+           "bsort_device_status", "bsort_level_stats", "bsort_timing_arm",
+           "bsort_timing_read", "bsort_timing_disarm"] + [f"bsort_{t}" for t in TYPED]
 
 lib.bsort_scratch_bytes.argtypes = [_i, _u64, _u64, _i, _u32]
 lib.bsort_scratch_bytes.restype = _sz
@@ -54,6 +55,14 @@ lib.bsort_strerror.argtypes = [_i]
 lib.bsort_strerror.restype = ctypes.c_char_p
 lib.bsort_device_status.argtypes = [_vp, _vp]
 lib.bsort_device_status.restype = _i
+lib.bsort_level_stats.argtypes = [_vp, _vp, _vp, _vp, _vp, _i, _vp, _vp]
+lib.bsort_level_stats.restype = _i
+lib.bsort_timing_arm.argtypes = [_i]
+lib.bsort_timing_arm.restype = _i
+lib.bsort_timing_read.argtypes = [_vp, _vp, _i]
+lib.bsort_timing_read.restype = _i
+lib.bsort_timing_disarm.argtypes = []
+lib.bsort_timing_disarm.restype = None
 
 
 def strerror(rc: int) -> str:
@@ -74,5 +83,9 @@ bsort_segmented_i32 = lib.bsort_segmented_i32
 bsort_backward_scatter = lib.bsort_backward_scatter
 bsort_strerror = lib.bsort_strerror
 bsort_device_status = lib.bsort_device_status
+bsort_level_stats = lib.bsort_level_stats
+bsort_timing_arm = lib.bsort_timing_arm
+bsort_timing_read = lib.bsort_timing_read
+bsort_timing_disarm = lib.bsort_timing_disarm
 for _t in TYPED:
     globals()[f"bsort_{_t}"] = getattr(lib, f"bsort_{_t}")

@@ -25,6 +25,25 @@ namespace {
 
 thread_local char g_hip_err[256] = "";
 
+// Benchmark instrumentation: hipEvent pairs around level-kernel launches.
+struct Timing {
+  int armed = 0;
+  int cap = 0;
+  int count = 0;
+  hipEvent_t *ev = nullptr;
+  int *lvl = nullptr;
+};
+Timing g_timing;
+
+void timing_free() {
+  if (g_timing.ev) {
+    for (int i = 0; i < 2 * g_timing.cap; ++i) (void)hipEventDestroy(g_timing.ev[i]);
+    delete[] g_timing.ev;
+    delete[] g_timing.lvl;
+  }
+  g_timing = Timing();
+}
+
 int hip_fail(hipError_t e, const char *what) {
   snprintf(g_hip_err, sizeof g_hip_err, "%s: %s", what, hipGetErrorString(e));
   return BSORT_EHIP;
@@ -58,12 +77,28 @@ int device_check(int *cus) {
 
 // Launch shapes per key width: level tile = LB * LIPT keys, finish
 // threshold T = FB * FIPT keys.
+#ifndef BSORT_LB
+#define BSORT_LB 512
+#endif
+#ifndef BSORT_LIPT
+#define BSORT_LIPT 8
+#endif
+#ifndef BSORT_FB
+#define BSORT_FB 512
+#endif
+#ifndef BSORT_FIPT
+#define BSORT_FIPT 16
+#endif
+#ifndef BSORT_FRB
+#define BSORT_FRB 5
+#endif
 template <typename KT>
 struct Tune {
-  static constexpr int LB = 256;
-  static constexpr int LIPT = sizeof(KT) == 8 ? 8 : 16;
-  static constexpr int FB = 256;
-  static constexpr int FIPT = 16;
+  static constexpr int LB = BSORT_LB;
+  static constexpr int LIPT = sizeof(KT) == 8 ? (BSORT_LIPT / 2 > 0 ? BSORT_LIPT / 2 : 1) : BSORT_LIPT;
+  static constexpr int FB = BSORT_FB;
+  static constexpr int FIPT = sizeof(KT) == 8 ? BSORT_FIPT / 2 : BSORT_FIPT;
+  static constexpr int FRB = BSORT_FRB;
   static constexpr uint32_t TILE = LB * LIPT;
   static constexpr uint32_t TFIN = FB * FIPT;
 };
@@ -88,7 +123,7 @@ size_t up256(size_t x) { return (x + 255) & ~(size_t)255; }
 // every parent yields at most two finish entries per level; copy entries
 // hold more than T keys each.
 struct Layout {
-  size_t hdr, flags, segs[2], acc[2], tmap[2], fin, cpy, keys1, idx0, idx1, total;
+  size_t hdr, cnts, segs[2], acc[2], tmap[2], fin, cpy, keys1, idx0, idx1, total;
   uint64_t smax, tmax, fmax, cmax;
 };
 
@@ -106,10 +141,13 @@ bool make_layout(int key_bytes, uint64_t n, uint64_t B, bool with_idx, uint32_t 
   L->cmax = n / (tfin + 1ull) + 1;
   size_t off = 0;
   L->hdr = off; off = up256(off + sizeof(Header));
-  L->flags = off; off = up256(off + L->tmax * 8);
+  // per-tile front counts: [tiles, 64-tile groups] x two level parities,
+  // each indexed up to 3 * tmax: two children per parent tile range, then
+  // the segments counted by the count pass at recount + tile0
+  L->cnts = off; off = up256(off + 4 * (3 * L->tmax) * 4);
   for (int i = 0; i < 2; ++i) { L->segs[i] = off; off = up256(off + L->smax * sizeof(Seg)); }
   for (int i = 0; i < 2; ++i) { L->acc[i] = off; off = up256(off + L->smax * sizeof(Acc)); }
-  for (int i = 0; i < 2; ++i) { L->tmap[i] = off; off = up256(off + L->tmax * 4); }
+  for (int i = 0; i < 2; ++i) { L->tmap[i] = off; off = up256(off + L->tmax * sizeof(Seg)); }
   L->fin = off; off = up256(off + L->fmax * sizeof(Seg));
   L->cpy = off; off = up256(off + L->cmax * sizeof(Seg));
   L->keys1 = off; off = up256(off + n * (size_t)key_bytes);
@@ -148,13 +186,12 @@ int launch_all(KT *keys, uint64_t n, const int64_t *offsets, uint64_t B, int mod
   const int no_finish = (flags & BSORT_NO_FINISH) ? 1 : 0;
 
   Header *hdr = reinterpret_cast<Header *>(scr + L.hdr);
-  uint64_t *lb = reinterpret_cast<uint64_t *>(scr + L.flags);
   Seg *segs[2] = {reinterpret_cast<Seg *>(scr + L.segs[0]),
                   reinterpret_cast<Seg *>(scr + L.segs[1])};
   Acc *acc[2] = {reinterpret_cast<Acc *>(scr + L.acc[0]),
                  reinterpret_cast<Acc *>(scr + L.acc[1])};
-  uint32_t *tmap[2] = {reinterpret_cast<uint32_t *>(scr + L.tmap[0]),
-                       reinterpret_cast<uint32_t *>(scr + L.tmap[1])};
+  Seg *tmap[2] = {reinterpret_cast<Seg *>(scr + L.tmap[0]),
+                  reinterpret_cast<Seg *>(scr + L.tmap[1])};
   Seg *fin = reinterpret_cast<Seg *>(scr + L.fin);
   Seg *cpy = reinterpret_cast<Seg *>(scr + L.cpy);
   KT *kbuf[2] = {keys, reinterpret_cast<KT *>(scr + L.keys1)};
@@ -166,8 +203,12 @@ int launch_all(KT *keys, uint64_t n, const int64_t *offsets, uint64_t B, int mod
   }
 
   const uint64_t cap = (uint64_t)cus * 16;
-  hipLaunchKernelGGL(init_kernel, dim3(clamp_grid((L.tmax + 255) / 256, 1024)), dim3(256), 0,
-                     st, hdr, lb, (uint64_t)L.tmax);
+  uint32_t *cnt_base = reinterpret_cast<uint32_t *>(scr + L.cnts);
+  const uint64_t cn = 3 * L.tmax;  // entries per count array
+  uint32_t *tcnt[2] = {cnt_base, cnt_base + 2 * cn};
+  uint32_t *scnt[2] = {cnt_base + cn, cnt_base + 3 * cn};
+  hipLaunchKernelGGL(init_kernel, dim3(clamp_grid((4 * cn + 255) / 256, 2048)), dim3(256), 0,
+                     st, hdr, cnt_base, 4 * cn);
   if (offsets)
     hipLaunchKernelGGL(validate_kernel, dim3(clamp_grid((B + 256) / 256, 1024)), dim3(256), 0,
                        st, offsets, B, n, hdr);
@@ -178,12 +219,13 @@ int launch_all(KT *keys, uint64_t n, const int64_t *offsets, uint64_t B, int mod
   la.cpy = cpy;
   la.tile = TU::TILE;
   la.t_fin = TU::TFIN;
+  la.recount = (uint32_t)(2 * L.tmax);
 
   SeedArgs sa;
   sa.l = la;
   sa.l.live_next = segs[0];
   sa.l.acc_next = acc[0];
-  sa.l.tile_map_next = tmap[0];
+  sa.l.tiles_next = tmap[0];
   sa.l.next_level = 0;
   sa.offsets = offsets;
   sa.B = B;
@@ -197,31 +239,57 @@ int launch_all(KT *keys, uint64_t n, const int64_t *offsets, uint64_t B, int mod
   static const int occ_level = occupancy(lk, TU::LB);
   const uint32_t lgrid = clamp_grid(L.tmax, (uint64_t)cus * occ_level);
   const uint32_t pgrid = clamp_grid((L.smax + 255) / 256, cap);
+  auto ck = count_kernel<KT, TU::LB, TU::LIPT>;
+  static const int occ_count = occupancy(ck, TU::LB);
+  const uint32_t cgrid = clamp_grid(L.tmax, (uint64_t)cus * occ_count);
   for (int lvl = 0; lvl < w; ++lvl) {
+    CountArgs<KT> ca;
+    ca.keys = kbuf[lvl & 1];
+    ca.tiles = tmap[lvl & 1];
+    ca.hdr = hdr;
+    ca.tcnt = tcnt[lvl & 1];
+    ca.scnt = scnt[lvl & 1];
+    ca.w = w;
+    ca.mode = mode;
+    ca.desc = desc;
+    ca.level = lvl;
+    hipLaunchKernelGGL(ck, dim3(cgrid), dim3(TU::LB), 0, st, ca);
+
     LevelArgs<KT> a;
     a.keys_in = kbuf[lvl & 1];
     a.keys_out = kbuf[(lvl + 1) & 1];
     a.idx_in = ibuf[lvl & 1];
     a.idx_out = ibuf[(lvl + 1) & 1];
-    a.segs = segs[lvl & 1];
+    a.tiles = tmap[lvl & 1];
     a.acc = acc[lvl & 1];
-    a.tile_map = tmap[lvl & 1];
-    a.lookback = lb;
     a.hdr = hdr;
+    a.tcnt_in = tcnt[lvl & 1];
+    a.scnt_in = scnt[lvl & 1];
+    a.tcnt_out = tcnt[(lvl + 1) & 1];
+    a.scnt_out = scnt[(lvl + 1) & 1];
     a.w = w;
     a.mode = mode;
     a.desc = desc;
     a.level = lvl;
+    const bool timed = g_timing.armed && g_timing.count < g_timing.cap;
+    if (timed) (void)hipEventRecord(g_timing.ev[2 * g_timing.count], st);
     hipLaunchKernelGGL(lk, dim3(lgrid), dim3(TU::LB), 0, st, a);
+    if (timed) {
+      (void)hipEventRecord(g_timing.ev[2 * g_timing.count + 1], st);
+      g_timing.lvl[g_timing.count++] = lvl;
+    }
 
     PlanArgs pa;
     pa.l = la;
     pa.l.live_next = segs[(lvl + 1) & 1];
     pa.l.acc_next = acc[(lvl + 1) & 1];
-    pa.l.tile_map_next = tmap[(lvl + 1) & 1];
+    pa.l.tiles_next = tmap[(lvl + 1) & 1];
     pa.l.next_level = lvl + 1;
     pa.live = segs[lvl & 1];
     pa.acc = acc[lvl & 1];
+    pa.zero_a = tcnt[lvl & 1];  // read by this level, filled by the next one
+    pa.zero_b = scnt[lvl & 1];
+    pa.zero_n = cn;
     pa.level = lvl;
     pa.w = w;
     pa.with_idx = IDX ? 1 : 0;
@@ -258,7 +326,7 @@ int launch_all(KT *keys, uint64_t n, const int64_t *offsets, uint64_t B, int mod
   fa.desc = desc;
   fa.idx64 = idx64;
   fa.no_skip = no_skip;
-  auto fk = finish_kernel<KT, IDX, TU::FB, TU::FIPT>;
+  auto fk = finish_kernel<KT, IDX, TU::FB, TU::FIPT, TU::FRB>;
   static const int occ_fin = occupancy(fk, TU::FB);
   hipLaunchKernelGGL(fk, dim3(clamp_grid(L.fmax, (uint64_t)cus * occ_fin)), dim3(TU::FB), 0, st,
                      fa);
@@ -425,6 +493,58 @@ const char *bsort_strerror(int status) {
     default: return "unknown status";
   }
 }
+
+int bsort_level_stats(const void *scratch, void *stream, uint64_t *live_keys,
+                      uint32_t *live_segments, uint32_t *tiles, int max_levels,
+                      uint64_t *finish_keys, uint64_t *copy_keys) {
+  if (!scratch || max_levels < 0) return BSORT_EINVAL;
+  Header h;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = hipMemcpyAsync(&h, scratch, sizeof h, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "bsort_level_stats");
+  const int m = max_levels < MAX_LEVELS ? max_levels : MAX_LEVELS;
+  for (int i = 0; i < m; ++i) {
+    if (live_keys) live_keys[i] = h.live_keys[i];
+    if (live_segments) live_segments[i] = (uint32_t)(h.packed[i] >> 32);
+    if (tiles) tiles[i] = (uint32_t)h.packed[i];
+  }
+  if (finish_keys) *finish_keys = h.finish_keys;
+  if (copy_keys) *copy_keys = h.copy_keys;
+  return m;
+}
+
+int bsort_timing_arm(int capacity) {
+  timing_free();
+  if (capacity <= 0) return BSORT_OK;
+  g_timing.ev = new hipEvent_t[2 * capacity];
+  g_timing.lvl = new int[capacity];
+  g_timing.cap = capacity;
+  for (int i = 0; i < 2 * capacity; ++i) {
+    const hipError_t e = hipEventCreate(&g_timing.ev[i]);
+    if (e != hipSuccess) {
+      g_timing.cap = i / 2;
+      timing_free();
+      return hip_fail(e, "hipEventCreate");
+    }
+  }
+  g_timing.armed = 1;
+  return BSORT_OK;
+}
+
+int bsort_timing_read(float *ms, int *levels, int capacity) {
+  const int n = g_timing.count < capacity ? g_timing.count : capacity;
+  for (int i = 0; i < n; ++i) {
+    hipError_t e = hipEventSynchronize(g_timing.ev[2 * i + 1]);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms[i], g_timing.ev[2 * i], g_timing.ev[2 * i + 1]);
+    if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+    if (levels) levels[i] = g_timing.lvl[i];
+  }
+  g_timing.count = 0;
+  return n;
+}
+
+void bsort_timing_disarm(void) { timing_free(); }
 
 int bsort_device_status(const void *scratch, void *stream) {
   if (!scratch) return BSORT_EINVAL;

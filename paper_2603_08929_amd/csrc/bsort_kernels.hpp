@@ -25,6 +25,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace bsort {
 
 enum : int { MODE_U = 0, MODE_I = 1, MODE_F = 2 };
@@ -36,6 +38,7 @@ constexpr uint32_t META_REV = 1u << 7; // stored right to left
 constexpr uint32_t META_SIGN = 1u << 8;  // float keys of this segment are negative
 constexpr uint32_t META_BUF = 1u << 9;   // data lives in the scratch buffers
 constexpr uint32_t META_IOTA = 1u << 10; // index payload not materialized yet
+constexpr uint32_t META_PRE = 1u << 11;  // the previous level counted `bit` per tile
 
 constexpr uint32_t STATUS_WAIT_TIMEOUT = 1u;
 constexpr uint32_t STATUS_BAD_OFFSETS = 2u;
@@ -49,25 +52,39 @@ struct Seg {
   uint64_t len;
   uint32_t meta;
   uint32_t tile0;
-  uint64_t pad_;
+  uint32_t cbase;  // front counts of this level's tiles: at cbase + j
+  uint32_t slot;   // per-tile copies: the segment's slot in its level's list
 };
 static_assert(sizeof(Seg) == 32, "Seg layout");
 
 // Per live segment: AND/OR of the keys that went to the front (lo) and back
 // (hi) child, and the split (number of front keys), written by the level.
-struct Acc {
+// The AND/OR words are replicated, one 128-byte line per replica, and a tile
+// updates replica (tile id mod ACC_REPL): with a single copy every tile of a
+// big segment would contend for the same line.
+constexpr int ACC_REPL = 16;
+struct AccRep {
   uint64_t and_lo, or_lo, and_hi, or_hi;
-  uint64_t split;
+  uint64_t pad_[12];
 };
+struct Acc {
+  AccRep r[ACC_REPL];
+  uint64_t split;
+  uint64_t pad_[15];
+};
+static_assert(sizeof(AccRep) == 128 && sizeof(Acc) % 128 == 0, "Acc layout");
 
 // Work-list counters, zeroed at the start of every call.
 struct Header {
-  uint64_t packed[MAX_LEVELS]; // per level: (live segments << 32) | tiles
-  uint32_t grab[MAX_LEVELS];   // per level: next tile id handed out
+  uint32_t status;             // kept first: read by bsort_device_status
   uint32_t n_finish;
   uint32_t n_copy;
-  uint32_t status;
   uint32_t pad_;
+  uint64_t finish_keys;        // keys handed to the LDS finish (all levels)
+  uint64_t copy_keys;          // keys of retired segments copied back
+  uint64_t packed[MAX_LEVELS]; // per level: (live segments << 32) | tiles
+  uint64_t live_keys[MAX_LEVELS]; // per level: keys in live segments
+  uint32_t grab[MAX_LEVELS];   // per level: next tile id handed out
 };
 
 // ---------------------------------------------------------------- helpers
@@ -94,10 +111,108 @@ __device__ __forceinline__ void atomic_or_u32(uint32_t *p, uint32_t v) {
   __hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Values that are the same in every lane (read back from LDS, say) made
+// provably uniform, so that addresses and buffer descriptors derived from
+// them live in scalar registers.
+__device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint64_t uni(uint64_t v) {
+  return (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)v) |
+         ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(v >> 32)) << 32);
+}
+
 // Number of set bits of m in lanes below this one.
 __device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
                                    __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// Raw buffer access: a per-tile descriptor (base in SGPRs, byte range) and
+// 32-bit lane offsets.  Loads past the range return 0 and stores past it
+// are dropped by the hardware.
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+// an element offset past any descriptor's range (x 8 bytes still < 2^31)
+constexpr uint32_t OOR_ELEMS = 0x0FFFFFFFu;
+__device__ __forceinline__ rsrc_t make_rsrc(const void *p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes,
+                                           0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ T buf_load(rsrc_t r, uint32_t off);
+template <>
+__device__ __forceinline__ uint8_t buf_load<uint8_t>(rsrc_t r, uint32_t off) {
+  return __builtin_amdgcn_raw_buffer_load_b8(r, (int)off, 0, 0);
+}
+template <>
+__device__ __forceinline__ uint16_t buf_load<uint16_t>(rsrc_t r, uint32_t off) {
+  return __builtin_amdgcn_raw_buffer_load_b16(r, (int)off, 0, 0);
+}
+template <>
+__device__ __forceinline__ uint32_t buf_load<uint32_t>(rsrc_t r, uint32_t off) {
+  return __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0);
+}
+template <>
+__device__ __forceinline__ uint64_t buf_load<uint64_t>(rsrc_t r, uint32_t off) {
+  const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0);
+  return (uint64_t)v[0] | ((uint64_t)v[1] << 32);
+}
+__device__ __forceinline__ void buf_store(rsrc_t r, uint32_t off, uint8_t v) {
+  __builtin_amdgcn_raw_buffer_store_b8(v, r, (int)off, 0, 0);
+}
+__device__ __forceinline__ void buf_store(rsrc_t r, uint32_t off, uint16_t v) {
+  __builtin_amdgcn_raw_buffer_store_b16(v, r, (int)off, 0, 0);
+}
+__device__ __forceinline__ void buf_store(rsrc_t r, uint32_t off, uint32_t v) {
+  __builtin_amdgcn_raw_buffer_store_b32(v, r, (int)off, 0, 0);
+}
+__device__ __forceinline__ void buf_store(rsrc_t r, uint32_t off, uint64_t v) {
+  typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+  u32x2 w;
+  w[0] = (uint32_t)v;
+  w[1] = (uint32_t)(v >> 32);
+  __builtin_amdgcn_raw_buffer_store_b64(w, r, (int)off, 0, 0);
+}
+
+// Wave-wide reductions and scans with DPP row shifts and row broadcasts
+// (rows of 16 lanes, then rows 0-1 into 1 and 3, then 0-2 into 2-3), so the
+// lane exchange stays in the VALU.  Lane 63 ends with the full result.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t dpp_src(uint32_t identity, uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)identity, (int)v, CTRL, ROWS, 0xf, false);
+}
+__device__ __forceinline__ uint32_t wave_incl_scan_dpp(uint32_t v) {
+  v += dpp_src<0x111, 0xf>(0u, v);  // row_shr:1
+  v += dpp_src<0x112, 0xf>(0u, v);  // row_shr:2
+  v += dpp_src<0x114, 0xf>(0u, v);  // row_shr:4
+  v += dpp_src<0x118, 0xf>(0u, v);  // row_shr:8
+  v += dpp_src<0x142, 0xa>(0u, v);  // row_bcast:15
+  v += dpp_src<0x143, 0xc>(0u, v);  // row_bcast:31
+  return v;
+}
+__device__ __forceinline__ uint32_t wave_and_dpp32(uint32_t v) {
+  v &= dpp_src<0x111, 0xf>(~0u, v);
+  v &= dpp_src<0x112, 0xf>(~0u, v);
+  v &= dpp_src<0x114, 0xf>(~0u, v);
+  v &= dpp_src<0x118, 0xf>(~0u, v);
+  v &= dpp_src<0x142, 0xa>(~0u, v);
+  v &= dpp_src<0x143, 0xc>(~0u, v);
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+__device__ __forceinline__ uint32_t wave_or_dpp32(uint32_t v) {
+  v |= dpp_src<0x111, 0xf>(0u, v);
+  v |= dpp_src<0x112, 0xf>(0u, v);
+  v |= dpp_src<0x114, 0xf>(0u, v);
+  v |= dpp_src<0x118, 0xf>(0u, v);
+  v |= dpp_src<0x142, 0xa>(0u, v);
+  v |= dpp_src<0x143, 0xc>(0u, v);
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+__device__ __forceinline__ uint64_t wave_and_dpp(uint64_t v) {
+  const uint32_t lo = wave_and_dpp32((uint32_t)v);
+  const uint32_t hi = ((v >> 32) == 0xffffffffull) && false ? 0xffffffffu : wave_and_dpp32((uint32_t)(v >> 32));
+  return (uint64_t)lo | ((uint64_t)hi << 32);
+}
+__device__ __forceinline__ uint64_t wave_or_dpp(uint64_t v) {
+  return (uint64_t)wave_or_dpp32((uint32_t)v) | ((uint64_t)wave_or_dpp32((uint32_t)(v >> 32)) << 32);
 }
 
 __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
@@ -145,72 +260,14 @@ __device__ __forceinline__ int flip_of(int bit, int w, int mode, int desc, int n
   return desc ^ (top ? (mode != MODE_U) : (mode == MODE_F && negative));
 }
 
-// Look-back status words: epoch (level + 1) | status | 48-bit value.
-constexpr uint64_t LB_AGG = 1, LB_INCL = 2;
-__device__ __forceinline__ uint64_t lb_pack(uint32_t epoch, uint64_t st, uint64_t v) {
-  return ((uint64_t)epoch << 50) | (st << 48) | (v & ((1ull << 48) - 1));
-}
-__device__ __forceinline__ uint64_t lb_status(uint64_t w, uint32_t epoch) {
-  return ((w >> 50) == epoch) ? ((w >> 48) & 3) : 0;
-}
-
-// Decoupled look-back within one segment (run by one whole wave): publishes
-// this tile's front count, then sums the counts of the segment's earlier
-// tiles until one with a published inclusive prefix.  Returns the number of
-// front keys in the segment's tiles before tile t.  Tiles are handed out in
-// increasing order, so every tile waited on is held by a running
-// workgroup; the wait is bounded all the same, and a timeout is recorded in
-// the status word instead of hanging.
-__device__ uint64_t look_back(uint64_t *flags, uint32_t t, uint32_t tile0, uint32_t count,
-                              uint32_t epoch, uint32_t *status) {
-  const int lane = threadIdx.x & 63;
-  if (lane == 0) st_relaxed(&flags[t], lb_pack(epoch, t == tile0 ? LB_INCL : LB_AGG, count));
-  if (t == tile0) return 0;
-  uint64_t acc = 0;
-  int64_t look = (int64_t)t - 1;
-  for (;;) {
-    const int64_t pred = look - lane;
-    const bool in = pred >= (int64_t)tile0;
-    uint64_t word = 0, st = 0;
-    uint32_t spins = 0;
-    for (;;) {
-      if (in) {
-        word = ld_relaxed(&flags[pred]);
-        st = lb_status(word, epoch);
-      }
-      if (__all(!in || st != 0)) break;
-      if (++spins > (1u << 20) ||
-          (spins > 64 && (__hip_atomic_load(status, __ATOMIC_RELAXED,
-                                            __HIP_MEMORY_SCOPE_AGENT) & STATUS_WAIT_TIMEOUT))) {
-        if (lane == 0) atomic_or_u32(status, STATUS_WAIT_TIMEOUT);
-        break;
-      }
-      __builtin_amdgcn_s_sleep(1);
-    }
-    const uint64_t incl = __ballot(in && st == LB_INCL);
-    uint64_t val = (in && st != 0) ? (word & ((1ull << 48) - 1)) : 0;
-    if (incl) {
-      const int stop = __ffsll((unsigned long long)incl) - 1;
-      if (lane > stop) val = 0;
-      acc += wave_sum_u64(val);
-      break;
-    }
-    acc += wave_sum_u64(val);
-    look -= 64;
-    if (look < (int64_t)tile0) break;  // only reachable after a timeout
-  }
-  if (lane == 0) st_relaxed(&flags[t], lb_pack(epoch, LB_INCL, acc + count));
-  return acc;
-}
-
 // ------------------------------------------------------------------- init
 
-__global__ void init_kernel(Header *hdr, uint64_t *flags, uint64_t nflags) {
+__global__ void init_kernel(Header *hdr, uint32_t *cnts, uint64_t ncnts) {
   const uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   uint32_t *h = reinterpret_cast<uint32_t *>(hdr);
   for (uint64_t i = i0; i < sizeof(Header) / 4; i += stride) h[i] = 0;
-  for (uint64_t i = i0; i < nflags; i += stride) flags[i] = 0;
+  for (uint64_t i = i0; i < ncnts; i += stride) cnts[i] = 0;
 }
 
 // offsets[0] = 0, non-decreasing, offsets[B] = n; otherwise flag it.
@@ -234,20 +291,23 @@ struct ListArgs {
   Header *hdr;
   Seg *live_next;       // level (lvl+1) live list
   Acc *acc_next;
-  uint32_t *tile_map_next;
+  Seg *tiles_next;      // level (lvl+1): one descriptor copy per tile
   Seg *fin;
   Seg *cpy;
   int next_level;
   uint32_t tile;        // keys per level tile
   uint32_t t_fin;       // finish threshold (keys)
+  uint32_t recount;     // count index base of segments counted by the count pass
 };
 
 struct Child {
   uint64_t start, len;
   uint32_t meta;
   uint32_t tiles;
+  uint32_t cbase;     // count base, or CBASE_OWN: recounted, at recount + tile0
   int kind;
 };
+constexpr uint32_t CBASE_OWN = 0xFFFFFFFFu;
 
 // Allocates slots for the children of one wave (two per lane) with one
 // atomic per list, writes the descriptors and the tile -> segment map.
@@ -255,13 +315,22 @@ __device__ void emit_children(const ListArgs &a, Child (&ch)[2]) {
   const int lane = threadIdx.x & 63;
   // live: slots and tiles packed in one 64-bit counter so that slot order
   // and tile order agree
-  uint64_t mine = 0;
+  uint64_t mine = 0, klive = 0, kfin = 0, kcpy = 0;
   uint32_t nfin = 0, ncpy = 0;
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
-    if (ch[c].kind == KIND_LIVE) mine += (1ull << 32) | ch[c].tiles;
-    nfin += ch[c].kind == KIND_FINISH;
-    ncpy += ch[c].kind == KIND_COPY;
+    if (ch[c].kind == KIND_LIVE) { mine += (1ull << 32) | ch[c].tiles; klive += ch[c].len; }
+    if (ch[c].kind == KIND_FINISH) { nfin++; kfin += ch[c].len; }
+    if (ch[c].kind == KIND_COPY) { ncpy++; kcpy += ch[c].len; }
+  }
+  // statistics (keys per list), one atomic per wave and list
+  klive = wave_sum_u64(klive);
+  kfin = wave_sum_u64(kfin);
+  kcpy = wave_sum_u64(kcpy);
+  if (lane == 0) {
+    if (klive) atomic_add_u64(&a.hdr->live_keys[a.next_level], klive);
+    if (kfin) atomic_add_u64(&a.hdr->finish_keys, kfin);
+    if (kcpy) atomic_add_u64(&a.hdr->copy_keys, kcpy);
   }
   const uint64_t inc_live = wave_incl_scan_u64(mine);
   const uint32_t inc_fin = wave_incl_scan_u32(nfin);
@@ -290,15 +359,23 @@ __device__ void emit_children(const ListArgs &a, Child (&ch)[2]) {
     s.len = ch[c].len;
     s.meta = ch[c].meta;
     s.tile0 = 0;
-    s.pad_ = 0;
+    s.cbase = 0;
+    s.slot = 0;
     if (ch[c].kind == KIND_LIVE) {
       slot[c] = (uint32_t)(pos >> 32);
       tile0[c] = (uint32_t)pos;
       s.tile0 = tile0[c];
+      s.cbase = ch[c].cbase == CBASE_OWN ? a.recount + tile0[c] : ch[c].cbase;
       a.live_next[slot[c]] = s;
-      Acc z;
-      z.and_lo = ~0ull; z.or_lo = 0; z.and_hi = ~0ull; z.or_hi = 0; z.split = 0;
-      a.acc_next[slot[c]] = z;
+      Acc *z = &a.acc_next[slot[c]];
+#pragma unroll
+      for (int k = 0; k < ACC_REPL; ++k) {
+        z->r[k].and_lo = ~0ull;
+        z->r[k].or_lo = 0;
+        z->r[k].and_hi = ~0ull;
+        z->r[k].or_hi = 0;
+      }
+      z->split = 0;
       pos += (1ull << 32) | ch[c].tiles;
     } else if (ch[c].kind == KIND_FINISH) {
       a.fin[fpos++] = s;
@@ -306,16 +383,21 @@ __device__ void emit_children(const ListArgs &a, Child (&ch)[2]) {
       a.cpy[cpos++] = s;
     }
   }
-  // tile -> segment map, written cooperatively by the wave
+  // per-tile descriptor copies, written cooperatively by the wave
   if (__ballot(ch[0].kind == KIND_LIVE || ch[1].kind == KIND_LIVE) == 0) return;
   for (int src = 0; src < 64; ++src) {
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
       const uint32_t nt = __shfl(ch[c].kind == KIND_LIVE ? ch[c].tiles : 0u, src);
       if (nt == 0) continue;
-      const uint32_t t0 = __shfl(tile0[c], src);
-      const uint32_t sl = __shfl(slot[c], src);
-      for (uint32_t k = lane; k < nt; k += 64) a.tile_map_next[t0 + k] = sl;
+      Seg d;
+      d.start = __shfl(ch[c].start, src);
+      d.len = __shfl(ch[c].len, src);
+      d.meta = __shfl(ch[c].meta, src);
+      d.tile0 = __shfl(tile0[c], src);
+      d.cbase = __shfl(ch[c].cbase == CBASE_OWN ? a.recount + tile0[c] : ch[c].cbase, src);
+      d.slot = __shfl(slot[c], src);
+      for (uint32_t k = lane; k < nt; k += 64) a.tiles_next[d.tile0 + k] = d;
     }
   }
 }
@@ -341,6 +423,7 @@ __global__ void seed_kernel(SeedArgs a) {
     Child ch[2];
     ch[0].kind = ch[1].kind = KIND_NONE;
     ch[0].tiles = ch[1].tiles = 0;
+    ch[0].cbase = ch[1].cbase = 0;
     if (s < a.B) {
       uint64_t st = 0, en = a.n;
       if (a.offsets) {
@@ -362,6 +445,7 @@ __global__ void seed_kernel(SeedArgs a) {
         } else {
           ch[0].kind = KIND_LIVE;
           ch[0].tiles = (uint32_t)((len + a.l.tile - 1) / a.l.tile);
+          ch[0].cbase = CBASE_OWN;  // counted by the count pass
         }
       }
     }
@@ -375,6 +459,9 @@ struct PlanArgs {
   ListArgs l;
   const Seg *live;
   const Acc *acc;
+  uint32_t *zero_a;  // count arrays the next level accumulates into
+  uint32_t *zero_b;
+  uint64_t zero_n;
   int level;
   int w;
   int with_idx;
@@ -387,21 +474,35 @@ __global__ void plan_kernel(PlanArgs a) {
   const uint32_t S = (uint32_t)(a.l.hdr->packed[a.level] >> 32);
   const uint32_t buf_out = (uint32_t)((a.level + 1) & 1) ? META_BUF : 0u;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.zero_n; i += stride) {
+    a.zero_a[i] = 0;
+    a.zero_b[i] = 0;
+  }
   for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x; base < S; base += stride) {
     const uint64_t q = base + threadIdx.x;
     Child ch[2];
     ch[0].kind = ch[1].kind = KIND_NONE;
     ch[0].tiles = ch[1].tiles = 0;
+    ch[0].cbase = ch[1].cbase = 0;
     if (q < S) {
       const Seg p = a.live[q];
-      const Acc ac = a.acc[q];
+      const Acc *acp = &a.acc[q];
+      uint64_t and_lo = ~0ull, or_lo = 0, and_hi = ~0ull, or_hi = 0;
+#pragma unroll
+      for (int k = 0; k < ACC_REPL; ++k) {
+        and_lo &= acp->r[k].and_lo;
+        or_lo |= acp->r[k].or_lo;
+        and_hi &= acp->r[k].and_hi;
+        or_hi |= acp->r[k].or_hi;
+      }
       const int bit = (int)(p.meta & BIT_MASK);
-      const uint64_t F = ac.split;
+      const uint64_t F = acp->split;
+      const uint32_t nt_p = (uint32_t)((p.len + a.l.tile - 1) / a.l.tile);
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
         const uint64_t len = c ? p.len - F : F;
-        const uint64_t andv = c ? ac.and_hi : ac.and_lo;
-        const uint64_t orv = c ? ac.or_hi : ac.or_lo;
+        const uint64_t andv = c ? and_hi : and_lo;
+        const uint64_t orv = c ? or_hi : or_lo;
         const uint32_t rev = c ? META_REV : 0u;
         ch[c].start = c ? p.start + F : p.start;
         ch[c].len = len;
@@ -428,9 +529,13 @@ __global__ void plan_kernel(PlanArgs a) {
           ch[c].meta = meta | (uint32_t)nb;
           ch[c].kind = KIND_FINISH;
         } else {
-          ch[c].meta = meta | (uint32_t)nb;
+          // the level counted this child's front keys on bit - 1 per tile;
+          // a child that skipped to a lower bit is counted by the count pass
+          const bool pre = nb == bit - 1;
+          ch[c].meta = meta | (pre ? META_PRE : 0u) | (uint32_t)nb;
           ch[c].kind = KIND_LIVE;
           ch[c].tiles = (uint32_t)((len + a.l.tile - 1) / a.l.tile);
+          ch[c].cbase = pre ? 2 * p.tile0 + (uint32_t)c * nt_p : CBASE_OWN;
         }
       }
     }
@@ -446,172 +551,381 @@ struct LevelArgs {
   KT *keys_out;
   const uint32_t *idx_in;
   uint32_t *idx_out;
-  const Seg *segs;
+  const Seg *tiles;   // per-tile descriptor copies (slot in .slot)
   Acc *acc;
-  const uint32_t *tile_map;
-  uint64_t *lookback;
   Header *hdr;
+  const uint32_t *tcnt_in;  // this level: front keys per tile
+  const uint32_t *scnt_in;  //   ... and per group of 64 tiles
+  uint32_t *tcnt_out;       // next level: front keys on bit - 1 per child tile
+  uint32_t *scnt_out;
   int w, mode, desc, level;
 };
 
+// Uniform description of one tile of a level (every lane holds the same).
+struct TileInfo {
+  uint64_t start, len, lo;
+  uint32_t t, slot, meta, tile0, cbase, j, cnt;
+  bool valid;
+};
+
+template <int TILE>
+__device__ __forceinline__ TileInfo tile_info(const Seg &sg, uint32_t t, uint32_t ntiles) {
+  TileInfo ti;
+  ti.t = uni(t);
+  ti.valid = ti.t < ntiles;
+  ti.start = uni(sg.start);
+  ti.len = uni(sg.len);
+  ti.meta = uni(sg.meta);
+  ti.tile0 = uni(sg.tile0);
+  ti.cbase = uni(sg.cbase);
+  ti.slot = uni(sg.slot);
+  ti.j = ti.t - ti.tile0;
+  ti.lo = (uint64_t)ti.j * TILE;
+  ti.cnt = ti.valid ? (uint32_t)((ti.len - ti.lo) < (uint64_t)TILE ? (ti.len - ti.lo) : (uint64_t)TILE)
+                    : 0u;
+  return ti;
+}
+
+// A tile's data in registers, loaded one tile ahead of its use.
+template <typename KT, int IPT>
+struct TileRegs {
+  KT key[IPT];
+  uint32_t ix[IPT];
+  uint32_t pv;      // wave 0: front keys of earlier tiles (precomputed counts)
+  uint64_t acw[4];  // thread 0: the segment's child AND/OR words as read
+};
+
+template <typename KT, bool IDX, int BLOCK, int IPT>
+__device__ __forceinline__ void issue_loads(const LevelArgs<KT> &a, const TileInfo &ti,
+                                            TileRegs<KT, IPT> &r) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const bool rev = (ti.meta & META_REV) != 0;
+  const bool iota = (ti.meta & META_IOTA) != 0;
+  r.pv = 0;
+  if (wave == 0) {
+    const uint32_t js = ti.j >> 6;
+    for (uint32_t s = lane; s < js; s += 64) r.pv += a.scnt_in[ti.cbase + s];
+    const uint32_t jt = (js << 6) + lane;
+    if (jt < ti.j) r.pv += a.tcnt_in[ti.cbase + jt];
+  }
+  // storage of the tile: [sbase, sbase + cnt); logical q is at sbase + q
+  // (forward) or sbase + cnt - 1 - q (reversed)
+  const uint64_t end = ti.start + ti.len;
+  const uint64_t sbase = rev ? (end - ti.lo - ti.cnt) : (ti.start + ti.lo);
+  const rsrc_t kr = make_rsrc(a.keys_in + sbase, ti.cnt * (uint32_t)sizeof(KT));
+  const rsrc_t ir = make_rsrc(IDX ? a.idx_in + sbase : nullptr, IDX && !iota ? ti.cnt * 4u : 0u);
+#pragma unroll
+  for (int i = 0; i < IPT; ++i) {
+    const uint32_t q = (uint32_t)(i * BLOCK + tid);
+    const uint32_t o = rev ? (ti.cnt - 1 - q) : q;  // past cnt: out of range, reads 0
+    r.key[i] = buf_load<KT>(kr, o * (uint32_t)sizeof(KT));
+    if (IDX) r.ix[i] = iota ? (uint32_t)(ti.lo + q) : buf_load<uint32_t>(ir, o * 4u);
+  }
+  if (tid == 0) {
+    const AccRep *ac = &a.acc[ti.slot].r[ti.t % ACC_REPL];
+    r.acw[0] = ac->and_lo;
+    r.acw[1] = ac->or_lo;
+    r.acw[2] = ac->and_hi;
+    r.acw[3] = ac->or_hi;
+  }
+}
+
+template <int NCNT>
+struct LevelShared {
+  uint32_t cnt[NCNT];  // (item, wave) front counts, position order
+  uint32_t nxt[4];     // next-level front counts of the tile, by child tile
+  uint64_t red[4];     // child AND/OR of the tile
+  Seg seg[2];          // descriptor of the next tile (double buffer)
+  uint32_t tile[2];
+  uint64_t prefix;
+};
+
+// Thread 0's claim pipeline: the tile id and descriptor it will publish.
+struct Claim {
+  uint32_t t;
+  Seg d;
+};
+
+// One tile: rank, publish the next tile and start its loads, then write.
+template <typename KT, bool IDX, int BLOCK, int IPT>
+__device__ __forceinline__ void level_tile(const LevelArgs<KT> &a, const TileInfo &ti,
+                                           TileRegs<KT, IPT> &r, TileInfo &tn,
+                                           TileRegs<KT, IPT> &rn,
+                                           LevelShared<IPT * (BLOCK / 64)> &sh, int &cur,
+                                           Claim &cl, uint32_t ntiles) {
+  constexpr int WAVES = BLOCK / 64;
+  constexpr int TILE = BLOCK * IPT;
+  constexpr int NCNT = IPT * WAVES;
+  using RT = typename std::conditional<sizeof(KT) == 8, uint64_t, uint32_t>::type;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int bit = (int)(ti.meta & BIT_MASK);
+  const uint32_t f = (uint32_t)flip_of(bit, a.w, a.mode, a.desc, (ti.meta & META_SIGN) ? 1 : 0);
+  const uint32_t cnt = ti.cnt;
+  const uint64_t end = ti.start + ti.len;
+
+  uint32_t fbits = 0;  // bit i: item i goes front
+  RT and_lo = (RT)~(RT)0, or_lo = 0, and_hi = (RT)~(RT)0, or_hi = 0;
+#pragma unroll
+  for (int i = 0; i < IPT; ++i) {
+    const bool valid = (uint32_t)(i * BLOCK + tid) < cnt;
+    const RT k = (RT)r.key[i];
+    const bool back = valid && ((((k >> bit) & 1u) ^ f) != 0);
+    const bool front = valid && !back;
+    const uint64_t fm = __ballot(front);
+    if (lane == 0) sh.cnt[i * WAVES + wave] = (uint32_t)__popcll(fm);
+    fbits |= (uint32_t)front << i;
+    const RT mf = front ? (RT)~(RT)0 : (RT)0;
+    const RT mb = back ? (RT)~(RT)0 : (RT)0;
+    and_lo &= k | ~mf;
+    or_lo |= k & mf;
+    and_hi &= k | ~mb;
+    or_hi |= k & mb;
+  }
+  {
+    const uint64_t al = wave_and_dpp((uint64_t)and_lo | (sizeof(KT) == 8 ? 0ull : ~0ull << 32));
+    const uint64_t ol = wave_or_dpp((uint64_t)or_lo);
+    const uint64_t ah = wave_and_dpp((uint64_t)and_hi | (sizeof(KT) == 8 ? 0ull : ~0ull << 32));
+    const uint64_t oh = wave_or_dpp((uint64_t)or_hi);
+    if (lane == 0) {
+      atomicAnd((unsigned long long *)&sh.red[0], (unsigned long long)al);
+      atomicOr((unsigned long long *)&sh.red[1], (unsigned long long)ol);
+      atomicAnd((unsigned long long *)&sh.red[2], (unsigned long long)ah);
+      atomicOr((unsigned long long *)&sh.red[3], (unsigned long long)oh);
+    }
+  }
+  if (wave == 0) {
+    const uint32_t p = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan_dpp(r.pv), 63);
+    if (lane == 0) sh.prefix = p;
+  }
+  if (tid == 0) {
+    // publish the next tile (claimed and fetched one tile earlier)
+    sh.tile[cur ^ 1] = cl.t;
+    if (cl.t < ntiles) sh.seg[cur ^ 1] = cl.d;
+  }
+  __syncthreads();
+
+  const uint32_t cv = lane < NCNT ? sh.cnt[lane] : 0u;
+  const uint32_t cinc = wave_incl_scan_dpp(cv);
+  const uint32_t c1 = (uint32_t)__builtin_amdgcn_readlane((int)cinc, 63);
+  const uint64_t P1 = uni(sh.prefix);
+  if (tid == 0) {
+    // An AND word only loses bits and an OR word only gains them, so an
+    // atomic whose value the (even stale) read already absorbs is skipped:
+    // big segments would otherwise send every tile's atomics to the same
+    // four words.
+    AccRep *ac = &a.acc[ti.slot].r[ti.t % ACC_REPL];
+    const uint64_t al = sh.red[0], ol = sh.red[1], ah = sh.red[2], oh = sh.red[3];
+    sh.red[0] = ~0ull;
+    sh.red[1] = 0;
+    sh.red[2] = ~0ull;
+    sh.red[3] = 0;
+    if ((r.acw[0] & al) != r.acw[0]) atomic_and_u64(&ac->and_lo, al);
+    if ((r.acw[1] | ol) != r.acw[1]) atomic_or_u64(&ac->or_lo, ol);
+    if ((r.acw[2] & ah) != r.acw[2]) atomic_and_u64(&ac->and_hi, ah);
+    if ((r.acw[3] | oh) != r.acw[3]) atomic_or_u64(&ac->or_hi, oh);
+    if (ti.lo + cnt == ti.len) a.acc[ti.slot].split = P1 + c1;
+  }
+
+  // start the next tile's loads before this tile's stores: stores and
+  // loads retire in order, so waiting for them later does not wait for
+  // these stores
+  tn = tile_info<TILE>(sh.seg[cur ^ 1], sh.tile[cur ^ 1], ntiles);
+  if (tn.valid) issue_loads<KT, IDX, BLOCK, IPT>(a, tn, rn);
+  if (tid == 0) {
+    cl.t = atomic_add_u32(&a.hdr->grab[a.level], 1u);
+    if (cl.t < ntiles) cl.d = a.tiles[cl.t];
+  }
+
+  const uint32_t c2 = cnt - c1;
+  const uint64_t P2 = ti.lo - P1;
+  // Front key of tile rank r1 -> start + P1 + r1; back key of tile back
+  // rank r2 -> end - 1 - P2 - r2.  Each wave's front lanes and back lanes
+  // write two contiguous runs; L2 merges the partial lines.
+  const rsrc_t fkr = make_rsrc(a.keys_out + (ti.start + P1), c1 * (uint32_t)sizeof(KT));
+  const rsrc_t bkr = make_rsrc(a.keys_out + (end - P2 - c2), c2 * (uint32_t)sizeof(KT));
+  const rsrc_t fir = make_rsrc(IDX ? a.idx_out + (ti.start + P1) : nullptr, IDX ? c1 * 4u : 0u);
+  const rsrc_t bir = make_rsrc(IDX ? a.idx_out + (end - P2 - c2) : nullptr, IDX ? c2 * 4u : 0u);
+  uint32_t rk[IPT];  // rank within the key's own side of this tile
+#pragma unroll
+  for (int i = 0; i < IPT; ++i) {
+    const uint32_t q = (uint32_t)(i * BLOCK + tid);
+    const bool valid = q < cnt;
+    const bool front = (fbits >> i) & 1u;
+    const uint64_t fm = __ballot(front);
+    const uint32_t base = (uint32_t)__builtin_amdgcn_readlane((int)(cinc - cv), i * WAVES + wave);
+    const uint32_t r1 = base + lanes_below(fm);
+    const uint32_t r2 = q - r1;
+    // both stores are issued by every lane with a uniform descriptor; the
+    // side a lane does not belong to gets an out-of-range offset, which the
+    // hardware drops (a per-lane choice of descriptor would make the
+    // compiler loop over the distinct descriptors)
+    const uint32_t fo = front ? r1 : OOR_ELEMS;
+    const uint32_t bo = (valid && !front) ? (c2 - 1 - r2) : OOR_ELEMS;
+    buf_store(fkr, fo * (uint32_t)sizeof(KT), r.key[i]);
+    buf_store(bkr, bo * (uint32_t)sizeof(KT), r.key[i]);
+    if (IDX) {
+      buf_store(fir, fo * 4u, r.ix[i]);
+      buf_store(bir, bo * 4u, r.ix[i]);
+    }
+    rk[i] = front ? r1 : r2;
+  }
+
+  // next level (bit - 1): for each child tile it will read, the number of
+  // keys that go front.  A child's keys have the segment's sign, or their
+  // side's when this level splits the sign bit.
+  const bool nxt = bit > 0;
+  if (nxt) {
+    const int nbit = bit - 1;
+    uint32_t sgn_f = (ti.meta & META_SIGN) ? 1u : 0u, sgn_b = sgn_f;
+    if (bit == a.w - 1) {
+      sgn_f = f;
+      sgn_b = 1u - f;
+    }
+    const uint32_t fnf = (uint32_t)a.desc ^ (uint32_t)(a.mode == MODE_F && sgn_f);
+    const uint32_t fnb = (uint32_t)a.desc ^ (uint32_t)(a.mode == MODE_F && sgn_b);
+    // ranks from which a key lies in its child's following tile
+    const uint32_t xf = (uint32_t)((P1 / TILE + 1) * TILE - P1);
+    const uint32_t xb = (uint32_t)((P2 / TILE + 1) * TILE - P2);
+    uint32_t n0 = 0, n1 = 0, n2 = 0, n3 = 0;
+#pragma unroll
+    for (int i = 0; i < IPT; ++i) {
+      const bool valid = (uint32_t)(i * BLOCK + tid) < cnt;
+      const uint32_t front = (fbits >> i) & 1u;
+      const uint32_t nb = (uint32_t)(((RT)r.key[i] >> nbit) & 1u);
+      const bool nf = valid && nb == (front ? fnf : fnb);
+      const bool later = rk[i] >= (front ? xf : xb);
+      const uint64_t fm = __ballot(front);
+      const uint64_t nfm = __ballot(nf);
+      const uint64_t lm = __ballot(later);
+      n0 += (uint32_t)__popcll(nfm & fm & ~lm);
+      n1 += (uint32_t)__popcll(nfm & fm & lm);
+      n2 += (uint32_t)__popcll(nfm & ~fm & ~lm);
+      n3 += (uint32_t)__popcll(nfm & ~fm & lm);
+    }
+    if (lane == 0) {
+      if (n0) atomicAdd(&sh.nxt[0], n0);
+      if (n1) atomicAdd(&sh.nxt[1], n1);
+      if (n2) atomicAdd(&sh.nxt[2], n2);
+      if (n3) atomicAdd(&sh.nxt[3], n3);
+    }
+  }
+  __syncthreads();
+  if (tid == 0 && nxt) {
+    // child c's tile j of the next level counts at 2*tile0 + c*nt + j
+    const uint32_t nt = (uint32_t)((ti.len + TILE - 1) / TILE);
+    const uint32_t base[2] = {2 * ti.tile0, 2 * ti.tile0 + nt};
+    const uint32_t j0[2] = {(uint32_t)(P1 / TILE), (uint32_t)(P2 / TILE)};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const uint32_t c = sh.nxt[k];
+      sh.nxt[k] = 0;
+      const uint32_t jj = j0[k >> 1] + (k & 1);
+      if (c) {
+        atomic_add_u32(&a.tcnt_out[base[k >> 1] + jj], c);
+        atomic_add_u32(&a.scnt_out[base[k >> 1] + (jj >> 6)], c);
+      }
+    }
+  }
+  cur ^= 1;
+}
+
+// One global level: every live segment is split on its bit.  Workgroups
+// take tiles in increasing order (claimed and fetched a tile ahead, loaded a
+// tile ahead).  A tile's front offset inside its segment comes from the
+// counts that the previous level (or the level-0 count pass) produced for
+// this bit: the sum over the tile's 64-tile group predecessors plus its own
+// group's earlier tiles.  Segments whose bit was reached by skipping have no
+// such counts and use a decoupled look-back instead.  Front keys go to
+// start + prefix, back keys are placed from the segment's right end
+// leftwards, so the back child is stored reversed.  While writing, each
+// tile also counts, for every child tile of the next level, how many keys
+// will go front on bit - 1 (the usual next bit).
 template <typename KT, bool IDX, int BLOCK, int IPT>
 __global__ __launch_bounds__(BLOCK) void level_kernel(LevelArgs<KT> a) {
   constexpr int WAVES = BLOCK / 64;
   constexpr int TILE = BLOCK * IPT;
   constexpr int NCNT = IPT * WAVES;
-  constexpr int CPL = (NCNT + 63) / 64;
-  __shared__ KT s_key[TILE];
-  __shared__ uint32_t s_idx[IDX ? TILE : 1];
-  __shared__ uint32_t s_cnt[NCNT];
-  __shared__ uint64_t s_red[4][WAVES];
-  __shared__ Seg s_seg;
-  __shared__ uint32_t s_tile, s_slot, s_c1;
-  __shared__ uint64_t s_prefix;
+  static_assert(NCNT <= 64, "one count per lane in the per-wave scan");
+  __shared__ LevelShared<NCNT> sh;
+  const int tid = threadIdx.x;
+  const uint32_t ntiles = (uint32_t)(a.hdr->packed[a.level] & 0xffffffffu);
 
+  Claim cl;
+  cl.t = 0;
+  if (tid == 0) {
+    const uint32_t t = atomic_add_u32(&a.hdr->grab[a.level], 1u);
+    sh.tile[0] = t;
+    if (t < ntiles) sh.seg[0] = a.tiles[t];
+    cl.t = atomic_add_u32(&a.hdr->grab[a.level], 1u);
+    if (cl.t < ntiles) cl.d = a.tiles[cl.t];
+    sh.nxt[0] = sh.nxt[1] = sh.nxt[2] = sh.nxt[3] = 0;
+    sh.red[0] = ~0ull;
+    sh.red[1] = 0;
+    sh.red[2] = ~0ull;
+    sh.red[3] = 0;
+  }
+  __syncthreads();
+  int cur = 0;
+  TileInfo ta = tile_info<TILE>(sh.seg[0], sh.tile[0], ntiles), tb;
+  TileRegs<KT, IPT> ra, rb;
+  if (ta.valid) issue_loads<KT, IDX, BLOCK, IPT>(a, ta, ra);
+  for (;;) {
+    if (!ta.valid) break;
+    level_tile<KT, IDX, BLOCK, IPT>(a, ta, ra, tb, rb, sh, cur, cl, ntiles);
+    if (!tb.valid) break;
+    level_tile<KT, IDX, BLOCK, IPT>(a, tb, rb, ta, ra, sh, cur, cl, ntiles);
+  }
+}
+
+// Front keys of every tile of a level whose segment reached its bit by
+// skipping (or is a level-0 segment), so that no level has to wait for
+// earlier tiles: the previous level counted only bit - 1.
+template <typename KT>
+struct CountArgs {
+  const KT *keys;
+  const Seg *tiles;
+  Header *hdr;
+  uint32_t *tcnt;
+  uint32_t *scnt;
+  int w, mode, desc, level;
+};
+
+template <typename KT, int BLOCK, int IPT>
+__global__ __launch_bounds__(BLOCK) void count_kernel(CountArgs<KT> a) {
+  constexpr int WAVES = BLOCK / 64;
+  constexpr int TILE = BLOCK * IPT;
+  __shared__ uint32_t s_w[WAVES];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const uint32_t ntiles = (uint32_t)(a.hdr->packed[a.level] & 0xffffffffu);
-  const uint32_t epoch = (uint32_t)a.level + 1;
-
-  for (;;) {
-    if (tid == 0) {
-      const uint32_t t = atomic_add_u32(&a.hdr->grab[a.level], 1u);
-      s_tile = t;
-      if (t < ntiles) {
-        const uint32_t slot = a.tile_map[t];
-        s_slot = slot;
-        s_seg = a.segs[slot];
-      }
-    }
-    __syncthreads();
-    const uint32_t t = s_tile;
-    if (t >= ntiles) break;
-    const uint32_t slot = s_slot;
-    const uint64_t start = s_seg.start, len = s_seg.len;
-    const uint32_t meta = s_seg.meta, tile0 = s_seg.tile0;
+  for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const uint32_t meta = uni(a.tiles[t].meta);
+    if (meta & META_PRE) continue;
+    const uint64_t start = uni(a.tiles[t].start), len = uni(a.tiles[t].len);
+    const uint32_t tile0 = uni(a.tiles[t].tile0), cbase = uni(a.tiles[t].cbase);
     const int bit = (int)(meta & BIT_MASK);
-    const bool rev = (meta & META_REV) != 0;
-    const bool iota = (meta & META_IOTA) != 0;
-    const int f = flip_of(bit, a.w, a.mode, a.desc, (meta & META_SIGN) ? 1 : 0);
+    const uint32_t f = (uint32_t)flip_of(bit, a.w, a.mode, a.desc, (meta & META_SIGN) ? 1 : 0);
     const uint32_t j = t - tile0;
     const uint64_t lo = (uint64_t)j * TILE;
     const uint32_t cnt = (uint32_t)((len - lo) < (uint64_t)TILE ? (len - lo) : (uint64_t)TILE);
-    const uint64_t end = start + len;
-
-    // load the tile in logical order (right to left for a reversed segment)
-    KT key[IPT];
-    uint32_t ix[IPT];
+    // the tile's keys as a set: [start+lo, +cnt) forward, [end-lo-cnt, +cnt) reversed
+    const uint64_t sbase = (meta & META_REV) ? (start + len - lo - cnt) : (start + lo);
+    const rsrc_t kr = make_rsrc(a.keys + sbase, cnt * (uint32_t)sizeof(KT));
+    uint32_t c = 0;
 #pragma unroll
     for (int i = 0; i < IPT; ++i) {
       const uint32_t q = (uint32_t)(i * BLOCK + tid);
-      const uint64_t pos = lo + q;
-      key[i] = 0;
-      ix[i] = 0;
-      if (q < cnt) {
-        const uint64_t addr = rev ? (end - 1 - pos) : (start + pos);
-        key[i] = a.keys_in[addr];
-        if (IDX) ix[i] = iota ? (uint32_t)pos : a.idx_in[addr];
-      }
+      const uint64_t k = (uint64_t)buf_load<KT>(kr, q * (uint32_t)sizeof(KT));
+      c += (q < cnt) && ((((k >> bit) & 1ull) ^ (uint64_t)f) == 0);
     }
-    // front/back test, per-(item, wave) front counts, child AND/OR
-    uint64_t fm[IPT];
-    uint64_t and_lo = ~0ull, or_lo = 0, and_hi = ~0ull, or_hi = 0;
-#pragma unroll
-    for (int i = 0; i < IPT; ++i) {
-      const uint32_t q = (uint32_t)(i * BLOCK + tid);
-      const bool valid = q < cnt;
-      const uint64_t k = (uint64_t)key[i];
-      const bool back = valid && ((((k >> bit) & 1ull) ^ (uint64_t)f) != 0);
-      const bool front = valid && !back;
-      fm[i] = __ballot(front);
-      if (lane == 0) s_cnt[i * WAVES + wave] = (uint32_t)__popcll(fm[i]);
-      if (front) { and_lo &= k; or_lo |= k; }
-      if (back) { and_hi &= k; or_hi |= k; }
-    }
-    and_lo = wave_and_u64(and_lo);
-    or_lo = wave_or_u64(or_lo);
-    and_hi = wave_and_u64(and_hi);
-    or_hi = wave_or_u64(or_hi);
-    if (lane == 0) {
-      s_red[0][wave] = and_lo;
-      s_red[1][wave] = or_lo;
-      s_red[2][wave] = and_hi;
-      s_red[3][wave] = or_hi;
-    }
+    c = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan_dpp(c), 63);
+    if (lane == 0) s_w[wave] = c;
     __syncthreads();
-
-    if (wave == 0) {
-      // exclusive scan of the (item, wave) front counts; position order is
-      // item-major, then wave, then lane
-      uint32_t v[CPL];
+    if (tid == 0) {
       uint32_t sum = 0;
 #pragma unroll
-      for (int c = 0; c < CPL; ++c) {
-        const int e = lane * CPL + c;
-        v[c] = e < NCNT ? s_cnt[e] : 0u;
-        sum += v[c];
-      }
-      const uint32_t incl = wave_incl_scan_u32(sum);
-      uint32_t ex = incl - sum;
-#pragma unroll
-      for (int c = 0; c < CPL; ++c) {
-        const int e = lane * CPL + c;
-        if (e < NCNT) s_cnt[e] = ex;
-        ex += v[c];
-      }
-      const uint32_t c1 = __shfl(incl, 63);
-      const uint64_t P1 = look_back(a.lookback, t, tile0, c1, epoch, &a.hdr->status);
-      if (lane == 0) {
-        s_prefix = P1;
-        s_c1 = c1;
-        uint64_t al = ~0ull, ol = 0, ah = ~0ull, oh = 0;
-#pragma unroll
-        for (int w2 = 0; w2 < WAVES; ++w2) {
-          al &= s_red[0][w2];
-          ol |= s_red[1][w2];
-          ah &= s_red[2][w2];
-          oh |= s_red[3][w2];
-        }
-        Acc *ac = &a.acc[slot];
-        if (c1 > 0) {
-          atomic_and_u64(&ac->and_lo, al);
-          atomic_or_u64(&ac->or_lo, ol);
-        }
-        if (cnt > c1) {
-          atomic_and_u64(&ac->and_hi, ah);
-          atomic_or_u64(&ac->or_hi, oh);
-        }
-        if (lo + cnt == len) ac->split = P1 + c1;
-      }
-    }
-    __syncthreads();
-
-    // stage the tile as [front run | back run reversed] in LDS
-    const uint64_t P1 = s_prefix;
-    const uint32_t c1 = s_c1;
-#pragma unroll
-    for (int i = 0; i < IPT; ++i) {
-      const uint32_t q = (uint32_t)(i * BLOCK + tid);
-      if (q < cnt) {
-        const uint32_t r1 = s_cnt[i * WAVES + wave] + lanes_below(fm[i]);
-        const bool front = (fm[i] >> lane) & 1ull;
-        const uint32_t x = front ? r1 : (cnt - 1 - (q - r1));
-        s_key[x] = key[i];
-        if (IDX) s_idx[x] = ix[i];
-      }
-    }
-    __syncthreads();
-
-    // two contiguous runs: front keys at start + P1 + x, back keys counted
-    // from the segment's right end (P2 back keys precede this tile)
-    const uint64_t P2 = lo - P1;
-#pragma unroll
-    for (int i = 0; i < IPT; ++i) {
-      const uint32_t x = (uint32_t)(i * BLOCK + tid);
-      if (x < cnt) {
-        const uint64_t dst = (x < c1) ? (start + P1 + x) : (end - P2 - (cnt - x));
-        a.keys_out[dst] = s_key[x];
-        if (IDX) a.idx_out[dst] = s_idx[x];
-      }
+      for (int w2 = 0; w2 < WAVES; ++w2) sum += s_w[w2];
+      a.tcnt[cbase + j] = sum;
+      if (sum) atomic_add_u32(&a.scnt[cbase + (j >> 6)], sum);
     }
     __syncthreads();
   }
@@ -630,38 +944,53 @@ struct FinishArgs {
   int w, mode, desc, idx64, no_skip;
 };
 
-// One workgroup per segment of at most BLOCK*IPT keys: all remaining bits
-// are split in LDS, MSB first, each split stable within every group of keys
-// that share the bits above (the groups are tracked with head flags that
-// travel with the keys).  Writes the final keys and indices to the caller's
-// buffers.
-template <typename KT, bool IDX, int BLOCK, int IPT>
+// Rank word of a key: bit b is 1 exactly when the key goes to the back part
+// in a split on bit b (the test of Algorithm 1 with the direction rules of
+// Algorithms 3-5), so sorting by it ascending is the method's order.  The
+// sign decides the direction of the lower bits of float keys.
+template <typename KT>
+__device__ __forceinline__ KT rank_word(KT k, int w, int mode, int desc) {
+  const KT top = (KT)((KT)1 << (w - 1));
+  KT m = desc ? (KT)~(KT)0 : (KT)0;
+  if (mode != MODE_U) m ^= top;
+  if (mode == MODE_F && (k & top)) m ^= (KT)~top;
+  return (KT)(k ^ m);
+}
+
+// One workgroup per segment of at most BLOCK*IPT keys: the keys are loaded
+// once, all remaining bits are resolved in LDS, and the final keys and
+// indices go to the caller's buffers (the switch to a cache-resident routine
+// for small parts that the paper proposes in Sections IV-B and V).  The
+// segment's keys share every bit above its current bit, so a stable sort of
+// the rank words on the bits where the segment's keys differ is the same
+// result as the remaining bit-by-bit splits.  It runs as stable passes over
+// RB of those bits at a time, least significant first; each pass ranks keys
+// with wave ballots (the lanes holding the same digit), per-(digit, chunk)
+// counts and one block-wide scan.
+template <typename KT, bool IDX, int BLOCK, int IPT, int RB>
 __global__ __launch_bounds__(BLOCK) void finish_kernel(FinishArgs<KT> a) {
   constexpr int WAVES = BLOCK / 64;
   constexpr int T = BLOCK * IPT;
-  constexpr int NCH = IPT * WAVES;  // 64-key chunks
-  constexpr int CPL = (NCH + 63) / 64;
+  constexpr int NCH = IPT * WAVES;  // 64-key chunks, in position order
+  constexpr int NDIG = 1 << RB;
+  constexpr int NH = NDIG * NCH;
+  constexpr int HPT = (NH + BLOCK - 1) / BLOCK;  // histogram entries per thread
   __shared__ KT s_key[T];
   __shared__ uint32_t s_idx[IDX ? T : 1];
-  __shared__ uint8_t s_head[T];
-  __shared__ uint32_t s_tot[T];
-  __shared__ uint32_t s_ccnt[NCH];
-  __shared__ int32_t s_chead[NCH];
-  __shared__ uint8_t s_cfirst[NCH + 1];
+  __shared__ uint32_t s_hist[NH];
   __shared__ uint64_t s_red[2][WAVES];
+  __shared__ uint32_t s_wsum[WAVES];
   __shared__ Seg s_seg;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const uint32_t nf = a.hdr->n_finish;
   const uint64_t lt = (1ull << lane) - 1;
-  const uint64_t le = lane == 63 ? ~0ull : ((2ull << lane) - 1);
-  if (tid == 0) s_cfirst[NCH] = 1;
 
   for (uint32_t e = blockIdx.x; e < nf; e += gridDim.x) {
     if (tid == 0) s_seg = a.list[e];
     __syncthreads();
     const uint64_t start = s_seg.start;
-    const uint32_t len = (uint32_t)s_seg.len;
+    const uint32_t len = (uint32_t)(s_seg.len < (uint64_t)T ? s_seg.len : (uint64_t)T);
     const uint32_t meta = s_seg.meta;
     const int bit0 = (int)(meta & BIT_MASK);
     const bool rev = (meta & META_REV) != 0;
@@ -669,16 +998,15 @@ __global__ __launch_bounds__(BLOCK) void finish_kernel(FinishArgs<KT> a) {
     const int buf = (meta & META_BUF) ? 1 : 0;
     const KT *kin = a.keys_buf[buf];
     const uint32_t *iin = a.idx_buf[buf];
+    if (tid == 0 && s_seg.len > (uint64_t)T) atomic_or_u32(&a.hdr->status, STATUS_WAIT_TIMEOUT);
 
     KT key[IPT];
     uint32_t ix[IPT];
-    bool head[IPT];
 #pragma unroll
     for (int i = 0; i < IPT; ++i) {
       const uint32_t p = (uint32_t)(i * BLOCK + tid);
       key[i] = 0;
       ix[i] = 0;
-      head[i] = p == 0;
       if (p < len) {
         const uint64_t addr = rev ? (start + len - 1 - p) : (start + p);
         key[i] = kin[addr];
@@ -687,13 +1015,14 @@ __global__ __launch_bounds__(BLOCK) void finish_kernel(FinishArgs<KT> a) {
     }
 
     if (bit0 != (int)BIT_NONE && len >= 2) {
-      // bits on which the whole segment agrees are skipped
+      // bits (at or below bit0) on which the segment's rank words differ
       uint64_t andv = ~0ull, orv = 0;
 #pragma unroll
       for (int i = 0; i < IPT; ++i) {
         if ((uint32_t)(i * BLOCK + tid) < len) {
-          andv &= (uint64_t)key[i];
-          orv |= (uint64_t)key[i];
+          const uint64_t u = (uint64_t)rank_word<KT>(key[i], a.w, a.mode, a.desc);
+          andv &= u;
+          orv |= u;
         }
       }
       andv = wave_and_u64(andv);
@@ -711,90 +1040,75 @@ __global__ __launch_bounds__(BLOCK) void finish_kernel(FinishArgs<KT> a) {
         orv |= s_red[1][w2];
       }
       const uint64_t below = (bit0 == 63) ? ~0ull : ((2ull << bit0) - 1);
-      const uint64_t todo = a.no_skip ? below : ((andv ^ orv) & below);
+      uint64_t todo = a.no_skip ? below : ((andv ^ orv) & below);
 
-      for (int b = bit0; b >= 0; --b) {
-        if (!((todo >> b) & 1ull)) continue;
-        uint64_t fm[IPT], hm[IPT];
+      while (todo) {
+        // this pass: the RB lowest bits still to do
+        int pos[RB];
+        int nb = 0;
+#pragma unroll
+        for (int k = 0; k < RB; ++k) {
+          pos[k] = 0;
+          if (todo) {
+            pos[k] = __ffsll((unsigned long long)todo) - 1;
+            todo &= todo - 1;
+            nb = k + 1;
+          }
+        }
+#pragma unroll
+        for (int h = 0; h < HPT; ++h) {
+          const int x = h * BLOCK + tid;
+          if (x < NH) s_hist[x] = 0;
+        }
+        __syncthreads();
+        uint32_t dg[IPT], rk[IPT];
 #pragma unroll
         for (int i = 0; i < IPT; ++i) {
           const uint32_t p = (uint32_t)(i * BLOCK + tid);
           const bool valid = p < len;
-          const uint64_t k = (uint64_t)key[i];
-          const int fl = flip_of(b, a.w, a.mode, a.desc, (int)((k >> (a.w - 1)) & 1ull));
-          const bool back = valid && ((((k >> b) & 1ull) ^ (uint64_t)fl) != 0);
-          fm[i] = __ballot(valid && !back);
-          hm[i] = __ballot(valid && head[i]);
-          if (lane == 0) {
-            const int c = i * WAVES + wave;
-            if (hm[i]) {
-              const int h = 63 - __clzll((long long)hm[i]);
-              s_chead[c] = c * 64 + h;
-              s_ccnt[c] = (uint32_t)__popcll(fm[i] >> h);
-            } else {
-              s_chead[c] = -1;
-              s_ccnt[c] = (uint32_t)__popcll(fm[i]);
+          const uint64_t u = (uint64_t)rank_word<KT>(key[i], a.w, a.mode, a.desc);
+          uint32_t d = 0;
+#pragma unroll
+          for (int k = 0; k < RB; ++k)
+            if (k < nb) d |= (uint32_t)((u >> pos[k]) & 1ull) << k;
+          // lanes of this 64-key chunk holding the same digit
+          uint64_t peers = __ballot(valid);
+#pragma unroll
+          for (int k = 0; k < RB; ++k) {
+            if (k < nb) {
+              const uint64_t bk = __ballot(valid && ((d >> k) & 1u));
+              peers &= ((d >> k) & 1u) ? bk : ~bk;
             }
-            s_cfirst[c] = (uint8_t)(hm[i] & 1ull);
           }
+          dg[i] = d;
+          rk[i] = (uint32_t)__popcll(peers & lt);
+          if (valid && (peers & lt) == 0)
+            s_hist[d * NCH + i * WAVES + wave] = (uint32_t)__popcll(peers);
         }
         __syncthreads();
-        if (wave == 0) {
-          // segmented exclusive scan of the chunk summaries: carry-in = the
-          // last head before the chunk and the front keys counted since it
-          int32_t hv[CPL];
-          uint32_t cv[CPL];
-          int32_t ah = -1;
-          uint32_t ac = 0;
+        // exclusive scan of the histogram in (digit, chunk) order
+        {
+          uint32_t v[HPT];
+          uint32_t sum = 0;
 #pragma unroll
-          for (int c = 0; c < CPL; ++c) {
-            const int e2 = lane * CPL + c;
-            hv[c] = e2 < NCH ? s_chead[e2] : -1;
-            cv[c] = e2 < NCH ? s_ccnt[e2] : 0u;
-            if (hv[c] >= 0) { ah = hv[c]; ac = cv[c]; } else { ac += cv[c]; }
+          for (int h = 0; h < HPT; ++h) {
+            const int x = tid * HPT + h;
+            v[h] = x < NH ? s_hist[x] : 0u;
+            sum += v[h];
           }
-          // inclusive scan of (ah, ac) with the segmented operator
+          const uint32_t inc = wave_incl_scan_u32(sum);
+          if (lane == 63) s_wsum[wave] = inc;
+          __syncthreads();
+          uint32_t base = 0;
 #pragma unroll
-          for (int d = 1; d < 64; d <<= 1) {
-            const int32_t uh = __shfl_up(ah, d);
-            const uint32_t uc = __shfl_up(ac, d);
-            if (lane >= d && ah < 0) { ah = uh; ac += uc; }
-          }
-          int32_t xh = __shfl_up(ah, 1);
-          uint32_t xc = __shfl_up(ac, 1);
-          if (lane == 0) { xh = -1; xc = 0; }
+          for (int w2 = 0; w2 < WAVES; ++w2)
+            if (w2 < wave) base += s_wsum[w2];
+          uint32_t ex = base + inc - sum;
 #pragma unroll
-          for (int c = 0; c < CPL; ++c) {
-            const int e2 = lane * CPL + c;
-            if (e2 < NCH) {
-              // reuse the chunk arrays for the exclusive carry-in
-              s_chead[e2] = xh;
-              s_ccnt[e2] = xc;
-            }
-            if (hv[c] >= 0) { xh = hv[c]; xc = cv[c]; } else { xc += cv[c]; }
-          }
-        }
-        __syncthreads();
-        uint32_t gs[IPT], r1[IPT];
-#pragma unroll
-        for (int i = 0; i < IPT; ++i) {
-          const uint32_t p = (uint32_t)(i * BLOCK + tid);
-          const int c = i * WAVES + wave;
-          const uint64_t hle = hm[i] & le;
-          if (hle) {
-            const int h = 63 - __clzll((long long)hle);
-            gs[i] = (uint32_t)(c * 64 + h);
-            r1[i] = (uint32_t)__popcll(fm[i] & lt & ~((1ull << h) - 1));
-          } else {
-            gs[i] = (uint32_t)s_chead[c];
-            r1[i] = s_ccnt[c] + (uint32_t)__popcll(fm[i] & lt);
-          }
-          const bool front = (fm[i] >> lane) & 1ull;
-          if (p < len) {
-            const bool nxt_head = (p + 1 == len) ||
-                                  (lane < 63 ? ((hm[i] >> (lane + 1)) & 1ull) != 0
-                                             : s_cfirst[c + 1] != 0);
-            if (nxt_head) s_tot[gs[i]] = r1[i] + (front ? 1u : 0u);
+          for (int h = 0; h < HPT; ++h) {
+            const int x = tid * HPT + h;
+            if (x < NH) s_hist[x] = ex;
+            ex += v[h];
           }
         }
         __syncthreads();
@@ -802,29 +1116,21 @@ __global__ __launch_bounds__(BLOCK) void finish_kernel(FinishArgs<KT> a) {
         for (int i = 0; i < IPT; ++i) {
           const uint32_t p = (uint32_t)(i * BLOCK + tid);
           if (p < len) {
-            const bool front = (fm[i] >> lane) & 1ull;
-            const uint32_t F = s_tot[gs[i]];
-            const uint32_t r2 = (p - gs[i]) - r1[i];
-            const uint32_t dst = front ? gs[i] + r1[i] : gs[i] + F + r2;
+            const uint32_t dst = s_hist[dg[i] * NCH + i * WAVES + wave] + rk[i];
             s_key[dst] = key[i];
             if (IDX) s_idx[dst] = ix[i];
-            s_head[dst] = (uint8_t)(front ? (r1[i] == 0) : (r2 == 0));
           }
         }
         __syncthreads();
-        bool all_heads = true;
 #pragma unroll
         for (int i = 0; i < IPT; ++i) {
           const uint32_t p = (uint32_t)(i * BLOCK + tid);
           if (p < len) {
             key[i] = s_key[p];
             if (IDX) ix[i] = s_idx[p];
-            head[i] = s_head[p] != 0;
-            all_heads &= head[i];
           }
         }
-        // also the barrier that protects LDS before the next bit
-        if (__syncthreads_and(all_heads)) break;
+        __syncthreads();
       }
     }
 
