@@ -123,7 +123,7 @@ size_t up256(size_t x) { return (x + 255) & ~(size_t)255; }
 // every parent yields at most two finish entries per level; copy entries
 // hold more than T keys each.
 struct Layout {
-  size_t hdr, cnts, segs[2], acc[2], tmap[2], fin, cpy, keys1, idx0, idx1, total;
+  size_t hdr, cnts, segs[2], recs[2], acc[2], tmap[2], fin, cpy, keys1, idx0, idx1, total;
   uint64_t smax, tmax, fmax, cmax;
 };
 
@@ -146,6 +146,7 @@ bool make_layout(int key_bytes, uint64_t n, uint64_t B, bool with_idx, uint32_t 
   // the segments counted by the count pass at recount + tile0
   L->cnts = off; off = up256(off + 4 * (3 * L->tmax) * 4);
   for (int i = 0; i < 2; ++i) { L->segs[i] = off; off = up256(off + L->smax * sizeof(Seg)); }
+  for (int i = 0; i < 2; ++i) { L->recs[i] = off; off = up256(off + L->smax * sizeof(Seg)); }
   for (int i = 0; i < 2; ++i) { L->acc[i] = off; off = up256(off + L->smax * sizeof(Acc)); }
   for (int i = 0; i < 2; ++i) { L->tmap[i] = off; off = up256(off + L->tmax * sizeof(Seg)); }
   L->fin = off; off = up256(off + L->fmax * sizeof(Seg));
@@ -188,6 +189,8 @@ int launch_all(KT *keys, uint64_t n, const int64_t *offsets, uint64_t B, int mod
   Header *hdr = reinterpret_cast<Header *>(scr + L.hdr);
   Seg *segs[2] = {reinterpret_cast<Seg *>(scr + L.segs[0]),
                   reinterpret_cast<Seg *>(scr + L.segs[1])};
+  Seg *recs[2] = {reinterpret_cast<Seg *>(scr + L.recs[0]),
+                  reinterpret_cast<Seg *>(scr + L.recs[1])};
   Acc *acc[2] = {reinterpret_cast<Acc *>(scr + L.acc[0]),
                  reinterpret_cast<Acc *>(scr + L.acc[1])};
   Seg *tmap[2] = {reinterpret_cast<Seg *>(scr + L.tmap[0]),
@@ -225,7 +228,7 @@ int launch_all(KT *keys, uint64_t n, const int64_t *offsets, uint64_t B, int mod
   sa.l = la;
   sa.l.live_next = segs[0];
   sa.l.acc_next = acc[0];
-  sa.l.tiles_next = tmap[0];
+  sa.l.rec_next = recs[0];
   sa.l.next_level = 0;
   sa.offsets = offsets;
   sa.B = B;
@@ -245,6 +248,8 @@ int launch_all(KT *keys, uint64_t n, const int64_t *offsets, uint64_t B, int mod
   for (int lvl = 0; lvl < w; ++lvl) {
     CountArgs<KT> ca;
     ca.keys = kbuf[lvl & 1];
+    ca.live = segs[lvl & 1];
+    ca.rec = recs[lvl & 1];
     ca.tiles = tmap[lvl & 1];
     ca.hdr = hdr;
     ca.tcnt = tcnt[lvl & 1];
@@ -283,7 +288,7 @@ int launch_all(KT *keys, uint64_t n, const int64_t *offsets, uint64_t B, int mod
     pa.l = la;
     pa.l.live_next = segs[(lvl + 1) & 1];
     pa.l.acc_next = acc[(lvl + 1) & 1];
-    pa.l.tiles_next = tmap[(lvl + 1) & 1];
+    pa.l.rec_next = recs[(lvl + 1) & 1];
     pa.l.next_level = lvl + 1;
     pa.live = segs[lvl & 1];
     pa.acc = acc[lvl & 1];

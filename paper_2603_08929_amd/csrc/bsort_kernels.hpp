@@ -40,7 +40,7 @@ constexpr uint32_t META_BUF = 1u << 9;   // data lives in the scratch buffers
 constexpr uint32_t META_IOTA = 1u << 10; // index payload not materialized yet
 constexpr uint32_t META_PRE = 1u << 11;  // the previous level counted `bit` per tile
 
-constexpr uint32_t STATUS_WAIT_TIMEOUT = 1u;
+constexpr uint32_t STATUS_OVERSIZE = 1u;  // a finish entry larger than the workgroup's capacity
 constexpr uint32_t STATUS_BAD_OFFSETS = 2u;
 
 constexpr int MAX_LEVELS = 66;
@@ -83,6 +83,7 @@ struct Header {
   uint64_t finish_keys;        // keys handed to the LDS finish (all levels)
   uint64_t copy_keys;          // keys of retired segments copied back
   uint64_t packed[MAX_LEVELS]; // per level: (live segments << 32) | tiles
+  uint64_t rec_packed[MAX_LEVELS]; // per level: (segments << 32) | tiles to recount
   uint64_t live_keys[MAX_LEVELS]; // per level: keys in live segments
   uint32_t grab[MAX_LEVELS];   // per level: next tile id handed out
 };
@@ -289,9 +290,9 @@ constexpr int KIND_NONE = 0, KIND_LIVE = 1, KIND_FINISH = 2, KIND_COPY = 3;
 
 struct ListArgs {
   Header *hdr;
-  Seg *live_next;       // level (lvl+1) live list
+  Seg *live_next;       // level (lvl+1) live list, in tile order
   Acc *acc_next;
-  Seg *tiles_next;      // level (lvl+1): one descriptor copy per tile
+  Seg *rec_next;        // level (lvl+1) segments the count pass must count
   Seg *fin;
   Seg *cpy;
   int next_level;
@@ -309,17 +310,25 @@ struct Child {
 };
 constexpr uint32_t CBASE_OWN = 0xFFFFFFFFu;
 
+// Replicas of a segment's AND/OR words in use: many only for segments with
+// many tiles (the ones whose tiles would contend).
+__device__ __forceinline__ uint32_t acc_repl(uint64_t len, uint32_t tile) {
+  const uint64_t nt = (len + tile - 1) / tile;
+  return nt >= 256 ? (uint32_t)ACC_REPL : (nt >= 64 ? 4u : 1u);
+}
+
 // Allocates slots for the children of one wave (two per lane) with one
-// atomic per list, writes the descriptors and the tile -> segment map.
+// atomic per list and writes their descriptors.
 __device__ void emit_children(const ListArgs &a, Child (&ch)[2]) {
   const int lane = threadIdx.x & 63;
   // live: slots and tiles packed in one 64-bit counter so that slot order
   // and tile order agree
-  uint64_t mine = 0, klive = 0, kfin = 0, kcpy = 0;
+  uint64_t mine = 0, mrec = 0, klive = 0, kfin = 0, kcpy = 0;
   uint32_t nfin = 0, ncpy = 0;
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
     if (ch[c].kind == KIND_LIVE) { mine += (1ull << 32) | ch[c].tiles; klive += ch[c].len; }
+    if (ch[c].kind == KIND_LIVE && ch[c].cbase == CBASE_OWN) mrec += (1ull << 32) | ch[c].tiles;
     if (ch[c].kind == KIND_FINISH) { nfin++; kfin += ch[c].len; }
     if (ch[c].kind == KIND_COPY) { ncpy++; kcpy += ch[c].len; }
   }
@@ -333,25 +342,29 @@ __device__ void emit_children(const ListArgs &a, Child (&ch)[2]) {
     if (kcpy) atomic_add_u64(&a.hdr->copy_keys, kcpy);
   }
   const uint64_t inc_live = wave_incl_scan_u64(mine);
+  const uint64_t inc_rec = wave_incl_scan_u64(mrec);
   const uint32_t inc_fin = wave_incl_scan_u32(nfin);
   const uint32_t inc_cpy = wave_incl_scan_u32(ncpy);
   const uint64_t tot_live = __shfl(inc_live, 63);
+  const uint64_t tot_rec = __shfl(inc_rec, 63);
   const uint32_t tot_fin = __shfl(inc_fin, 63);
   const uint32_t tot_cpy = __shfl(inc_cpy, 63);
-  uint64_t b_live = 0;
+  uint64_t b_live = 0, b_rec = 0;
   uint32_t b_fin = 0, b_cpy = 0;
   if (lane == 0) {
     if (tot_live) b_live = atomic_add_u64(&a.hdr->packed[a.next_level], tot_live);
+    if (tot_rec) b_rec = atomic_add_u64(&a.hdr->rec_packed[a.next_level], tot_rec);
     if (tot_fin) b_fin = atomic_add_u32(&a.hdr->n_finish, tot_fin);
     if (tot_cpy) b_cpy = atomic_add_u32(&a.hdr->n_copy, tot_cpy);
   }
   b_live = __shfl(b_live, 0);
+  b_rec = __shfl(b_rec, 0);
   b_fin = __shfl(b_fin, 0);
   b_cpy = __shfl(b_cpy, 0);
   uint64_t pos = b_live + (inc_live - mine);
+  uint64_t rpos = b_rec + (inc_rec - mrec);
   uint32_t fpos = b_fin + (inc_fin - nfin);
   uint32_t cpos = b_cpy + (inc_cpy - ncpy);
-  uint32_t slot[2] = {0, 0}, tile0[2] = {0, 0};
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
     Seg s;
@@ -362,14 +375,14 @@ __device__ void emit_children(const ListArgs &a, Child (&ch)[2]) {
     s.cbase = 0;
     s.slot = 0;
     if (ch[c].kind == KIND_LIVE) {
-      slot[c] = (uint32_t)(pos >> 32);
-      tile0[c] = (uint32_t)pos;
-      s.tile0 = tile0[c];
-      s.cbase = ch[c].cbase == CBASE_OWN ? a.recount + tile0[c] : ch[c].cbase;
-      a.live_next[slot[c]] = s;
-      Acc *z = &a.acc_next[slot[c]];
-#pragma unroll
-      for (int k = 0; k < ACC_REPL; ++k) {
+      const uint32_t slot = (uint32_t)(pos >> 32);
+      s.tile0 = (uint32_t)pos;
+      s.cbase = ch[c].cbase == CBASE_OWN ? a.recount + s.tile0 : ch[c].cbase;
+      s.slot = slot;
+      a.live_next[slot] = s;
+      Acc *z = &a.acc_next[slot];
+      const uint32_t nr = acc_repl(ch[c].len, a.tile);
+      for (uint32_t k = 0; k < nr; ++k) {
         z->r[k].and_lo = ~0ull;
         z->r[k].or_lo = 0;
         z->r[k].and_hi = ~0ull;
@@ -377,27 +390,18 @@ __device__ void emit_children(const ListArgs &a, Child (&ch)[2]) {
       }
       z->split = 0;
       pos += (1ull << 32) | ch[c].tiles;
+      if (ch[c].cbase == CBASE_OWN) {
+        // to be counted on its bit before the level; .slot holds the
+        // segment's first tile in the recount tile space
+        Seg r = s;
+        r.slot = (uint32_t)rpos;
+        a.rec_next[rpos >> 32] = r;
+        rpos += (1ull << 32) | ch[c].tiles;
+      }
     } else if (ch[c].kind == KIND_FINISH) {
       a.fin[fpos++] = s;
     } else if (ch[c].kind == KIND_COPY) {
       a.cpy[cpos++] = s;
-    }
-  }
-  // per-tile descriptor copies, written cooperatively by the wave
-  if (__ballot(ch[0].kind == KIND_LIVE || ch[1].kind == KIND_LIVE) == 0) return;
-  for (int src = 0; src < 64; ++src) {
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-      const uint32_t nt = __shfl(ch[c].kind == KIND_LIVE ? ch[c].tiles : 0u, src);
-      if (nt == 0) continue;
-      Seg d;
-      d.start = __shfl(ch[c].start, src);
-      d.len = __shfl(ch[c].len, src);
-      d.meta = __shfl(ch[c].meta, src);
-      d.tile0 = __shfl(tile0[c], src);
-      d.cbase = __shfl(ch[c].cbase == CBASE_OWN ? a.recount + tile0[c] : ch[c].cbase, src);
-      d.slot = __shfl(slot[c], src);
-      for (uint32_t k = lane; k < nt; k += 64) a.tiles_next[d.tile0 + k] = d;
     }
   }
 }
@@ -488,8 +492,8 @@ __global__ void plan_kernel(PlanArgs a) {
       const Seg p = a.live[q];
       const Acc *acp = &a.acc[q];
       uint64_t and_lo = ~0ull, or_lo = 0, and_hi = ~0ull, or_hi = 0;
-#pragma unroll
-      for (int k = 0; k < ACC_REPL; ++k) {
+      const uint32_t nr = acc_repl(p.len, a.l.tile);
+      for (uint32_t k = 0; k < nr; ++k) {
         and_lo &= acp->r[k].and_lo;
         or_lo |= acp->r[k].or_lo;
         and_hi &= acp->r[k].and_hi;
@@ -622,7 +626,7 @@ __device__ __forceinline__ void issue_loads(const LevelArgs<KT> &a, const TileIn
     if (IDX) r.ix[i] = iota ? (uint32_t)(ti.lo + q) : buf_load<uint32_t>(ir, o * 4u);
   }
   if (tid == 0) {
-    const AccRep *ac = &a.acc[ti.slot].r[ti.t % ACC_REPL];
+    const AccRep *ac = &a.acc[ti.slot].r[ti.t % acc_repl(ti.len, (uint32_t)(BLOCK * IPT))];
     r.acw[0] = ac->and_lo;
     r.acw[1] = ac->or_lo;
     r.acw[2] = ac->and_hi;
@@ -713,7 +717,7 @@ __device__ __forceinline__ void level_tile(const LevelArgs<KT> &a, const TileInf
     // atomic whose value the (even stale) read already absorbs is skipped:
     // big segments would otherwise send every tile's atomics to the same
     // four words.
-    AccRep *ac = &a.acc[ti.slot].r[ti.t % ACC_REPL];
+    AccRep *ac = &a.acc[ti.slot].r[ti.t % acc_repl(ti.len, (uint32_t)TILE)];
     const uint64_t al = sh.red[0], ol = sh.red[1], ah = sh.red[2], oh = sh.red[3];
     sh.red[0] = ~0ull;
     sh.red[1] = 0;
@@ -877,13 +881,18 @@ __global__ __launch_bounds__(BLOCK) void level_kernel(LevelArgs<KT> a) {
   }
 }
 
-// Front keys of every tile of a level whose segment reached its bit by
-// skipping (or is a level-0 segment), so that no level has to wait for
-// earlier tiles: the previous level counted only bit - 1.
+// Before each level: (1) the per-tile descriptor map of the level, one
+// thread per tile finding its segment by binary search over the live list
+// (which is in tile order); (2) the front keys of every tile of the
+// segments on the recount list -- level-0 segments and segments that
+// reached their bit by skipping -- since the previous level counted only
+// bit - 1.  With these, no tile of the level waits for another.
 template <typename KT>
 struct CountArgs {
   const KT *keys;
-  const Seg *tiles;
+  const Seg *live;
+  const Seg *rec;
+  Seg *tiles;
   Header *hdr;
   uint32_t *tcnt;
   uint32_t *scnt;
@@ -895,16 +904,38 @@ __global__ __launch_bounds__(BLOCK) void count_kernel(CountArgs<KT> a) {
   constexpr int WAVES = BLOCK / 64;
   constexpr int TILE = BLOCK * IPT;
   __shared__ uint32_t s_w[WAVES];
+  __shared__ Seg s_rs;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const uint32_t ntiles = (uint32_t)(a.hdr->packed[a.level] & 0xffffffffu);
-  for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const uint32_t meta = uni(a.tiles[t].meta);
-    if (meta & META_PRE) continue;
-    const uint64_t start = uni(a.tiles[t].start), len = uni(a.tiles[t].len);
-    const uint32_t tile0 = uni(a.tiles[t].tile0), cbase = uni(a.tiles[t].cbase);
+  const uint64_t pk = a.hdr->packed[a.level];
+  const uint32_t S = (uint32_t)(pk >> 32), ntiles = (uint32_t)pk;
+  for (uint32_t t = blockIdx.x * BLOCK + tid; t < ntiles; t += gridDim.x * BLOCK) {
+    uint32_t lo = 0, hi = S - 1;
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi + 1) >> 1;
+      if (a.live[mid].tile0 <= t) lo = mid;
+      else hi = mid - 1;
+    }
+    a.tiles[t] = a.live[lo];
+  }
+
+  const uint64_t rk = a.hdr->rec_packed[a.level];
+  const uint32_t R = (uint32_t)(rk >> 32), rtiles = (uint32_t)rk;
+  for (uint32_t u = blockIdx.x; u < rtiles; u += gridDim.x) {
+    if (tid == 0) {
+      uint32_t lo = 0, hi = R - 1;
+      while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (a.rec[mid].slot <= u) lo = mid;
+        else hi = mid - 1;
+      }
+      s_rs = a.rec[lo];
+    }
+    __syncthreads();
+    const uint64_t start = uni(s_rs.start), len = uni(s_rs.len);
+    const uint32_t meta = uni(s_rs.meta), cbase = uni(s_rs.cbase);
+    const uint32_t j = u - uni(s_rs.slot);
     const int bit = (int)(meta & BIT_MASK);
     const uint32_t f = (uint32_t)flip_of(bit, a.w, a.mode, a.desc, (meta & META_SIGN) ? 1 : 0);
-    const uint32_t j = t - tile0;
     const uint64_t lo = (uint64_t)j * TILE;
     const uint32_t cnt = (uint32_t)((len - lo) < (uint64_t)TILE ? (len - lo) : (uint64_t)TILE);
     // the tile's keys as a set: [start+lo, +cnt) forward, [end-lo-cnt, +cnt) reversed
@@ -956,6 +987,16 @@ __device__ __forceinline__ KT rank_word(KT k, int w, int mode, int desc) {
   if (mode == MODE_F && (k & top)) m ^= (KT)~top;
   return (KT)(k ^ m);
 }
+// Its inverse: the top bit of the key follows from the top bit of the word.
+template <typename KT>
+__device__ __forceinline__ KT key_of_rank_word(KT u, int w, int mode, int desc) {
+  const KT top = (KT)((KT)1 << (w - 1));
+  KT m = desc ? (KT)~(KT)0 : (KT)0;
+  if (mode != MODE_U) m ^= top;
+  const bool ktop = ((u ^ m) & top) != 0;
+  if (mode == MODE_F && ktop) m ^= (KT)~top;
+  return (KT)(u ^ m);
+}
 
 // One workgroup per segment of at most BLOCK*IPT keys: the keys are loaded
 // once, all remaining bits are resolved in LDS, and the final keys and
@@ -963,10 +1004,11 @@ __device__ __forceinline__ KT rank_word(KT k, int w, int mode, int desc) {
 // for small parts that the paper proposes in Sections IV-B and V).  The
 // segment's keys share every bit above its current bit, so a stable sort of
 // the rank words on the bits where the segment's keys differ is the same
-// result as the remaining bit-by-bit splits.  It runs as stable passes over
-// RB of those bits at a time, least significant first; each pass ranks keys
-// with wave ballots (the lanes holding the same digit), per-(digit, chunk)
-// counts and one block-wide scan.
+// result as the remaining bit-by-bit splits.  Those bits are packed into a
+// contiguous code, sorted in stable passes of RB bits, least significant
+// first; each pass ranks keys with wave ballots (the lanes holding the same
+// digit), per-(digit, chunk) counts and one block-wide scan.  The constant
+// bits are put back at the end.
 template <typename KT, bool IDX, int BLOCK, int IPT, int RB>
 __global__ __launch_bounds__(BLOCK) void finish_kernel(FinishArgs<KT> a) {
   constexpr int WAVES = BLOCK / 64;
@@ -975,7 +1017,8 @@ __global__ __launch_bounds__(BLOCK) void finish_kernel(FinishArgs<KT> a) {
   constexpr int NDIG = 1 << RB;
   constexpr int NH = NDIG * NCH;
   constexpr int HPT = (NH + BLOCK - 1) / BLOCK;  // histogram entries per thread
-  __shared__ KT s_key[T];
+  using RT = typename std::conditional<sizeof(KT) == 8, uint64_t, uint32_t>::type;
+  __shared__ RT s_code[T];
   __shared__ uint32_t s_idx[IDX ? T : 1];
   __shared__ uint32_t s_hist[NH];
   __shared__ uint64_t s_red[2][WAVES];
@@ -989,72 +1032,81 @@ __global__ __launch_bounds__(BLOCK) void finish_kernel(FinishArgs<KT> a) {
   for (uint32_t e = blockIdx.x; e < nf; e += gridDim.x) {
     if (tid == 0) s_seg = a.list[e];
     __syncthreads();
-    const uint64_t start = s_seg.start;
-    const uint32_t len = (uint32_t)(s_seg.len < (uint64_t)T ? s_seg.len : (uint64_t)T);
-    const uint32_t meta = s_seg.meta;
+    const uint64_t start = uni(s_seg.start);
+    const uint64_t slen = uni(s_seg.len);
+    const uint32_t len = (uint32_t)(slen < (uint64_t)T ? slen : (uint64_t)T);
+    const uint32_t meta = uni(s_seg.meta);
     const int bit0 = (int)(meta & BIT_MASK);
     const bool rev = (meta & META_REV) != 0;
     const bool iota = (meta & META_IOTA) != 0;
     const int buf = (meta & META_BUF) ? 1 : 0;
-    const KT *kin = a.keys_buf[buf];
-    const uint32_t *iin = a.idx_buf[buf];
-    if (tid == 0 && s_seg.len > (uint64_t)T) atomic_or_u32(&a.hdr->status, STATUS_WAIT_TIMEOUT);
+    if (tid == 0 && slen > (uint64_t)T) atomic_or_u32(&a.hdr->status, STATUS_OVERSIZE);
 
-    KT key[IPT];
+    // logical position p is at sbase + p (forward) or sbase + len - 1 - p
+    const rsrc_t kr = make_rsrc(a.keys_buf[buf] + start, len * (uint32_t)sizeof(KT));
+    const rsrc_t ir = make_rsrc(IDX ? a.idx_buf[buf] + start : nullptr, IDX && !iota ? len * 4u : 0u);
+    RT u[IPT];
     uint32_t ix[IPT];
 #pragma unroll
     for (int i = 0; i < IPT; ++i) {
       const uint32_t p = (uint32_t)(i * BLOCK + tid);
-      key[i] = 0;
+      const uint32_t o = rev ? (len - 1 - p) : p;  // past len: out of range, reads 0
+      u[i] = (RT)rank_word<KT>(buf_load<KT>(kr, o * (uint32_t)sizeof(KT)), a.w, a.mode, a.desc);
       ix[i] = 0;
-      if (p < len) {
-        const uint64_t addr = rev ? (start + len - 1 - p) : (start + p);
-        key[i] = kin[addr];
-        if (IDX) ix[i] = iota ? p : iin[addr];
-      }
+      if (IDX) ix[i] = iota ? p : buf_load<uint32_t>(ir, o * 4u);
     }
 
+    RT constw = 0;  // the bits all keys share, at their place in the word
+    RT todo = 0;    // the bits still to sort by, at or below bit0
     if (bit0 != (int)BIT_NONE && len >= 2) {
-      // bits (at or below bit0) on which the segment's rank words differ
-      uint64_t andv = ~0ull, orv = 0;
+      RT andv = (RT)~(RT)0, orv = 0;
 #pragma unroll
       for (int i = 0; i < IPT; ++i) {
         if ((uint32_t)(i * BLOCK + tid) < len) {
-          const uint64_t u = (uint64_t)rank_word<KT>(key[i], a.w, a.mode, a.desc);
-          andv &= u;
-          orv |= u;
+          andv &= u[i];
+          orv |= u[i];
         }
       }
-      andv = wave_and_u64(andv);
-      orv = wave_or_u64(orv);
+      const uint64_t aw = wave_and_dpp((uint64_t)andv | (sizeof(RT) == 8 ? 0ull : ~0ull << 32));
+      const uint64_t ow = wave_or_dpp((uint64_t)orv);
       if (lane == 0) {
-        s_red[0][wave] = andv;
-        s_red[1][wave] = orv;
+        s_red[0][wave] = aw;
+        s_red[1][wave] = ow;
       }
       __syncthreads();
-      andv = ~0ull;
-      orv = 0;
+      uint64_t at = ~0ull, ot = 0;
 #pragma unroll
       for (int w2 = 0; w2 < WAVES; ++w2) {
-        andv &= s_red[0][w2];
-        orv |= s_red[1][w2];
+        at &= s_red[0][w2];
+        ot |= s_red[1][w2];
       }
       const uint64_t below = (bit0 == 63) ? ~0ull : ((2ull << bit0) - 1);
-      uint64_t todo = a.no_skip ? below : ((andv ^ orv) & below);
+      todo = (RT)(a.no_skip ? below : ((at ^ ot) & below));
+      constw = (RT)(at & ~(uint64_t)todo);
+    }
 
-      while (todo) {
-        // this pass: the RB lowest bits still to do
-        int pos[RB];
-        int nb = 0;
+    if (todo) {
+      // pack the bits to sort by into a contiguous code (runs of set bits
+      // of `todo`, low to high)
+      const int nbits = (int)__popcll((uint64_t)todo);
+      RT code[IPT];
 #pragma unroll
-        for (int k = 0; k < RB; ++k) {
-          pos[k] = 0;
-          if (todo) {
-            pos[k] = __ffsll((unsigned long long)todo) - 1;
-            todo &= todo - 1;
-            nb = k + 1;
-          }
+      for (int i = 0; i < IPT; ++i) code[i] = 0;
+      {
+        RT m = todo;
+        int pos = 0;
+        while (m) {
+          const int lo = __ffsll((unsigned long long)m) - 1;
+          const RT run = (RT)(m >> lo);
+          const int rl = (~run == 0) ? (int)(8 * sizeof(RT)) - lo : __ffsll((unsigned long long)~run) - 1;
+          const RT rmask = rl >= (int)(8 * sizeof(RT)) ? (RT)~(RT)0 : (RT)(((RT)1 << rl) - 1);
+#pragma unroll
+          for (int i = 0; i < IPT; ++i) code[i] |= ((u[i] >> lo) & rmask) << pos;
+          pos += rl;
+          m &= ~(RT)(rmask << lo);
         }
+      }
+      for (int sh = 0; sh < nbits; sh += RB) {
 #pragma unroll
         for (int h = 0; h < HPT; ++h) {
           const int x = h * BLOCK + tid;
@@ -1064,21 +1116,14 @@ __global__ __launch_bounds__(BLOCK) void finish_kernel(FinishArgs<KT> a) {
         uint32_t dg[IPT], rk[IPT];
 #pragma unroll
         for (int i = 0; i < IPT; ++i) {
-          const uint32_t p = (uint32_t)(i * BLOCK + tid);
-          const bool valid = p < len;
-          const uint64_t u = (uint64_t)rank_word<KT>(key[i], a.w, a.mode, a.desc);
-          uint32_t d = 0;
-#pragma unroll
-          for (int k = 0; k < RB; ++k)
-            if (k < nb) d |= (uint32_t)((u >> pos[k]) & 1ull) << k;
+          const bool valid = (uint32_t)(i * BLOCK + tid) < len;
+          const uint32_t d = (uint32_t)(code[i] >> sh) & (uint32_t)(NDIG - 1);
           // lanes of this 64-key chunk holding the same digit
           uint64_t peers = __ballot(valid);
 #pragma unroll
           for (int k = 0; k < RB; ++k) {
-            if (k < nb) {
-              const uint64_t bk = __ballot(valid && ((d >> k) & 1u));
-              peers &= ((d >> k) & 1u) ? bk : ~bk;
-            }
+            const uint64_t bk = __ballot((d >> k) & 1u);
+            peers &= ((d >> k) & 1u) ? bk : ~bk;
           }
           dg[i] = d;
           rk[i] = (uint32_t)__popcll(peers & lt);
@@ -1096,7 +1141,7 @@ __global__ __launch_bounds__(BLOCK) void finish_kernel(FinishArgs<KT> a) {
             v[h] = x < NH ? s_hist[x] : 0u;
             sum += v[h];
           }
-          const uint32_t inc = wave_incl_scan_u32(sum);
+          const uint32_t inc = wave_incl_scan_dpp(sum);
           if (lane == 63) s_wsum[wave] = inc;
           __syncthreads();
           uint32_t base = 0;
@@ -1117,7 +1162,7 @@ __global__ __launch_bounds__(BLOCK) void finish_kernel(FinishArgs<KT> a) {
           const uint32_t p = (uint32_t)(i * BLOCK + tid);
           if (p < len) {
             const uint32_t dst = s_hist[dg[i] * NCH + i * WAVES + wave] + rk[i];
-            s_key[dst] = key[i];
+            s_code[dst] = code[i];
             if (IDX) s_idx[dst] = ix[i];
           }
         }
@@ -1126,23 +1171,47 @@ __global__ __launch_bounds__(BLOCK) void finish_kernel(FinishArgs<KT> a) {
         for (int i = 0; i < IPT; ++i) {
           const uint32_t p = (uint32_t)(i * BLOCK + tid);
           if (p < len) {
-            key[i] = s_key[p];
+            code[i] = s_code[p];
             if (IDX) ix[i] = s_idx[p];
           }
         }
         __syncthreads();
       }
+      // unpack: the sorted bits back into place, the shared bits around them
+      {
+        RT m = todo;
+        int pos = 0;
+#pragma unroll
+        for (int i = 0; i < IPT; ++i) u[i] = constw;
+        while (m) {
+          const int lo = __ffsll((unsigned long long)m) - 1;
+          const RT run = (RT)(m >> lo);
+          const int rl = (~run == 0) ? (int)(8 * sizeof(RT)) - lo : __ffsll((unsigned long long)~run) - 1;
+          const RT rmask = rl >= (int)(8 * sizeof(RT)) ? (RT)~(RT)0 : (RT)(((RT)1 << rl) - 1);
+#pragma unroll
+          for (int i = 0; i < IPT; ++i) u[i] |= ((code[i] >> pos) & rmask) << lo;
+          pos += rl;
+          m &= ~(RT)(rmask << lo);
+        }
+      }
     }
 
+    const rsrc_t kw = make_rsrc(a.keys_final + start, len * (uint32_t)sizeof(KT));
 #pragma unroll
     for (int i = 0; i < IPT; ++i) {
       const uint32_t p = (uint32_t)(i * BLOCK + tid);
-      if (p < len) {
-        a.keys_final[start + p] = key[i];
-        if (IDX) {
-          if (a.idx64) static_cast<int64_t *>(a.idx_final)[start + p] = (int64_t)ix[i];
-          else static_cast<uint32_t *>(a.idx_final)[start + p] = ix[i];
-        }
+      buf_store(kw, p * (uint32_t)sizeof(KT), key_of_rank_word<KT>((KT)u[i], a.w, a.mode, a.desc));
+    }
+    if (IDX) {
+      if (a.idx64) {
+        const rsrc_t iw = make_rsrc(static_cast<int64_t *>(a.idx_final) + start, len * 8u);
+#pragma unroll
+        for (int i = 0; i < IPT; ++i)
+          buf_store(iw, (uint32_t)(i * BLOCK + tid) * 8u, (uint64_t)ix[i]);
+      } else {
+        const rsrc_t iw = make_rsrc(static_cast<uint32_t *>(a.idx_final) + start, len * 4u);
+#pragma unroll
+        for (int i = 0; i < IPT; ++i) buf_store(iw, (uint32_t)(i * BLOCK + tid) * 4u, ix[i]);
       }
     }
     __syncthreads();
