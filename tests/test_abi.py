@@ -1,0 +1,107 @@
+"""The C ABI without a GPU: the library loads, exports every function that
+include/bsort.h declares, sizes its scratch, and rejects bad arguments
+before it would touch a device (no compute call is made here)."""
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "bsort.h")
+
+_lib = pytest.importorskip("paper_2603_08929_amd._lib")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(bsort_\w+)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for t in ("u8", "u16", "u32", "u64", "i8", "i16", "i32", "i64", "f8", "f16", "f32", "f64"):
+        assert f"bsort_{t}" in names
+    for n in ("bsort_scratch_bytes", "bsort_segmented", "bsort_backward_scatter",
+              "bsort_strerror", "bsort_device_status", "bsort_sort"):
+        assert n in names
+
+
+@pytest.mark.parametrize("name", declared_functions())
+def test_library_exports_declared_symbol(name):
+    assert hasattr(_lib.lib, name), f"{name} declared in bsort.h but not exported"
+    assert name in _lib.SYMBOLS
+
+
+def test_scratch_bytes():
+    sb = _lib.bsort_scratch_bytes
+    assert sb(3, 100, 1, 1, 0) == 0            # bad key width
+    assert sb(4, 100, 1, 1, 1 << 20) == 0      # unknown flag
+    base = sb(4, 1 << 20, 1, 0, 0)
+    with_idx = sb(4, 1 << 20, 1, 1, 0)
+    idx64 = sb(4, 1 << 20, 1, 1, _lib.IDX64)
+    assert base >= 4 * (1 << 20)               # the second key buffer
+    assert with_idx - base >= 4 * (1 << 20)    # a second index buffer
+    assert idx64 - with_idx >= 4 * (1 << 20)   # both uint32 halves in scratch
+    assert sb(4, 1 << 21, 1, 1, 0) > with_idx  # grows with n
+    assert sb(8, 1 << 20, 1, 1, 0) > with_idx  # and with the key width
+    # the no-finish mode needs work lists for many small segments
+    assert sb(4, 1 << 20, 1, 1, _lib.NO_FINISH) > with_idx
+    for kb in (1, 2, 4, 8):
+        assert sb(kb, 0, 1, 1, 0) > 0 and sb(kb, 1, 1, 1, 0) > 0
+
+
+def test_strerror():
+    assert _lib.strerror(_lib.OK) == "ok"
+    assert "scratch" in _lib.strerror(_lib.ESCRATCH)
+    assert "invalid" in _lib.strerror(_lib.EINVAL)
+    assert "gfx950" in _lib.strerror(_lib.ENODEV)
+    assert _lib.strerror(12345) == "unknown status"
+
+
+def test_validation_before_any_device_work():
+    """Every case below returns before the library queries a device."""
+    f = _lib.bsort_u32
+    fake = 1 << 40  # never dereferenced: validation fails first
+    # n = 0 is a no-op that succeeds, even with null pointers
+    assert f(None, 0, 0, None, None, 0, None) == _lib.OK
+    # unknown flag bits
+    assert f(fake, 10, 1 << 7, None, fake, 1 << 30, None) == _lib.EINVAL
+    # null keys or scratch with n > 0
+    assert f(None, 10, 0, None, fake, 1 << 30, None) == _lib.EINVAL
+    assert f(fake, 10, 0, None, None, 1 << 30, None) == _lib.EINVAL
+    # scratch too small
+    need = _lib.bsort_scratch_bytes(4, 1000, 1, 1, 0)
+    assert f(fake, 1000, 0, fake, fake, need - 1, None) == _lib.ESCRATCH
+    # 2^32 keys or more with uint32 indices
+    assert f(fake, 1 << 32, 0, fake, fake, 1 << 62, None) == _lib.ETOOBIG
+    # misaligned scratch
+    assert f(fake, 1000, 0, None, fake + 4, 1 << 30, None) == _lib.EINVAL
+    # generic entry point: bad key family or width
+    assert _lib.bsort_sort(fake, 7, 4, 10, 0, None, fake, 1 << 30, None) == _lib.EINVAL
+    assert _lib.bsort_sort(fake, 0, 3, 10, 0, None, fake, 1 << 30, None) == _lib.EINVAL
+    # segmented: offsets required; zero segments only with zero keys
+    seg = _lib.bsort_segmented
+    assert seg(fake, 0, 4, None, 3, 10, 0, None, fake, 1 << 30, None) == _lib.EINVAL
+    assert seg(fake, 0, 4, fake, 0, 10, 0, None, fake, 1 << 30, None) == _lib.EINVAL
+    assert seg(fake, 0, 4, fake, 0, 0, 0, None, fake, 1 << 30, None) == _lib.OK
+    # backward scatter: element width and flags
+    bs = _lib.bsort_backward_scatter
+    assert bs(fake, fake, 2, 3, 3, fake, 0, None) == _lib.EINVAL
+    assert bs(fake, fake, 2, 3, 4, fake, 1, None) == _lib.EINVAL
+    assert bs(None, None, 0, 3, 4, None, 0, None) == _lib.OK
+    assert bs(None, fake, 2, 3, 4, fake, 0, None) == _lib.EINVAL
+    # status read needs a scratch pointer
+    assert _lib.bsort_device_status(None, None) == _lib.EINVAL
+
+
+def test_torch_dtype_mapping():
+    import torch
+    from paper_2603_08929_amd import api
+    assert api.key_type(torch.float32) == (_lib.KEY_F, 4)
+    assert api.key_type(torch.bfloat16) == (_lib.KEY_F, 2)
+    assert api.key_type(torch.int8) == (_lib.KEY_I, 1)
+    assert api.key_type(torch.uint8) == (_lib.KEY_U, 1)
+    with pytest.raises(TypeError):
+        api.key_type(torch.complex64)
