@@ -116,10 +116,11 @@ int bsort_f64(double *keys, uint64_t n, uint32_t flags, void *indices, void *scr
  * a DEVICE array of num_segments+1 int64 with offsets[0] = 0,
  * non-decreasing, offsets[num_segments] = n.  Each segment is sorted as by
  * the single-array call (the same result, bit for bit), in one pass over
- * all of them.  Indices are local to each segment.  Offsets are read on the
- * device; values outside [0, n] or decreasing are clamped so that no access
- * leaves keys[0, n) (the result is then unspecified but memory-safe).
- * key_type is BSORT_KEY_U/I/F, key_bytes in {1,2,4,8}.
+ * all of them.  Indices are local to each segment.  Offsets are read and
+ * checked on the device: if offsets[0] != 0, offsets[num_segments] != n, or
+ * any offset is outside [0, n] or smaller than its predecessor, nothing is
+ * sorted (keys and indices are left as they were) and bsort_device_status
+ * reports bit 1.  key_type is BSORT_KEY_U/I/F, key_bytes in {1,2,4,8}.
  */
 int bsort_segmented(void *keys, int key_type, int key_bytes, const int64_t *offsets,
                     uint64_t num_segments, uint64_t n, uint32_t flags, void *indices,
@@ -154,8 +155,10 @@ int bsort_backward_scatter(const void *grad_sorted, const void *indices, uint64_
 const char *bsort_strerror(int status);
 
 /* Device status word written by the last call that used this scratch:
- * 0 = fine; bit 0 = a cross-tile wait gave up (result invalid).  Reads it
- * synchronously on `stream`.  Returns the word, or a negative status. */
+ * 0 = fine; bit 0 = a part handed to the in-LDS finish exceeded its capacity
+ * (an internal error: the result is invalid); bit 1 = the segment offsets
+ * failed the device-side check (nothing was sorted).  Reads
+ * it synchronously on `stream`.  Returns the word, or a negative status. */
 int bsort_device_status(const void *scratch, void *stream);
 
 /* ---- instrumentation (benchmarks and tests; not needed to sort) ---- */

@@ -1,0 +1,250 @@
+"""The workloads at their full sizes, sorted in the launch configuration the
+benchmark times (one call per array, keys + uint32 indices, or one
+segmented call for the batch).  The 64 Ki-key array is compared with the
+oracle element by element; at 2^26..2^28 keys the checks are properties
+that pin the result at any size -- ordered by the paper's order key,
+gather(input, idx) == keys, idx a permutation, equal keys in input order --
+plus outputs at sampled ranks that the oracle's quickselect computes one by
+one (key and source index, exactly)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2603_08929_amd import _lib
+from paper_2603_08929_amd import workloads as W
+from paper_2603_08929_amd.workloads import DTYPES
+from gpu_util import ENTRY, FAMILY, key_bytes, oracle_sort, stream, to_device
+
+pytestmark = pytest.mark.gpu
+
+MIN64 = -(1 << 63)
+
+
+def order_key(t: torch.Tensor, name: str) -> torch.Tensor:
+    """int64 tensor whose signed order is the paper's key order of the raw
+    patterns in t (the signed carrier of a w-bit dtype)."""
+    w, fam = DTYPES[name][0], DTYPES[name][1]
+    t = t.to(torch.int64)
+    if w == 64:
+        if fam == "U":
+            return t ^ MIN64
+        if fam == "I":
+            return t
+        return torch.where(t < 0, (~t) ^ MIN64, t)
+    mask = (1 << w) - 1
+    top = 1 << (w - 1)
+    u = t & mask
+    if fam == "U":
+        return u
+    if fam == "I":
+        return u ^ top
+    return torch.where((u & top) != 0, (~u) & mask, u | top)
+
+
+def check_properties(name, src, keys, idx, desc, seg_id=None, seg_start=None):
+    """src, keys: device tensors of raw patterns; idx: int64 device tensor
+    (segment-local when seg_id is given)."""
+    n = src.numel()
+    v = order_key(keys, name)
+    gidx = idx if seg_start is None else idx + seg_start[seg_id]
+    # gather(input, idx) == keys (bit patterns)
+    assert torch.equal(src[gidx], keys)
+    # idx is a permutation (of each segment)
+    assert bool((gidx >= 0).all()) and bool((gidx < n).all())
+    assert bool((torch.bincount(gidx, minlength=n) == 1).all())
+    if n < 2:
+        return
+    same_seg = torch.ones(n - 1, dtype=torch.bool, device=src.device)
+    if seg_id is not None:
+        same_seg = seg_id[1:] == seg_id[:-1]
+    ordered = v[1:] <= v[:-1] if desc else v[1:] >= v[:-1]
+    assert bool((ordered | ~same_seg).all()), "not ordered"
+    ties = (v[1:] == v[:-1]) & same_seg
+    assert bool((idx[1:][ties] > idx[:-1][ties]).all()), "equal keys out of input order"
+
+
+def sort_call(name, t, desc, idx=True):
+    n = t.numel()
+    fl = _lib.DESCENDING if desc else 0
+    ind = torch.empty(n, dtype=torch.int32, device="cuda") if idx else None
+    need = _lib.bsort_scratch_bytes(key_bytes(name), n, 1, int(idx), fl)
+    scratch = torch.empty(need, dtype=torch.uint8, device="cuda")
+    rc = getattr(_lib, ENTRY[name])(t.data_ptr(), n, fl,
+                                    ind.data_ptr() if idx else None,
+                                    scratch.data_ptr(), need, stream())
+    _lib.check(rc, ENTRY[name])
+    torch.cuda.synchronize()
+    assert _lib.bsort_device_status(scratch.data_ptr(), stream()) == 0
+    del scratch
+    if not idx:
+        return None
+    return ind.to(torch.int64) & 0xFFFFFFFF
+
+
+def sample_ranks(n, k, seed):
+    """The middle rank and k random ranks (the oracle's select costs a few
+    seconds per rank at these sizes)."""
+    rng = np.random.default_rng(seed)
+    return sorted(set([n // 2] + [int(j) for j in rng.integers(0, n, size=k)]))
+
+
+def check_samples(name, bits, keys_np, idx_np, desc, ranks):
+    w, _, raw, _ = DTYPES[name]
+    _, mode, mant = oracle.DTYPES[name]
+    u = bits.astype(np.uint64) if w == 64 else bits.astype(raw).astype(np.uint64)
+    for j in ranks:
+        k, i = oracle.select(u, w, mode, not desc, j, mant)
+        assert int(np.asarray(keys_np[j]).astype(np.uint64)) == k, f"key at rank {j}"
+        assert int(idx_np[j]) == i, f"index at rank {j}"
+
+
+def test_u32_64k_exact():
+    """64 Ki uint32 keys uniform over [0, 2^32), seed 0, ascending: keys and
+    indices element by element, default and plain (w full passes) modes."""
+    bits = W.uniform_bits("u32", 65536, 0)
+    rk, ri = oracle_sort("u32", bits, asc=True)
+    for flags in (0, _lib.PLAIN):
+        t = to_device(bits, "u32")
+        ind = torch.empty(65536, dtype=torch.int32, device="cuda")
+        need = _lib.bsort_scratch_bytes(4, 65536, 1, 1, flags)
+        scratch = torch.empty(need, dtype=torch.uint8, device="cuda")
+        _lib.check(_lib.bsort_u32(t.data_ptr(), 65536, flags, ind.data_ptr(),
+                                  scratch.data_ptr(), need, stream()), "bsort_u32")
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(t.cpu().numpy().view(np.uint32), rk)
+        np.testing.assert_array_equal(ind.cpu().numpy().view(np.uint32).astype(np.int64), ri)
+        # keys-only call: same keys
+        t = to_device(bits, "u32")
+        _lib.check(_lib.bsort_u32(t.data_ptr(), 65536, flags, None, scratch.data_ptr(), need,
+                                  stream()), "bsort_u32")
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(t.cpu().numpy().view(np.uint32), rk)
+
+
+N26 = 1 << 26
+
+
+def single_arrays():
+    return [("i32_uniform", "i32", lambda: W.uniform_bits("i32", N26, 0), False),
+            ("f32_normal_specials", "f32",
+             lambda: W.plant_specials(W.normal_bits("f32", N26, 0), "f32", 0.001, 1), False),
+            ("u32_dups16", "u32", lambda: W.heavy_duplicates_u32(N26, 0), False),
+            ("u32_sorted_asc", "u32", lambda: W.presorted_u32(N26, 0), False),
+            ("u32_sorted_desc", "u32", lambda: W.presorted_u32(N26, 0), True),
+            ("u32_reverse_asc", "u32", lambda: W.presorted_u32(N26, 0, reverse=True), False),
+            ("u32_reverse_desc", "u32", lambda: W.presorted_u32(N26, 0, reverse=True), True)]
+
+
+@pytest.mark.parametrize("case", single_arrays(), ids=lambda c: c[0])
+def test_single_arrays_2_26(case):
+    label, name, make, desc = case
+    print(f"full size {label}", flush=True)
+    bits = make()
+    src = to_device(bits, name)
+    t = src.clone()
+    idx = sort_call(name, t, desc)
+    check_properties(name, src, t, idx, desc)
+    check_samples(name, bits, t.cpu().numpy().view(DTYPES[name][2]), idx.cpu().numpy(), desc,
+                  sample_ranks(N26, 1, 7))
+
+
+def sweep_arrays():
+    N28, N27 = 1 << 28, 1 << 27
+    return [("u8", N28, lambda: W.uniform_bits("u8", N28, 0)),
+            ("i8", N28, lambda: W.uniform_bits("i8", N28, 0)),
+            ("i16", N28, lambda: W.uniform_bits("i16", N28, 0)),
+            ("f16", N28, lambda: W.normal_bits("f16", N28, 0)),
+            ("bf16", N28, lambda: W.normal_bits("bf16", N28, 0)),
+            ("u64", N27, lambda: W.uniform_bits("u64", N27, 0)),
+            ("i64", N27, lambda: W.uniform_bits("i64", N27, 0)),
+            ("f64", N27, lambda: W.normal_bits("f64", N27, 0))]
+
+
+@pytest.mark.parametrize("case", sweep_arrays(), ids=lambda c: c[0])
+def test_word_size_sweep(case):
+    name, n, make = case
+    print(f"full size {name} n={n}", flush=True)
+    bits = make()
+    src = to_device(bits, name)
+    for flags_desc in (False,):
+        t = src.clone()
+        idx = sort_call(name, t, flags_desc)
+        check_properties(name, src, t, idx, flags_desc)
+        check_samples(name, bits, t.cpu().numpy().view(DTYPES[name][2]), idx.cpu().numpy(),
+                      flags_desc, sample_ranks(n, 0, 8))
+        del t, idx
+
+
+@pytest.mark.parametrize("name", ["f32", "i32"])
+def test_batched_4096(name):
+    """4096 arrays with log-uniform lengths in [1, 2^20] in one segmented
+    call; every segment checked by properties, a few against the oracle."""
+    lengths = W.batched_lengths()
+    n = int(lengths.sum())
+    print(f"batched {name} n={n}", flush=True)
+    bits = W.normal_bits("f32", n, 0) if name == "f32" else W.uniform_bits("i32", n, 0)
+    offs = np.concatenate([[0], np.cumsum(lengths)])
+    src = to_device(bits, name)
+    t = src.clone()
+    offsets = torch.from_numpy(offs).cuda()
+    ind = torch.empty(n, dtype=torch.int32, device="cuda")
+    B = lengths.size
+    need = _lib.bsort_scratch_bytes(4, n, B, 1, 0)
+    scratch = torch.empty(need, dtype=torch.uint8, device="cuda")
+    rc = _lib.bsort_segmented(t.data_ptr(), FAMILY[DTYPES[name][1]], 4, offsets.data_ptr(), B,
+                              n, 0, ind.data_ptr(), scratch.data_ptr(), need, stream())
+    _lib.check(rc, "bsort_segmented")
+    torch.cuda.synchronize()
+    assert _lib.bsort_device_status(scratch.data_ptr(), stream()) == 0
+    del scratch
+    idx = ind.to(torch.int64) & 0xFFFFFFFF
+    lens = torch.from_numpy(lengths).cuda()
+    seg_id = torch.repeat_interleave(torch.arange(B, device="cuda"), lens)
+    seg_start = offsets[:-1]
+    check_properties(name, src, t, idx, False, seg_id=seg_id, seg_start=seg_start)
+    keys_np = t.cpu().numpy().view(DTYPES[name][2])
+    idx_np = idx.cpu().numpy()
+    picks = [int(np.argmax(lengths)), int(np.argmin(lengths))]
+    picks += [int(s) for s in np.random.default_rng(9).integers(0, B, size=6)]
+    for s in picks:
+        a, b = offs[s], offs[s + 1]
+        rk, ri = oracle_sort(name, bits[a:b], asc=True)
+        np.testing.assert_array_equal(keys_np[a:b], rk)
+        np.testing.assert_array_equal(idx_np[a:b], ri)
+
+
+@pytest.mark.parametrize("shape,dtype", [((1024, 65536), torch.float32),
+                                         ((4096, 16384), torch.float16)])
+def test_differentiable_sort_full(shape, dtype):
+    from paper_2603_08929_amd.autograd import sort_along
+    g = torch.Generator(device="cuda").manual_seed(0)
+    x = torch.randn(*shape, generator=g, device="cuda", dtype=torch.float32).to(dtype)
+    g3 = torch.Generator(device="cuda").manual_seed(3)
+    Wt = torch.randn(*shape, generator=g3, device="cuda", dtype=torch.float32).to(dtype)
+    xg = x.clone().requires_grad_(True)
+    v, idx = sort_along(xg)
+    (Wt * v).sum().backward()
+    # gradient: grad_x[r, idx[r, j]] = W[r, j], checked against torch's scatter
+    ref = torch.zeros_like(x).scatter_(-1, idx, Wt)
+    assert torch.equal(xg.grad, ref)
+    assert torch.equal(x.gather(-1, idx), v.detach())
+    # per-row order, stability, permutation
+    rows = shape[0]
+    vb = v.detach().view(torch.int16 if dtype == torch.float16 else torch.int32)
+    name = "f16" if dtype == torch.float16 else "f32"
+    okey = order_key(vb, name)
+    assert bool((okey[:, 1:] >= okey[:, :-1]).all())
+    ties = okey[:, 1:] == okey[:, :-1]
+    assert bool((idx[:, 1:][ties] > idx[:, :-1][ties]).all())
+    assert torch.equal(torch.sort(idx, dim=-1)[0],
+                       torch.arange(shape[1], device="cuda").expand(rows, -1))
+    # a few rows against the oracle, exactly
+    xb = x.view(torch.int16 if dtype == torch.float16 else torch.int32).cpu().numpy()
+    vbn = vb.cpu().numpy()
+    idn = idx.cpu().numpy()
+    raw = DTYPES[name][2]
+    for r in (0, rows // 2, rows - 1):
+        rk, ri = oracle_sort(name, xb[r].view(raw), asc=True)
+        np.testing.assert_array_equal(vbn[r].view(raw), rk)
+        np.testing.assert_array_equal(idn[r], ri)
