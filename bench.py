@@ -16,11 +16,25 @@ timed steps (Gkeys/s).
 are bracketed by hipEvents on the library's stream during the timed region;
 algorithmic bytes per launch = live keys of that level x (read + write of
 key and index: 2 * (4 + 4) bytes; level 0 reads no index: 4 + 4 + 4).
+`traffic` is the HBM bytes per level launch that the FETCH_SIZE and
+WRITE_SIZE counters measured for this kernel (committed summary under
+profiles/, scaled by the same counters' reading of a plain 1 GiB copy), or
+null if the kernel sources changed since.
 `cpu_baseline` times the oracle (single thread) on a prefix sample.
+
+The other workloads are reported beside the headline (`extras`, skipped
+with --no-extras): the word-size sweep (8-, 16- and 64-bit keys at 2^28 /
+2^27, default and plain w-pass mode), the 4096-array batch in one segmented
+call vs one call per array (outputs compared bit for bit), and the backward
+scatter of the differentiable sort.
+
+`--summarize-pmc FETCH_CSV WRITE_CSV` turns the counter files of two
+rocprofv3 --pmc runs of this script into the traffic summary.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -34,6 +48,24 @@ METRIC = "Gkeys/s and achieved HBM GB/s per dtype; batched vs per-array, bit-exa
 HBM_PEAK_GBS = 8000.0
 N = 1 << 26
 MAX_LEVELS = 66
+LEVEL_KERNEL = "level_kernel<unsigned int, true"
+CALIB_KERNEL = "bitwise_not"
+CALIB_ELEMS = 1 << 28  # int32: 1 GiB read + 1 GiB written
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "level_kernel_u32_idx_2p26_traffic.txt")
+SOURCES = [os.path.join(ROOT, "paper_2603_08929_amd", "csrc", f)
+           for f in ("bsort_kernels.hpp", "bsort_api.hip")]
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    for p in SOURCES:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def workload_arrays():
@@ -53,21 +85,293 @@ def workload_arrays():
             ("u32_reverse_desc", "u32", rev, True)]
 
 
+# ----------------------------------------------------------- counter summary
+
+def summarize_pmc(fetch_csv: str, write_csv: str) -> str:
+    """Per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of the level kernel and of
+    the calibration copy -> HBM bytes per level launch."""
+    import csv
+
+    def load(path, counter):
+        per = {}
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != counter:
+                continue
+            name = r["Kernel_Name"]
+            key = ("level" if LEVEL_KERNEL in name else
+                   "calib" if CALIB_KERNEL in name else None)
+            if key is None:
+                continue
+            per.setdefault(key, []).append(float(r["Counter_Value"]) * 1024.0)
+        return per
+
+    fe = load(fetch_csv, "FETCH_SIZE")
+    wr = load(write_csv, "WRITE_SIZE")
+    true_bytes = 4.0 * CALIB_ELEMS
+    f_scale = true_bytes / (sum(fe["calib"]) / len(fe["calib"]))
+    w_scale = true_bytes / (sum(wr["calib"]) / len(wr["calib"]))
+    nl = len(fe["level"])
+    assert nl == len(wr["level"]), "level launches differ between the passes"
+    fetch = sum(fe["level"]) / nl * f_scale
+    write = sum(wr["level"]) / nl * w_scale
+    lines = [
+        f"source_sha256_16: {source_hash()}",
+        f"level_launches: {nl}",
+        f"calibration: {CALIB_KERNEL} over {CALIB_ELEMS} int32 "
+        f"({true_bytes / 2**30:.0f} GiB read + {true_bytes / 2**30:.0f} GiB written)",
+        f"calib_fetch_counter_bytes: {sum(fe['calib']) / len(fe['calib']):.0f}",
+        f"calib_write_counter_bytes: {sum(wr['calib']) / len(wr['calib']):.0f}",
+        f"fetch_scale: {f_scale:.4f}",
+        f"write_scale: {w_scale:.4f}",
+        f"level_fetch_counter_bytes_per_launch: {sum(fe['level']) / nl:.0f}",
+        f"level_write_counter_bytes_per_launch: {sum(wr['level']) / nl:.0f}",
+        f"level_fetch_bytes_per_launch: {fetch:.0f}",
+        f"level_write_bytes_per_launch: {write:.0f}",
+        f"level_traffic_bytes_per_launch: {fetch + write:.0f}",
+    ]
+    return "\n".join(lines) + "\n"
+
+
+def load_traffic():
+    """HBM bytes per level launch from the committed counter summary, or
+    None if it is missing or was taken on other kernel sources."""
+    try:
+        kv = {}
+        for line in open(TRAFFIC_FILE):
+            if ":" in line and not line.startswith(("#", " ")):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+        if kv.get("source_sha256_16") != source_hash():
+            return None
+        return float(kv["level_traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+# ------------------------------------------------------------------ helpers
+
+def level_stats(lib, scratch, stream):
+    import ctypes
+    import numpy as np
+    buf = np.zeros(MAX_LEVELS, dtype=np.uint64)
+    fk = ctypes.c_uint64(0)
+    ck = ctypes.c_uint64(0)
+    lib.bsort_level_stats(scratch.data_ptr(), stream, buf.ctypes.data, None, None, MAX_LEVELS,
+                          ctypes.byref(fk), ctypes.byref(ck))
+    return buf, int(fk.value), int(ck.value)
+
+
+def alg_bytes(live, finish_keys, K, I):
+    """Algorithmic HBM bytes of one sort: every executed level reads and
+    writes its live keys and indices (level 0 reads no index); the LDS
+    finish reads and writes its keys once for all remaining bits."""
+    tot = 0.0
+    for lvl, nl in enumerate(live):
+        tot += float(nl) * ((2 * K + I) if lvl == 0 else 2 * (K + I))
+    return tot + finish_keys * 2.0 * (K + I)
+
+
+def timed(fn, reps, torch):
+    """Median milliseconds of fn() over reps runs, hipEvents on the current
+    stream (the one the library is given)."""
+    ts = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
+# ------------------------------------------------------------------- extras
+
+def extras_word_size(lib, torch, np, dev, stream):
+    from paper_2603_08929_amd import workloads as W
+    entry = {"u8": lib.bsort_u8, "i8": lib.bsort_i8, "i16": lib.bsort_i16, "f16": lib.bsort_f16,
+             "bf16": lib.bsort_f16, "u64": lib.bsort_u64, "i64": lib.bsort_i64,
+             "f64": lib.bsort_f64}
+    sint = {1: np.int8, 2: np.int16, 8: np.int64}
+    N28, N27 = 1 << 28, 1 << 27
+    cases = [("u8", N28, "uniform"), ("i8", N28, "uniform"), ("i16", N28, "uniform"),
+             ("f16", N28, "normal"), ("bf16", N28, "normal"), ("u64", N27, "uniform"),
+             ("i64", N27, "uniform"), ("f64", N27, "normal")]
+    out = []
+    for name, n, dist in cases:
+        log(f"word-size sweep {name} n={n}")
+        w = W.DTYPES[name][0]
+        K, I = w // 8, 4
+        bits = W.uniform_bits(name, n, 0) if dist == "uniform" else W.normal_bits(name, n, 0)
+        src = torch.from_numpy(bits.view(sint[K])).to(dev)
+        del bits
+        work = torch.empty_like(src)
+        idx = torch.empty(n, dtype=torch.int32, device=dev)
+        need = max(lib.bsort_scratch_bytes(K, n, 1, 1, fl) for fl in (0, lib.PLAIN))
+        scratch = torch.empty(need, dtype=torch.uint8, device=dev)
+
+        def run(flags):
+            lib.check(entry[name](work.data_ptr(), n, flags, idx.data_ptr(), scratch.data_ptr(),
+                                  need, stream), name)
+
+        def once(flags):
+            work.copy_(src)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            run(flags)
+            e1.record()
+            e1.synchronize()
+            return e0.elapsed_time(e1)
+
+        once(0)
+        ms = sorted(once(0) for _ in range(3))[1]
+        live, fk, _ = level_stats(lib, scratch, stream)
+        ab = alg_bytes(live, fk, K, I)
+        # plain mode: exactly w full passes; per-pass time from the level events
+        lib.check(lib.bsort_timing_arm(w), "arm")
+        ms_plain = once(lib.PLAIN)
+        lv_ms = np.zeros(w, dtype=np.float32)
+        lv = np.zeros(w, dtype=np.int32)
+        got = lib.bsort_timing_read(lv_ms.ctypes.data, lv.ctypes.data, w)
+        lib.bsort_timing_disarm()
+        per_pass = float(np.median(lv_ms[1:got])) if got > 1 else float("nan")
+        pass_bytes = 2.0 * n * (K + I)
+        out.append({
+            "dtype": name, "n": n, "ms": round(ms, 3), "gkeys_s": round(n / ms / 1e6, 3),
+            "levels_executed": int((live > 0).sum()), "finish_keys": fk,
+            "alg_GBps": round(ab / ms / 1e6, 1), "alg_frac": round(ab / ms / 1e6 / HBM_PEAK_GBS, 4),
+            "plain_ms": round(ms_plain, 3), "plain_levels": int(got),
+            "plain_pass_us": round(per_pass * 1e3, 1),
+            "plain_pass_frac": round(pass_bytes / (per_pass / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+        })
+        del src, work, idx, scratch
+        torch.cuda.empty_cache()
+    return out
+
+
+def extras_batched(lib, torch, np, dev, stream):
+    from paper_2603_08929_amd import workloads as W
+    lengths = W.batched_lengths()
+    n = int(lengths.sum())
+    B = lengths.size
+    offs = np.concatenate([[0], np.cumsum(lengths)]).astype(np.int64)
+    offsets = torch.from_numpy(offs).to(dev)
+    out = []
+    for name in ("f32", "i32"):
+        log(f"batched {name} n={n} arrays={B}")
+        kt = lib.KEY_F if name == "f32" else lib.KEY_I
+        typed = lib.bsort_f32 if name == "f32" else lib.bsort_i32
+        bits = W.normal_bits("f32", n, 0) if name == "f32" else W.uniform_bits("i32", n, 0)
+        src = torch.from_numpy(bits.view(np.int32)).to(dev)
+        del bits
+        work = torch.empty_like(src)
+        idx = torch.empty(n, dtype=torch.int32, device=dev)
+        need = lib.bsort_scratch_bytes(4, n, B, 1, 0)
+        need1 = lib.bsort_scratch_bytes(4, int(lengths.max()), 1, 1, 0)
+        scratch = torch.empty(max(need, need1), dtype=torch.uint8, device=dev)
+        kp, ip, sp = work.data_ptr(), idx.data_ptr(), scratch.data_ptr()
+
+        def batched():
+            lib.check(lib.bsort_segmented(kp, kt, 4, offsets.data_ptr(), B, n, 0, ip, sp,
+                                          scratch.numel(), stream), "segmented")
+
+        def per_array():
+            for s in range(B):
+                a = int(offs[s])
+                lib.check(typed(kp + 4 * a, int(lengths[s]), 0, ip + 4 * a, sp, need1, stream),
+                          "per-array")
+
+        def once(fn):
+            work.copy_(src)
+            return timed(fn, 1, torch)
+
+        once(batched)
+        t_b = sorted(once(batched) for _ in range(3))[1]
+        live, fk, _ = level_stats(lib, scratch, stream)
+        ab = alg_bytes(live, fk, 4, 4)
+        kb, ib = work.clone(), idx.clone()
+        once(per_array)
+        t_p = once(per_array)
+        same = bool(torch.equal(kb, work) and torch.equal(ib, idx))
+        out.append({"dtype": name, "arrays": B, "keys": n,
+                    "batched_ms": round(t_b, 3), "batched_gkeys_s": round(n / t_b / 1e6, 3),
+                    "batched_alg_GBps": round(ab / t_b / 1e6, 1),
+                    "per_array_ms": round(t_p, 3), "per_array_gkeys_s": round(n / t_p / 1e6, 3),
+                    "speedup": round(t_p / t_b, 2), "bit_exact_equal": same,
+                    "levels_executed": int((live > 0).sum()), "finish_keys": fk})
+        del src, work, idx, scratch, kb, ib
+        torch.cuda.empty_cache()
+    return out
+
+
+def extras_backward(lib, torch, np, dev, stream):
+    from paper_2603_08929_amd.autograd import sort_along
+    out = []
+    for shape, dt in (((1024, 65536), torch.float32), ((4096, 16384), torch.float16)):
+        log(f"differentiable sort {tuple(shape)} {dt}")
+        g = torch.Generator(device=dev).manual_seed(0)
+        x = torch.randn(*shape, generator=g, device=dev, dtype=torch.float32).to(dt)
+        g3 = torch.Generator(device=dev).manual_seed(3)
+        Wt = torch.randn(*shape, generator=g3, device=dev, dtype=torch.float32).to(dt)
+        xg = x.clone().requires_grad_(True)
+
+        def fwd():
+            return sort_along(xg)
+
+        v, idx = fwd()
+        t_f = timed(fwd, 3, torch)
+        gin = torch.empty_like(x)
+        rows, cols = shape
+        eb = x.element_size()
+
+        def bwd():
+            lib.check(lib.bsort_backward_scatter(Wt.data_ptr(), idx.data_ptr(), rows, cols, eb,
+                                                 gin.data_ptr(), lib.IDX64, stream), "bwd")
+
+        bwd()
+        t_b = timed(bwd, 5, torch)
+        loss = (Wt * v).sum()
+        t0 = time.perf_counter()
+        loss.backward()
+        torch.cuda.synchronize(dev)
+        t_ab = (time.perf_counter() - t0) * 1e3
+        ok = bool(torch.equal(xg.grad, gin))
+        bb = (2 * eb + 8) * rows * cols
+        out.append({"shape": list(shape), "dtype": str(dt).replace("torch.", ""),
+                    "forward_ms": round(t_f, 3),
+                    "forward_gkeys_s": round(rows * cols / t_f / 1e6, 3),
+                    "backward_scatter_ms": round(t_b, 4),
+                    "backward_GBps": round(bb / t_b / 1e6, 1),
+                    "backward_frac": round(bb / t_b / 1e6 / HBM_PEAK_GBS, 4),
+                    "autograd_backward_wall_ms": round(t_ab, 3), "grad_equal": ok})
+        del x, Wt, xg, v, idx, gin
+        torch.cuda.empty_cache()
+    return out
+
+
+# --------------------------------------------------------------------- main
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=1 << 23,
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=1 << 25,
                     help="keys per array in the oracle's timed sample")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
     args = ap.parse_args()
+    if args.summarize_pmc:
+        sys.stdout.write(summarize_pmc(*args.summarize_pmc))
+        return 0
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the sort of one "
                           "array is a single-GPU workload here (--gpus 1)"}))
         return 2
-
-    import ctypes
 
     import numpy as np
     import torch
@@ -77,8 +381,16 @@ def main() -> int:
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream(dev).cuda_stream
+    log("generating inputs")
     arrays = workload_arrays()
     entry = {"i32": _lib.bsort_i32, "f32": _lib.bsort_f32, "u32": _lib.bsort_u32}
+
+    # counter calibration: one plain elementwise pass of known size
+    a = torch.zeros(CALIB_ELEMS, dtype=torch.int32, device=dev)
+    b = torch.empty_like(a)
+    torch.bitwise_not(a, out=b)
+    torch.cuda.synchronize(dev)
+    del a, b
 
     pristine = [torch.from_numpy(a[2].view(np.int32)).to(dev) for a in arrays]
     idx = [torch.empty(N, dtype=torch.int32, device=dev) for _ in arrays]
@@ -93,28 +405,25 @@ def main() -> int:
         _lib.check(rc, "bsort")
 
     # work statistics per array (deterministic: identical in every step)
+    log("characterising the arrays")
     live = np.zeros((len(arrays), MAX_LEVELS), dtype=np.uint64)
     per_array = []
     for j in range(len(arrays)):
         k = pristine[j].clone()
         sort_one(j, k)
-        fk = ctypes.c_uint64(0)
-        ck = ctypes.c_uint64(0)
-        buf = np.zeros(MAX_LEVELS, dtype=np.uint64)
-        _lib.bsort_level_stats(scratch.data_ptr(), stream, buf.ctypes.data, None, None,
-                               MAX_LEVELS, ctypes.byref(fk), ctypes.byref(ck))
+        buf, fk, ck = level_stats(_lib, scratch, stream)
         st = _lib.bsort_device_status(scratch.data_ptr(), stream)
         if st != 0:
             raise RuntimeError(f"device status {st} on {arrays[j][0]}")
         live[j] = buf
-        per_array.append({"array": arrays[j][0],
-                          "global_levels": int((buf > 0).sum()),
-                          "finish_keys": int(fk.value), "copy_keys": int(ck.value)})
+        per_array.append({"array": arrays[j][0], "global_levels": int((buf > 0).sum()),
+                          "finish_keys": fk, "copy_keys": ck})
         del k
 
     steps, warm = args.steps, args.warmup
     work = [[p.clone() for p in pristine] for _ in range(steps + warm)]
     torch.cuda.synchronize(dev)
+    log("warmup")
     for s in range(warm):
         for j in range(len(arrays)):
             sort_one(j, work[s][j])
@@ -122,6 +431,7 @@ def main() -> int:
 
     cap = steps * len(arrays) * 32
     _lib.check(_lib.bsort_timing_arm(cap), "bsort_timing_arm")
+    log("timed steps")
     torch.cuda.synchronize(dev)
     t0 = time.perf_counter()
     for s in range(warm, warm + steps):
@@ -135,6 +445,7 @@ def main() -> int:
     _lib.bsort_timing_disarm()
     if got != cap:
         raise RuntimeError(f"timing: {got} of {cap} level launches recorded")
+    del work
 
     # algorithmic bytes of each timed level launch (launch order: step, array, level)
     K, I = 4, 4
@@ -151,11 +462,21 @@ def main() -> int:
     elapsed = t1 - t0
     keys_total = steps * len(arrays) * N
     value = keys_total / elapsed / 1e9
+    traffic = load_traffic()
+
+    extras = None
+    if not args.no_extras:
+        del pristine, idx, scratch
+        torch.cuda.empty_cache()
+        extras = {"word_size_sweep": extras_word_size(_lib, torch, np, dev, stream),
+                  "batched_vs_per_array": extras_batched(_lib, torch, np, dev, stream),
+                  "differentiable_sort": extras_backward(_lib, torch, np, dev, stream)}
 
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
         m = min(args.cpu_sample, N)
+        log(f"oracle on {m} keys per array")
         tot = 0.0
         for (label, name, bits, desc) in arrays:
             sample = bits[:m].astype(np.uint64)
@@ -186,14 +507,17 @@ def main() -> int:
                    "keys_per_array": N, "arrays_per_step": len(arrays)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None,
+                     "traffic": None if traffic is None else round(traffic),
+                     "traffic_unit": "HBM bytes per level launch",
+                     "alg_bytes_per_launch": round(float(alg.mean())),
                      "kernel": "level_kernel<u32, idx>",
                      "launches": int(cap), "avg_launch_us": round(level_time_s / cap * 1e6, 3),
                      "level_time_share": round(level_time_s / elapsed, 4)},
         "cpu_baseline": cpu,
         "per_array": per_array,
+        "extras": extras,
     }
-    print(json.dumps(out))
+    print(json.dumps(out), flush=True)
     return 0
 
 

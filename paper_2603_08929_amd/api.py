@@ -101,13 +101,17 @@ def segmented_sort_(keys: torch.Tensor, offsets: torch.Tensor, descending: bool 
     return idx
 
 
-def backward_scatter(grad_sorted: torch.Tensor, indices: torch.Tensor) -> torch.Tensor:
-    """grad_in[r, idx[r, j]] = grad_sorted[r, j] along the last dim."""
+def backward_scatter(grad_sorted: torch.Tensor, indices: torch.Tensor,
+                     zero_fill: bool = True) -> torch.Tensor:
+    """grad_in[r, idx[r, j]] = grad_sorted[r, j] along the last dim.  With
+    zero_fill=False the output is not cleared first: only for indices whose
+    rows are permutations (as a sort returns them), which write every
+    element exactly once."""
     g = grad_sorted.contiguous()
     ix = indices.contiguous()
     cols = g.shape[-1] if g.dim() else 1
     rows = g.numel() // cols if cols else 0
-    out = torch.zeros_like(g)
+    out = torch.zeros_like(g) if zero_fill else torch.empty_like(g)
     if ix.dtype == torch.int64:
         fl = IDX64
     elif ix.dtype == torch.int32:

@@ -40,7 +40,7 @@ class BSortFunction(torch.autograd.Function):
         (idx,) = ctx.saved_tensors
         d = ctx.dim
         g = grad_values.movedim(d, -1).contiguous()
-        gx = api.backward_scatter(g, idx)
+        gx = api.backward_scatter(g, idx, zero_fill=False)  # idx rows are permutations
         return gx.movedim(-1, d), None, None
 
 

@@ -123,7 +123,8 @@ size_t up256(size_t x) { return (x + 255) & ~(size_t)255; }
 // every parent yields at most two finish entries per level; copy entries
 // hold more than T keys each.
 struct Layout {
-  size_t hdr, cnts, segs[2], recs[2], acc[2], tmap[2], fin, cpy, keys1, idx0, idx1, total;
+  size_t hdr, cnts, segs[2], recs[2], acc[2], split[2], tmap[2], fin, cpy, keys1, idx0, idx1,
+      total;
   uint64_t smax, tmax, fmax, cmax;
 };
 
@@ -147,7 +148,8 @@ bool make_layout(int key_bytes, uint64_t n, uint64_t B, bool with_idx, uint32_t 
   L->cnts = off; off = up256(off + 4 * (3 * L->tmax) * 4);
   for (int i = 0; i < 2; ++i) { L->segs[i] = off; off = up256(off + L->smax * sizeof(Seg)); }
   for (int i = 0; i < 2; ++i) { L->recs[i] = off; off = up256(off + L->smax * sizeof(Seg)); }
-  for (int i = 0; i < 2; ++i) { L->acc[i] = off; off = up256(off + L->smax * sizeof(Acc)); }
+  for (int i = 0; i < 2; ++i) { L->acc[i] = off; off = up256(off + L->tmax * sizeof(AccRep)); }
+  for (int i = 0; i < 2; ++i) { L->split[i] = off; off = up256(off + L->smax * 8); }
   for (int i = 0; i < 2; ++i) { L->tmap[i] = off; off = up256(off + L->tmax * sizeof(Seg)); }
   L->fin = off; off = up256(off + L->fmax * sizeof(Seg));
   L->cpy = off; off = up256(off + L->cmax * sizeof(Seg));
@@ -191,8 +193,10 @@ int launch_all(KT *keys, uint64_t n, const int64_t *offsets, uint64_t B, int mod
                   reinterpret_cast<Seg *>(scr + L.segs[1])};
   Seg *recs[2] = {reinterpret_cast<Seg *>(scr + L.recs[0]),
                   reinterpret_cast<Seg *>(scr + L.recs[1])};
-  Acc *acc[2] = {reinterpret_cast<Acc *>(scr + L.acc[0]),
-                 reinterpret_cast<Acc *>(scr + L.acc[1])};
+  AccRep *acc[2] = {reinterpret_cast<AccRep *>(scr + L.acc[0]),
+                    reinterpret_cast<AccRep *>(scr + L.acc[1])};
+  uint64_t *split[2] = {reinterpret_cast<uint64_t *>(scr + L.split[0]),
+                        reinterpret_cast<uint64_t *>(scr + L.split[1])};
   Seg *tmap[2] = {reinterpret_cast<Seg *>(scr + L.tmap[0]),
                   reinterpret_cast<Seg *>(scr + L.tmap[1])};
   Seg *fin = reinterpret_cast<Seg *>(scr + L.fin);
@@ -228,6 +232,7 @@ int launch_all(KT *keys, uint64_t n, const int64_t *offsets, uint64_t B, int mod
   sa.l = la;
   sa.l.live_next = segs[0];
   sa.l.acc_next = acc[0];
+  sa.l.split_next = split[0];
   sa.l.rec_next = recs[0];
   sa.l.next_level = 0;
   sa.offsets = offsets;
@@ -245,7 +250,11 @@ int launch_all(KT *keys, uint64_t n, const int64_t *offsets, uint64_t B, int mod
   auto ck = count_kernel<KT, TU::LB, TU::LIPT>;
   static const int occ_count = occupancy(ck, TU::LB);
   const uint32_t cgrid = clamp_grid(L.tmax, (uint64_t)cus * occ_count);
-  for (int lvl = 0; lvl < w; ++lvl) {
+  // A single array that fits the LDS finish never has a live segment: the
+  // seed hands it straight to the finish, so the level passes and the copy
+  // would all find empty lists.
+  const int levels = (!offsets && !no_finish && n <= TU::TFIN) ? 0 : w;
+  for (int lvl = 0; lvl < levels; ++lvl) {
     CountArgs<KT> ca;
     ca.keys = kbuf[lvl & 1];
     ca.live = segs[lvl & 1];
@@ -267,6 +276,7 @@ int launch_all(KT *keys, uint64_t n, const int64_t *offsets, uint64_t B, int mod
     a.idx_out = ibuf[(lvl + 1) & 1];
     a.tiles = tmap[lvl & 1];
     a.acc = acc[lvl & 1];
+    a.split = split[lvl & 1];
     a.hdr = hdr;
     a.tcnt_in = tcnt[lvl & 1];
     a.scnt_in = scnt[lvl & 1];
@@ -288,10 +298,12 @@ int launch_all(KT *keys, uint64_t n, const int64_t *offsets, uint64_t B, int mod
     pa.l = la;
     pa.l.live_next = segs[(lvl + 1) & 1];
     pa.l.acc_next = acc[(lvl + 1) & 1];
+    pa.l.split_next = split[(lvl + 1) & 1];
     pa.l.rec_next = recs[(lvl + 1) & 1];
     pa.l.next_level = lvl + 1;
     pa.live = segs[lvl & 1];
     pa.acc = acc[lvl & 1];
+    pa.split = split[lvl & 1];
     pa.zero_a = tcnt[lvl & 1];  // read by this level, filled by the next one
     pa.zero_b = scnt[lvl & 1];
     pa.zero_n = cn;
@@ -314,8 +326,9 @@ int launch_all(KT *keys, uint64_t n, const int64_t *offsets, uint64_t B, int mod
   ca.list = cpy;
   ca.hdr = hdr;
   ca.idx64 = idx64;
-  hipLaunchKernelGGL((copy_kernel<KT, IDX>), dim3(clamp_grid(cus * 4, cap)), dim3(256), 0, st,
-                     ca);
+  if (levels > 0)
+    hipLaunchKernelGGL((copy_kernel<KT, IDX>), dim3(clamp_grid(cus * 4, cap)), dim3(256), 0, st,
+                       ca);
 
   FinishArgs<KT> fa;
   fa.keys_buf[0] = kbuf[0];

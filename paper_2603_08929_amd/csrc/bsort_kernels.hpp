@@ -58,21 +58,20 @@ struct Seg {
 static_assert(sizeof(Seg) == 32, "Seg layout");
 
 // Per live segment: AND/OR of the keys that went to the front (lo) and back
-// (hi) child, and the split (number of front keys), written by the level.
-// The AND/OR words are replicated, one 128-byte line per replica, and a tile
-// updates replica (tile id mod ACC_REPL): with a single copy every tile of a
-// big segment would contend for the same line.
+// (hi) child, written by the level's tiles, and the split (number of front
+// keys, one word per segment slot).  The AND/OR words are replicated (with a
+// single copy every tile of a big segment would contend for the same line):
+// a segment of nt tiles keeps R = acc_repl(len) replicas, tile j updating
+// replica j mod R, and replica r lives at entry tile0 + ACC_STRIDE * r of the
+// level's per-tile array.  Since ACC_STRIDE * (R - 1) < nt, segments never
+// share entries, and the replicas of one segment sit on distinct 128-byte
+// lines.  The array is sized by tiles, not by segments x ACC_REPL.
 constexpr int ACC_REPL = 16;
+constexpr uint32_t ACC_STRIDE = 4;
 struct AccRep {
   uint64_t and_lo, or_lo, and_hi, or_hi;
-  uint64_t pad_[12];
 };
-struct Acc {
-  AccRep r[ACC_REPL];
-  uint64_t split;
-  uint64_t pad_[15];
-};
-static_assert(sizeof(AccRep) == 128 && sizeof(Acc) % 128 == 0, "Acc layout");
+static_assert(sizeof(AccRep) * ACC_STRIDE == 128, "AccRep layout");
 
 // Work-list counters, zeroed at the start of every call.
 struct Header {
@@ -291,7 +290,8 @@ constexpr int KIND_NONE = 0, KIND_LIVE = 1, KIND_FINISH = 2, KIND_COPY = 3;
 struct ListArgs {
   Header *hdr;
   Seg *live_next;       // level (lvl+1) live list, in tile order
-  Acc *acc_next;
+  AccRep *acc_next;     // per-tile AND/OR replicas of level (lvl+1)
+  uint64_t *split_next;  // per-slot split of level (lvl+1)
   Seg *rec_next;        // level (lvl+1) segments the count pass must count
   Seg *fin;
   Seg *cpy;
@@ -380,15 +380,15 @@ __device__ void emit_children(const ListArgs &a, Child (&ch)[2]) {
       s.cbase = ch[c].cbase == CBASE_OWN ? a.recount + s.tile0 : ch[c].cbase;
       s.slot = slot;
       a.live_next[slot] = s;
-      Acc *z = &a.acc_next[slot];
       const uint32_t nr = acc_repl(ch[c].len, a.tile);
       for (uint32_t k = 0; k < nr; ++k) {
-        z->r[k].and_lo = ~0ull;
-        z->r[k].or_lo = 0;
-        z->r[k].and_hi = ~0ull;
-        z->r[k].or_hi = 0;
+        AccRep *z = &a.acc_next[s.tile0 + ACC_STRIDE * k];
+        z->and_lo = ~0ull;
+        z->or_lo = 0;
+        z->and_hi = ~0ull;
+        z->or_hi = 0;
       }
-      z->split = 0;
+      a.split_next[slot] = 0;
       pos += (1ull << 32) | ch[c].tiles;
       if (ch[c].cbase == CBASE_OWN) {
         // to be counted on its bit before the level; .slot holds the
@@ -462,7 +462,8 @@ __global__ void seed_kernel(SeedArgs a) {
 struct PlanArgs {
   ListArgs l;
   const Seg *live;
-  const Acc *acc;
+  const AccRep *acc;
+  const uint64_t *split;
   uint32_t *zero_a;  // count arrays the next level accumulates into
   uint32_t *zero_b;
   uint64_t zero_n;
@@ -490,17 +491,17 @@ __global__ void plan_kernel(PlanArgs a) {
     ch[0].cbase = ch[1].cbase = 0;
     if (q < S) {
       const Seg p = a.live[q];
-      const Acc *acp = &a.acc[q];
       uint64_t and_lo = ~0ull, or_lo = 0, and_hi = ~0ull, or_hi = 0;
       const uint32_t nr = acc_repl(p.len, a.l.tile);
       for (uint32_t k = 0; k < nr; ++k) {
-        and_lo &= acp->r[k].and_lo;
-        or_lo |= acp->r[k].or_lo;
-        and_hi &= acp->r[k].and_hi;
-        or_hi |= acp->r[k].or_hi;
+        const AccRep *acp = &a.acc[p.tile0 + ACC_STRIDE * k];
+        and_lo &= acp->and_lo;
+        or_lo |= acp->or_lo;
+        and_hi &= acp->and_hi;
+        or_hi |= acp->or_hi;
       }
       const int bit = (int)(p.meta & BIT_MASK);
-      const uint64_t F = acp->split;
+      const uint64_t F = a.split[q];
       const uint32_t nt_p = (uint32_t)((p.len + a.l.tile - 1) / a.l.tile);
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
@@ -556,7 +557,8 @@ struct LevelArgs {
   const uint32_t *idx_in;
   uint32_t *idx_out;
   const Seg *tiles;   // per-tile descriptor copies (slot in .slot)
-  Acc *acc;
+  AccRep *acc;        // per-tile AND/OR replicas
+  uint64_t *split;    // per-slot split
   Header *hdr;
   const uint32_t *tcnt_in;  // this level: front keys per tile
   const uint32_t *scnt_in;  //   ... and per group of 64 tiles
@@ -626,7 +628,8 @@ __device__ __forceinline__ void issue_loads(const LevelArgs<KT> &a, const TileIn
     if (IDX) r.ix[i] = iota ? (uint32_t)(ti.lo + q) : buf_load<uint32_t>(ir, o * 4u);
   }
   if (tid == 0) {
-    const AccRep *ac = &a.acc[ti.slot].r[ti.t % acc_repl(ti.len, (uint32_t)(BLOCK * IPT))];
+    const AccRep *ac =
+        &a.acc[ti.tile0 + ACC_STRIDE * (ti.j % acc_repl(ti.len, (uint32_t)(BLOCK * IPT)))];
     r.acw[0] = ac->and_lo;
     r.acw[1] = ac->or_lo;
     r.acw[2] = ac->and_hi;
@@ -717,7 +720,7 @@ __device__ __forceinline__ void level_tile(const LevelArgs<KT> &a, const TileInf
     // atomic whose value the (even stale) read already absorbs is skipped:
     // big segments would otherwise send every tile's atomics to the same
     // four words.
-    AccRep *ac = &a.acc[ti.slot].r[ti.t % acc_repl(ti.len, (uint32_t)TILE)];
+    AccRep *ac = &a.acc[ti.tile0 + ACC_STRIDE * (ti.j % acc_repl(ti.len, (uint32_t)TILE))];
     const uint64_t al = sh.red[0], ol = sh.red[1], ah = sh.red[2], oh = sh.red[3];
     sh.red[0] = ~0ull;
     sh.red[1] = 0;
@@ -727,7 +730,7 @@ __device__ __forceinline__ void level_tile(const LevelArgs<KT> &a, const TileInf
     if ((r.acw[1] | ol) != r.acw[1]) atomic_or_u64(&ac->or_lo, ol);
     if ((r.acw[2] & ah) != r.acw[2]) atomic_and_u64(&ac->and_hi, ah);
     if ((r.acw[3] | oh) != r.acw[3]) atomic_or_u64(&ac->or_hi, oh);
-    if (ti.lo + cnt == ti.len) a.acc[ti.slot].split = P1 + c1;
+    if (ti.lo + cnt == ti.len) a.split[ti.slot] = P1 + c1;
   }
 
   // start the next tile's loads before this tile's stores: stores and
