@@ -60,12 +60,20 @@ def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def source_hash() -> str:
+def code_hash(texts) -> str:
+    """Hash of the kernel sources with comments and blank space removed, so
+    that only a change of the code itself invalidates a measurement."""
+    import re
     h = hashlib.sha256()
-    for p in SOURCES:
-        with open(p, "rb") as f:
-            h.update(f.read())
+    for t in texts:
+        t = re.sub(r"/\*.*?\*/", "", t, flags=re.S)
+        t = re.sub(r"//[^\n]*", "", t)
+        h.update("".join(t.split()).encode())
     return h.hexdigest()[:16]
+
+
+def source_hash() -> str:
+    return code_hash(open(p).read() for p in SOURCES)
 
 
 def workload_arrays():

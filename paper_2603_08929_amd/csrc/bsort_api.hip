@@ -2,11 +2,13 @@
 // sequence behind the C ABI declared in include/bsort.h.
 //
 // One call enqueues, on the caller's stream and without any host readback:
-//   init   -- zero the work-list counters and look-back words
+//   init   -- zero the work-list counters and the per-tile count arrays
 //   (validate offsets, segmented calls only)
 //   seed   -- level-0 work lists: each user segment is split on its top bit
 //             (the first pass of Algorithms 2-4) or finished in LDS
-//   w x { level, plan } -- one breadth-first level of the recursion each
+//   w x { count, level, plan } -- one breadth-first level of the recursion
+//             each: tile map and missing per-tile counts, the split pass,
+//             then the children's lists
 //   copy   -- large retired segments not yet in the caller's buffer
 //   finish -- small segments: all remaining bits in LDS, final write
 // Grids are sized from upper bounds; the kernels read their real work from

@@ -8,9 +8,10 @@
 //
 // A level is ONE pass over the live keys: each workgroup takes a tile of
 // one segment, ranks its keys front/back with wave ballots and an LDS scan,
-// finds how many front keys precede the tile through a decoupled look-back
-// over the segment's earlier tiles, and scatters the tile as two contiguous
-// runs.  The split point of a segment is not needed before its back part is
+// takes how many front keys precede the tile from per-tile counts made
+// before the level (by the previous level while it wrote the keys, or by a
+// count pass for segments whose bit was reached by skipping), and scatters
+// the tile as two contiguous runs.  The split point of a segment is not needed before its back part is
 // written: back keys are placed from the segment's right end leftwards, so
 // the back child is stored in reverse order and the next level reads it
 // right to left (a per-segment "rev" flag).  The same pass folds the AND and
@@ -841,8 +842,8 @@ __device__ __forceinline__ void level_tile(const LevelArgs<KT> &a, const TileInf
 // tile ahead).  A tile's front offset inside its segment comes from the
 // counts that the previous level (or the level-0 count pass) produced for
 // this bit: the sum over the tile's 64-tile group predecessors plus its own
-// group's earlier tiles.  Segments whose bit was reached by skipping have no
-// such counts and use a decoupled look-back instead.  Front keys go to
+// group's earlier tiles.  Segments whose bit was reached by skipping are
+// counted by the count pass before the level.  Front keys go to
 // start + prefix, back keys are placed from the segment's right end
 // leftwards, so the back child is stored reversed.  While writing, each
 // tile also counts, for every child tile of the next level, how many keys
