@@ -91,11 +91,17 @@ def test_select_matches_sort(dtype):
     if w == 64:
         keys |= rng.integers(0, 2, size=n, dtype=np.uint64) << np.uint64(63)
     keys[::7] = keys[3]  # duplicates
+    mname = {oracle.UNSIGNED: "unsigned", oracle.SIGNED: "signed", oracle.FLOAT: "float"}[mode]
+    keyfn = order_key_fn(mname, w, mant)
+    kl = [int(k) for k in keys]
     for asc in (True, False):
         sk, si = oracle.sort(keys, w, mode, asc=asc, mant_bits=mant)
+        # the numeric order written out independently of the oracle
+        perm = expected_stable(kl, keyfn, asc)
         for j in [0, 1, n // 2, n - 2, n - 1] + rng.integers(0, n, 10).tolist():
             k, i = oracle.select(keys, w, mode, asc, int(j), mant_bits=mant)
             assert k == int(sk[j]) and i == int(si[j])
+            assert i == perm[j] and k == kl[perm[j]]
 
 
 def test_permute_backward():
