@@ -151,6 +151,59 @@ int bsort_backward_scatter(const void *grad_sorted, const void *indices, uint64_
                            uint64_t cols, int elem_bytes, void *grad_in, uint32_t flags,
                            void *stream);
 
+/* ---- launch configurations and the autotuner ----
+ *
+ * Section V proposes handing partitions to a cache-resident routine once
+ * they are small enough; how small is a tuning question.  Here that size is
+ * the LDS-finish threshold T, tuned together with the level tile, the block
+ * sizes and the grid:
+ * a configuration fixes
+ *   level kernel: 512 or 256 threads x 8 keys (4 with 8-byte keys) per tile,
+ *   finish: 512 x 16, 256 x 16 or 512 x 8 keys per workgroup (halved for
+ *           8-byte keys) -- T = 8192, 4096 or 4096 keys of 4 B,
+ *   grids: every resident workgroup, or half of them.
+ * Configuration 0 is the default.  Every configuration gives the same
+ * result, bit for bit; only the time differs. */
+int bsort_config_count(void);
+/* Static text describing a configuration. */
+const char *bsort_config_name(int config);
+/* Force one configuration for every later call of this process (-1 clears
+ * the override).  For tests and measurements. */
+int bsort_config_override(int config);
+/* The configuration a call with these parameters would use on the current
+ * device (the override, else the tuned one, else 0), or a negative status. */
+int bsort_tuned_config(int key_bytes, int with_indices, uint64_t n, uint64_t num_segments);
+/* Times every configuration `reps` times on the caller's data (the arguments
+ * of bsort_segmented; offsets == NULL means one array of n keys) and keeps
+ * the fastest for this device, key width, index mode and size class
+ * (log2 of n / num_segments).  On return the buffers hold the sorted result,
+ * as after a normal call.  Unlike the sort calls it allocates a copy of the
+ * keys (hipMalloc) and synchronizes `stream`; not thread-safe.  Returns the
+ * chosen configuration, or a negative status. */
+int bsort_autotune(void *keys, int key_type, int key_bytes, const int64_t *offsets,
+                   uint64_t num_segments, uint64_t n, uint32_t flags, void *indices,
+                   void *scratch, size_t scratch_bytes, void *stream, int reps);
+/* Forget every tuned choice. */
+void bsort_autotune_reset(void);
+
+/* ---- HIP graphs ----
+ * For callers that sort buffers of the same shape again and again (batched
+ * workloads, training loops): the whole launch sequence of one call is
+ * recorded once into a HIP graph and replayed with a single launch, so the
+ * host submits one command per sort instead of about 3w + 5.  The graph is
+ * bound to the pointers, sizes, flags and configuration given at creation;
+ * every launch sorts whatever the buffers hold then.  The sequence records no
+ * memset or host callback.  Launches that share a scratch buffer must not
+ * overlap.  bsort_graph_create validates like bsort_segmented (offsets ==
+ * NULL: one array of n keys); it records on a private stream and enqueues
+ * nothing. */
+typedef struct bsort_graph bsort_graph;
+int bsort_graph_create(bsort_graph **graph, void *keys, int key_type, int key_bytes,
+                       const int64_t *offsets, uint64_t num_segments, uint64_t n,
+                       uint32_t flags, void *indices, void *scratch, size_t scratch_bytes);
+int bsort_graph_launch(const bsort_graph *graph, void *stream);
+int bsort_graph_destroy(bsort_graph *graph);
+
 /* Text for a status code (for BSORT_EHIP, the last HIP error seen). */
 const char *bsort_strerror(int status);
 

@@ -33,7 +33,10 @@ TYPED = ["u8", "u16", "u32", "u64", "i8", "i16", "i32", "i64", "f8", "f16", "f32
 SYMBOLS = ["bsort_scratch_bytes", "bsort_sort", "bsort_segmented", "bsort_segmented_f32",
            "bsort_segmented_i32", "bsort_backward_scatter", "bsort_strerror",
            "bsort_device_status", "bsort_level_stats", "bsort_timing_arm",
-           "bsort_timing_read", "bsort_timing_disarm"] + [f"bsort_{t}" for t in TYPED]
+           "bsort_timing_read", "bsort_timing_disarm", "bsort_config_count",
+           "bsort_config_name", "bsort_config_override", "bsort_tuned_config",
+           "bsort_autotune", "bsort_autotune_reset", "bsort_graph_create",
+           "bsort_graph_launch", "bsort_graph_destroy"] + [f"bsort_{t}" for t in TYPED]
 
 lib.bsort_scratch_bytes.argtypes = [_i, _u64, _u64, _i, _u32]
 lib.bsort_scratch_bytes.restype = _sz
@@ -63,6 +66,25 @@ lib.bsort_timing_read.argtypes = [_vp, _vp, _i]
 lib.bsort_timing_read.restype = _i
 lib.bsort_timing_disarm.argtypes = []
 lib.bsort_timing_disarm.restype = None
+lib.bsort_config_count.argtypes = []
+lib.bsort_config_count.restype = _i
+lib.bsort_config_name.argtypes = [_i]
+lib.bsort_config_name.restype = ctypes.c_char_p
+lib.bsort_config_override.argtypes = [_i]
+lib.bsort_config_override.restype = _i
+lib.bsort_tuned_config.argtypes = [_i, _i, _u64, _u64]
+lib.bsort_tuned_config.restype = _i
+lib.bsort_autotune.argtypes = [_vp, _i, _i, _vp, _u64, _u64, _u32, _vp, _vp, _sz, _vp, _i]
+lib.bsort_autotune.restype = _i
+lib.bsort_autotune_reset.argtypes = []
+lib.bsort_autotune_reset.restype = None
+lib.bsort_graph_create.argtypes = [ctypes.POINTER(_vp), _vp, _i, _i, _vp, _u64, _u64, _u32, _vp,
+                                   _vp, _sz]
+lib.bsort_graph_create.restype = _i
+lib.bsort_graph_launch.argtypes = [_vp, _vp]
+lib.bsort_graph_launch.restype = _i
+lib.bsort_graph_destroy.argtypes = [_vp]
+lib.bsort_graph_destroy.restype = _i
 
 
 def strerror(rc: int) -> str:
@@ -87,5 +109,14 @@ bsort_level_stats = lib.bsort_level_stats
 bsort_timing_arm = lib.bsort_timing_arm
 bsort_timing_read = lib.bsort_timing_read
 bsort_timing_disarm = lib.bsort_timing_disarm
+bsort_config_count = lib.bsort_config_count
+bsort_config_name = lib.bsort_config_name
+bsort_config_override = lib.bsort_config_override
+bsort_tuned_config = lib.bsort_tuned_config
+bsort_autotune = lib.bsort_autotune
+bsort_autotune_reset = lib.bsort_autotune_reset
+bsort_graph_create = lib.bsort_graph_create
+bsort_graph_launch = lib.bsort_graph_launch
+bsort_graph_destroy = lib.bsort_graph_destroy
 for _t in TYPED:
     globals()[f"bsort_{_t}"] = getattr(lib, f"bsort_{_t}")

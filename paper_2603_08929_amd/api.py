@@ -126,3 +126,76 @@ def backward_scatter(grad_sorted: torch.Tensor, indices: torch.Tensor,
 
 def device_status(scratch: torch.Tensor) -> int:
     return int(_lib.bsort_device_status(scratch.data_ptr(), _stream(scratch.device)))
+
+
+def _segment_args(keys: torch.Tensor, offsets: Optional[torch.Tensor]):
+    if not keys.is_cuda or keys.dim() != 1 or not keys.is_contiguous():
+        raise ValueError("bsort: need a contiguous 1-D GPU tensor")
+    if offsets is not None and (offsets.dtype != torch.int64 or not offsets.is_cuda
+                                or not offsets.is_contiguous()):
+        raise ValueError("bsort: offsets must be a contiguous int64 GPU tensor")
+    B = offsets.numel() - 1 if offsets is not None else 1
+    return B, (offsets.data_ptr() if offsets is not None else None)
+
+
+def autotune(keys: torch.Tensor, offsets: Optional[torch.Tensor] = None,
+             descending: bool = False, indices: Optional[torch.Tensor] = None,
+             flags: int = 0, reps: int = 2, scratch: Optional[torch.Tensor] = None) -> int:
+    """Times every launch configuration on these keys (sorting them, like a
+    normal call) and keeps the fastest for calls of this shape class.
+    indices: None, or an int32 / int64 tensor of keys.numel() to fill.
+    Returns the chosen configuration."""
+    kt, kb = key_type(keys.dtype)
+    B, off = _segment_args(keys, offsets)
+    n = keys.numel()
+    fl = _flags(descending, flags, indices is not None and indices.dtype == torch.int64)
+    need = _lib.bsort_scratch_bytes(kb, n, max(B, 1), int(indices is not None), fl)
+    if scratch is None or scratch.numel() < need:
+        scratch = torch.empty(max(need, 256), dtype=torch.uint8, device=keys.device)
+    rc = _lib.bsort_autotune(keys.data_ptr(), kt, kb, off, B, n, fl,
+                             indices.data_ptr() if indices is not None else None,
+                             scratch.data_ptr(), scratch.numel(), _stream(keys.device), reps)
+    if rc < 0:
+        _lib.check(rc, "bsort_autotune")
+    return rc
+
+
+class SortGraph:
+    """One sort of fixed buffers recorded into a HIP graph; launch() replays
+    it on the current stream (the buffers' contents at that time are
+    sorted).  Keeps the buffers alive while it exists."""
+
+    def __init__(self, keys: torch.Tensor, offsets: Optional[torch.Tensor] = None,
+                 descending: bool = False, indices: Optional[torch.Tensor] = None,
+                 flags: int = 0, scratch: Optional[torch.Tensor] = None):
+        import ctypes
+        kt, kb = key_type(keys.dtype)
+        B, off = _segment_args(keys, offsets)
+        n = keys.numel()
+        fl = _flags(descending, flags, indices is not None and indices.dtype == torch.int64)
+        need = _lib.bsort_scratch_bytes(kb, n, max(B, 1), int(indices is not None), fl)
+        if scratch is None or scratch.numel() < need:
+            scratch = torch.empty(max(need, 256), dtype=torch.uint8, device=keys.device)
+        self._bufs = (keys, offsets, indices, scratch)
+        self._h = ctypes.c_void_p()
+        with torch.cuda.device(keys.device):
+            rc = _lib.bsort_graph_create(ctypes.byref(self._h), keys.data_ptr(), kt, kb, off, B,
+                                         n, fl, indices.data_ptr() if indices is not None else None,
+                                         scratch.data_ptr(), scratch.numel())
+        _lib.check(rc, "bsort_graph_create")
+        self.device = keys.device
+        self.scratch = scratch
+
+    def launch(self) -> None:
+        _lib.check(_lib.bsort_graph_launch(self._h, _stream(self.device)), "bsort_graph_launch")
+
+    def close(self) -> None:
+        if self._h:
+            _lib.check(_lib.bsort_graph_destroy(self._h), "bsort_graph_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -36,6 +36,7 @@ struct Timing {
   int *lvl = nullptr;
 };
 Timing g_timing;
+thread_local int g_capturing = 0;  // set while a call is recorded into a graph
 
 void timing_free() {
   if (g_timing.ev) {
@@ -58,7 +59,7 @@ struct DevState {
 };
 DevState g_dev[64];
 
-int device_check(int *cus) {
+int device_check(int *cus, int *device = nullptr) {
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
@@ -74,44 +75,46 @@ int device_check(int *cus) {
   }
   if (!d.ok) return BSORT_ENODEV;
   *cus = d.cus;
+  if (device) *device = dev;
   return BSORT_OK;
 }
 
-// Launch shapes per key width: level tile = LB * LIPT keys, finish
-// threshold T = FB * FIPT keys.
-#ifndef BSORT_LB
-#define BSORT_LB 512
-#endif
-#ifndef BSORT_LIPT
-#define BSORT_LIPT 8
-#endif
-#ifndef BSORT_FB
-#define BSORT_FB 512
-#endif
-#ifndef BSORT_FIPT
-#define BSORT_FIPT 16
-#endif
-#ifndef BSORT_FRB
-#define BSORT_FRB 5
-#endif
-template <typename KT>
-struct Tune {
-  static constexpr int LB = BSORT_LB;
-  static constexpr int LIPT = sizeof(KT) == 8 ? (BSORT_LIPT / 2 > 0 ? BSORT_LIPT / 2 : 1) : BSORT_LIPT;
-  static constexpr int FB = BSORT_FB;
-  static constexpr int FIPT = sizeof(KT) == 8 ? BSORT_FIPT / 2 : BSORT_FIPT;
-  static constexpr int FRB = BSORT_FRB;
+// Launch configurations.  A configuration fixes the level kernel's block
+// and tile (TILE = LB * LIPT keys), the finish kernel's block and threshold
+// (T = FB * FIPT keys) and the grids (every resident workgroup, or half).
+// Configuration 0 is the default; bsort_autotune times all of them on the
+// caller's data and remembers the fastest per key width, index mode and
+// size class.
+constexpr int N_LEVEL_SHAPES = 2, N_FINISH_SHAPES = 3, N_GRIDS = 2;
+constexpr int N_CONFIGS = N_LEVEL_SHAPES * N_FINISH_SHAPES * N_GRIDS;
+
+template <typename KT, int V>
+struct LevelShape {
+  static constexpr int LB = V == 0 ? 512 : 256;
+  static constexpr int LIPT = sizeof(KT) == 8 ? 4 : 8;
   static constexpr uint32_t TILE = LB * LIPT;
+};
+template <typename KT, int V>
+struct FinishShape {
+  static constexpr int FB = V == 1 ? 256 : 512;
+  static constexpr int FIPT = (V == 2 ? 8 : 16) / (sizeof(KT) == 8 ? 2 : 1);
+  static constexpr int FRB = 5;
   static constexpr uint32_t TFIN = FB * FIPT;
 };
 
-void shape_for(int key_bytes, uint32_t *tile, uint32_t *tfin) {
-  switch (key_bytes) {
-    case 1: *tile = Tune<uint8_t>::TILE; *tfin = Tune<uint8_t>::TFIN; break;
-    case 2: *tile = Tune<uint16_t>::TILE; *tfin = Tune<uint16_t>::TFIN; break;
-    case 4: *tile = Tune<uint32_t>::TILE; *tfin = Tune<uint32_t>::TFIN; break;
-    default: *tile = Tune<uint64_t>::TILE; *tfin = Tune<uint64_t>::TFIN; break;
-  }
+struct Config {
+  int lv, fv, grid;  // level shape, finish shape, grid (0 full, 1 half)
+};
+Config config_of(int id) { return Config{id / 6, (id / 2) % 3, id % 2}; }
+constexpr int CONFIG_DRY_RUN = -2;  // validate the arguments and the device, launch nothing
+
+uint32_t tile_of(int key_bytes, int lv) {
+  const uint32_t lb = lv == 0 ? 512 : 256;
+  return lb * (key_bytes == 8 ? 4 : 8);
+}
+uint32_t tfin_of(int key_bytes, int fv) {
+  const uint32_t fb = fv == 1 ? 256 : 512;
+  return fb * ((fv == 2 ? 8 : 16) / (key_bytes == 8 ? 2 : 1));
 }
 
 constexpr uint32_t ALL_FLAGS =
@@ -131,10 +134,8 @@ struct Layout {
 };
 
 bool make_layout(int key_bytes, uint64_t n, uint64_t B, bool with_idx, uint32_t flags,
-                 Layout *L) {
+                 uint32_t tile, uint32_t tfin, Layout *L) {
   if (key_bytes != 1 && key_bytes != 2 && key_bytes != 4 && key_bytes != 8) return false;
-  uint32_t tile, tfin;
-  shape_for(key_bytes, &tile, &tfin);
   const uint64_t w = 8ull * key_bytes;
   const bool no_finish = (flags & BSORT_NO_FINISH) != 0;
   L->smax = (no_finish ? n / 2 : n / (tfin + 1ull)) + 1;
@@ -176,14 +177,17 @@ int occupancy(K kernel, int block) {
 
 uint32_t clamp_grid(uint64_t want, uint64_t cap) {
   if (want < 1) want = 1;
+  if (cap < 1) cap = 1;
   return (uint32_t)(want < cap ? want : cap);
 }
 
-template <typename KT, bool IDX>
+template <typename KT, bool IDX, int LV, int FV>
 int launch_all(KT *keys, uint64_t n, const int64_t *offsets, uint64_t B, int mode,
-               uint32_t flags, void *indices, char *scr, const Layout &L, int cus,
+               uint32_t flags, void *indices, char *scr, const Layout &L, int cus, int half,
                hipStream_t st) {
-  using TU = Tune<KT>;
+  using LS = LevelShape<KT, LV>;
+  using FS = FinishShape<KT, FV>;
+  const uint64_t gdiv = half ? 2 : 1;
   const int w = 8 * (int)sizeof(KT);
   const int desc = (flags & BSORT_DESCENDING) ? 1 : 0;
   const int idx64 = (IDX && (flags & BSORT_IDX64)) ? 1 : 0;
@@ -226,8 +230,8 @@ int launch_all(KT *keys, uint64_t n, const int64_t *offsets, uint64_t B, int mod
   la.hdr = hdr;
   la.fin = fin;
   la.cpy = cpy;
-  la.tile = TU::TILE;
-  la.t_fin = TU::TFIN;
+  la.tile = LS::TILE;
+  la.t_fin = FS::TFIN;
   la.recount = (uint32_t)(2 * L.tmax);
 
   SeedArgs sa;
@@ -245,17 +249,17 @@ int launch_all(KT *keys, uint64_t n, const int64_t *offsets, uint64_t B, int mod
   sa.no_finish = no_finish;
   hipLaunchKernelGGL(seed_kernel, dim3(clamp_grid((B + 255) / 256, cap)), dim3(256), 0, st, sa);
 
-  auto lk = level_kernel<KT, IDX, TU::LB, TU::LIPT>;
-  static const int occ_level = occupancy(lk, TU::LB);
-  const uint32_t lgrid = clamp_grid(L.tmax, (uint64_t)cus * occ_level);
+  auto lk = level_kernel<KT, IDX, LS::LB, LS::LIPT>;
+  static const int occ_level = occupancy(lk, LS::LB);
+  const uint32_t lgrid = clamp_grid(L.tmax, (uint64_t)cus * occ_level / gdiv);
   const uint32_t pgrid = clamp_grid((L.smax + 255) / 256, cap);
-  auto ck = count_kernel<KT, TU::LB, TU::LIPT>;
-  static const int occ_count = occupancy(ck, TU::LB);
-  const uint32_t cgrid = clamp_grid(L.tmax, (uint64_t)cus * occ_count);
+  auto ck = count_kernel<KT, LS::LB, LS::LIPT>;
+  static const int occ_count = occupancy(ck, LS::LB);
+  const uint32_t cgrid = clamp_grid(L.tmax, (uint64_t)cus * occ_count / gdiv);
   // A single array that fits the LDS finish never has a live segment: the
   // seed hands it straight to the finish, so the level passes and the copy
   // would all find empty lists.
-  const int levels = (!offsets && !no_finish && n <= TU::TFIN) ? 0 : w;
+  const int levels = (!offsets && !no_finish && n <= FS::TFIN) ? 0 : w;
   for (int lvl = 0; lvl < levels; ++lvl) {
     CountArgs<KT> ca;
     ca.keys = kbuf[lvl & 1];
@@ -269,7 +273,7 @@ int launch_all(KT *keys, uint64_t n, const int64_t *offsets, uint64_t B, int mod
     ca.mode = mode;
     ca.desc = desc;
     ca.level = lvl;
-    hipLaunchKernelGGL(ck, dim3(cgrid), dim3(TU::LB), 0, st, ca);
+    hipLaunchKernelGGL(ck, dim3(cgrid), dim3(LS::LB), 0, st, ca);
 
     LevelArgs<KT> a;
     a.keys_in = kbuf[lvl & 1];
@@ -288,9 +292,9 @@ int launch_all(KT *keys, uint64_t n, const int64_t *offsets, uint64_t B, int mod
     a.mode = mode;
     a.desc = desc;
     a.level = lvl;
-    const bool timed = g_timing.armed && g_timing.count < g_timing.cap;
+    const bool timed = g_timing.armed && !g_capturing && g_timing.count < g_timing.cap;
     if (timed) (void)hipEventRecord(g_timing.ev[2 * g_timing.count], st);
-    hipLaunchKernelGGL(lk, dim3(lgrid), dim3(TU::LB), 0, st, a);
+    hipLaunchKernelGGL(lk, dim3(lgrid), dim3(LS::LB), 0, st, a);
     if (timed) {
       (void)hipEventRecord(g_timing.ev[2 * g_timing.count + 1], st);
       g_timing.lvl[g_timing.count++] = lvl;
@@ -346,19 +350,58 @@ int launch_all(KT *keys, uint64_t n, const int64_t *offsets, uint64_t B, int mod
   fa.desc = desc;
   fa.idx64 = idx64;
   fa.no_skip = no_skip;
-  auto fk = finish_kernel<KT, IDX, TU::FB, TU::FIPT, TU::FRB>;
-  static const int occ_fin = occupancy(fk, TU::FB);
-  hipLaunchKernelGGL(fk, dim3(clamp_grid(L.fmax, (uint64_t)cus * occ_fin)), dim3(TU::FB), 0, st,
-                     fa);
+  auto fk = finish_kernel<KT, IDX, FS::FB, FS::FIPT, FS::FRB>;
+  static const int occ_fin = occupancy(fk, FS::FB);
+  const uint32_t fgrid = clamp_grid(L.fmax, (uint64_t)cus * occ_fin / gdiv);
+  hipLaunchKernelGGL(fk, dim3(fgrid), dim3(FS::FB), 0, st, fa);
 
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
   return BSORT_OK;
 }
 
+// Configuration choice: a process-wide override (tests), else what the
+// autotuner found for this device, key width, index mode and size class
+// (log2 of the mean segment length), else configuration 0.
+int g_override = -1;
+signed char g_tuned[64][4][2][48];  // configuration + 1; 0 = not tuned
+
+int kb_slot(int key_bytes) { return key_bytes == 1 ? 0 : key_bytes == 2 ? 1 : key_bytes == 4 ? 2 : 3; }
+int size_class(uint64_t n, uint64_t B) {
+  const uint64_t mean = n / (B ? B : 1);
+  const int c = 63 - __builtin_clzll(mean | 1);
+  return c < 47 ? c : 47;
+}
+int choose_config(int dev, int key_bytes, bool with_idx, uint64_t n, uint64_t B) {
+  if (g_override >= 0) return g_override;
+  const int t = g_tuned[dev][kb_slot(key_bytes)][with_idx ? 1 : 0][size_class(n, B)];
+  return t > 0 ? t - 1 : 0;
+}
+
+template <typename KT, bool IDX>
+int launch_cfg(const Config &c, KT *k, uint64_t n, const int64_t *off, uint64_t b, int mode,
+               uint32_t flags, void *indices, char *scr, const Layout &L, int cus,
+               hipStream_t st) {
+#define BSORT_CFG(LV, FV)                                                                    \
+  case LV * 3 + FV:                                                                          \
+    return launch_all<KT, IDX, LV, FV>(k, n, off, b, mode, flags, indices, scr, L, cus,      \
+                                       c.grid, st)
+  switch (c.lv * 3 + c.fv) {
+    BSORT_CFG(0, 0);
+    BSORT_CFG(0, 1);
+    BSORT_CFG(0, 2);
+    BSORT_CFG(1, 0);
+    BSORT_CFG(1, 1);
+    BSORT_CFG(1, 2);
+    default: return BSORT_EINVAL;
+  }
+#undef BSORT_CFG
+}
+
 template <typename KT>
 int run(void *keys, uint64_t n, const int64_t *offsets, uint64_t B, bool segmented, int mode,
-        uint32_t flags, void *indices, void *scratch, size_t scratch_bytes, void *stream) {
+        uint32_t flags, void *indices, void *scratch, size_t scratch_bytes, void *stream,
+        int force_config) {
   if (flags & ~ALL_FLAGS) return BSORT_EINVAL;
   if (segmented && B > 0 && !offsets) return BSORT_EINVAL;
   if (segmented && B == 0 && n != 0) return BSORT_EINVAL;
@@ -367,42 +410,50 @@ int run(void *keys, uint64_t n, const int64_t *offsets, uint64_t B, bool segment
   const bool with_idx = indices != nullptr;
   if (with_idx && n >= (1ull << 32)) return BSORT_ETOOBIG;
   if (n >= (1ull << 47)) return BSORT_ETOOBIG;
+  const uint64_t b = segmented ? B : 1;
+  // the scratch check uses the largest layout of any configuration, so a
+  // buffer sized by bsort_scratch_bytes fits every one of them
   Layout L;
-  if (!make_layout((int)sizeof(KT), n, segmented ? B : 1, with_idx, flags, &L))
+  if (!make_layout((int)sizeof(KT), n, b, with_idx, flags, tile_of((int)sizeof(KT), 1),
+                   tfin_of((int)sizeof(KT), 1), &L))
     return BSORT_EINVAL;
   if (scratch_bytes < L.total) return BSORT_ESCRATCH;
   if (reinterpret_cast<uintptr_t>(scratch) & 255) return BSORT_EINVAL;
-  int cus = 0;
-  const int rc = device_check(&cus);
+  int cus = 0, dev = 0;
+  const int rc = device_check(&cus, &dev);
   if (rc != BSORT_OK) return rc;
+  if (force_config == CONFIG_DRY_RUN) return BSORT_OK;
+  const int id = force_config >= 0 ? force_config
+                                   : choose_config(dev, (int)sizeof(KT), with_idx, n, b);
+  const Config c = config_of(id);
+  make_layout((int)sizeof(KT), n, b, with_idx, flags, tile_of((int)sizeof(KT), c.lv),
+              tfin_of((int)sizeof(KT), c.fv), &L);
   hipStream_t st = static_cast<hipStream_t>(stream);
   char *scr = static_cast<char *>(scratch);
   KT *k = static_cast<KT *>(keys);
   const int64_t *off = segmented ? offsets : nullptr;
-  const uint64_t b = segmented ? B : 1;
-  if (with_idx)
-    return launch_all<KT, true>(k, n, off, b, mode, flags, indices, scr, L, cus, st);
-  return launch_all<KT, false>(k, n, off, b, mode, flags, indices, scr, L, cus, st);
+  if (with_idx) return launch_cfg<KT, true>(c, k, n, off, b, mode, flags, indices, scr, L, cus, st);
+  return launch_cfg<KT, false>(c, k, n, off, b, mode, flags, indices, scr, L, cus, st);
 }
 
 int dispatch(void *keys, int key_type, int key_bytes, uint64_t n, const int64_t *offsets,
              uint64_t B, bool segmented, uint32_t flags, void *indices, void *scratch,
-             size_t scratch_bytes, void *stream) {
+             size_t scratch_bytes, void *stream, int force_config = -1) {
   if (key_type != BSORT_KEY_U && key_type != BSORT_KEY_I && key_type != BSORT_KEY_F)
     return BSORT_EINVAL;
   switch (key_bytes) {
     case 1:
       return run<uint8_t>(keys, n, offsets, B, segmented, key_type, flags, indices, scratch,
-                          scratch_bytes, stream);
+                          scratch_bytes, stream, force_config);
     case 2:
       return run<uint16_t>(keys, n, offsets, B, segmented, key_type, flags, indices, scratch,
-                           scratch_bytes, stream);
+                           scratch_bytes, stream, force_config);
     case 4:
       return run<uint32_t>(keys, n, offsets, B, segmented, key_type, flags, indices, scratch,
-                           scratch_bytes, stream);
+                           scratch_bytes, stream, force_config);
     case 8:
       return run<uint64_t>(keys, n, offsets, B, segmented, key_type, flags, indices, scratch,
-                           scratch_bytes, stream);
+                           scratch_bytes, stream, force_config);
     default:
       return BSORT_EINVAL;
   }
@@ -415,8 +466,11 @@ extern "C" {
 size_t bsort_scratch_bytes(int key_bytes, uint64_t n, uint64_t num_segments, int with_indices,
                            uint32_t flags) {
   if (flags & ~ALL_FLAGS) return 0;
+  if (key_bytes != 1 && key_bytes != 2 && key_bytes != 4 && key_bytes != 8) return 0;
+  // the largest layout of any configuration: the smallest tile and threshold
   Layout L;
-  if (!make_layout(key_bytes, n, num_segments ? num_segments : 1, with_indices != 0, flags, &L))
+  if (!make_layout(key_bytes, n, num_segments ? num_segments : 1, with_indices != 0, flags,
+                   tile_of(key_bytes, 1), tfin_of(key_bytes, 1), &L))
     return 0;
   return L.total;
 }
@@ -499,6 +553,165 @@ int bsort_backward_scatter(const void *grad_sorted, const void *indices, uint64_
 #undef BS_LAUNCH
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  return BSORT_OK;
+}
+
+int bsort_config_count(void) { return N_CONFIGS; }
+
+const char *bsort_config_name(int config) {
+  static char names[N_CONFIGS][96];
+  if (config < 0 || config >= N_CONFIGS) return "invalid configuration";
+  if (!names[config][0]) {
+    const Config c = config_of(config);
+    snprintf(names[config], sizeof names[config],
+             "level %dx%d (tile %u keys of 4 B), finish %dx%d (T %u keys of 4 B), %s grid",
+             c.lv == 0 ? 512 : 256, 8, tile_of(4, c.lv), c.fv == 1 ? 256 : 512,
+             c.fv == 2 ? 8 : 16, tfin_of(4, c.fv), c.grid ? "half" : "full");
+  }
+  return names[config];
+}
+
+int bsort_config_override(int config) {
+  if (config < -1 || config >= N_CONFIGS) return BSORT_EINVAL;
+  g_override = config;
+  return BSORT_OK;
+}
+
+int bsort_tuned_config(int key_bytes, int with_indices, uint64_t n, uint64_t num_segments) {
+  if (key_bytes != 1 && key_bytes != 2 && key_bytes != 4 && key_bytes != 8) return BSORT_EINVAL;
+  int cus = 0, dev = 0;
+  const int rc = device_check(&cus, &dev);
+  if (rc != BSORT_OK) return rc;
+  return choose_config(dev, key_bytes, with_indices != 0, n, num_segments ? num_segments : 1);
+}
+
+void bsort_autotune_reset(void) { memset(g_tuned, 0, sizeof g_tuned); }
+
+int bsort_autotune(void *keys, int key_type, int key_bytes, const int64_t *offsets,
+                   uint64_t num_segments, uint64_t n, uint32_t flags, void *indices,
+                   void *scratch, size_t scratch_bytes, void *stream, int reps) {
+  if (g_capturing) return BSORT_EINVAL;
+  const bool seg = offsets != nullptr;
+  const uint64_t B = seg ? num_segments : 1;
+  // arguments checked as a sort would check them, nothing launched
+  int rc = dispatch(keys, key_type, key_bytes, n, offsets, B, seg, flags, indices, scratch,
+                    scratch_bytes, stream, CONFIG_DRY_RUN);
+  if (rc != BSORT_OK) return rc;
+  if (n == 0) return 0;
+  int cus = 0, dev = 0;
+  rc = device_check(&cus, &dev);
+  if (rc != BSORT_OK) return rc;
+  if (reps < 1) reps = 1;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const size_t bytes = n * (size_t)key_bytes;
+  void *orig = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipMalloc(&orig, bytes);
+  if (e != hipSuccess) return hip_fail(e, "bsort_autotune: hipMalloc");
+  e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e == hipSuccess) e = hipMemcpyAsync(orig, keys, bytes, hipMemcpyDeviceToDevice, st);
+  const int armed = g_timing.armed;
+  g_timing.armed = 0;  // tuning launches are not benchmark launches
+  int best = -1;
+  float best_ms = 0.f;
+  for (int id = 0; id < N_CONFIGS && e == hipSuccess && rc == BSORT_OK; ++id) {
+    float t_min = 0.f;
+    for (int r = 0; r < reps && e == hipSuccess && rc == BSORT_OK; ++r) {
+      e = hipMemcpyAsync(keys, orig, bytes, hipMemcpyDeviceToDevice, st);
+      if (e == hipSuccess) e = hipEventRecord(e0, st);
+      if (e != hipSuccess) break;
+      rc = dispatch(keys, key_type, key_bytes, n, offsets, B, seg, flags, indices, scratch,
+                    scratch_bytes, stream, id);
+      if (rc != BSORT_OK) break;
+      e = hipEventRecord(e1, st);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e == hipSuccess && (r == 0 || ms < t_min)) t_min = ms;
+    }
+    if (e == hipSuccess && rc == BSORT_OK && (best < 0 || t_min < best_ms)) {
+      best = id;
+      best_ms = t_min;
+    }
+  }
+  // leave the caller's buffers as a sort with the chosen configuration would
+  if (e == hipSuccess && rc == BSORT_OK) {
+    g_tuned[dev][kb_slot(key_bytes)][indices ? 1 : 0][size_class(n, B)] = (signed char)(best + 1);
+    e = hipMemcpyAsync(keys, orig, bytes, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess)
+      rc = dispatch(keys, key_type, key_bytes, n, offsets, B, seg, flags, indices, scratch,
+                    scratch_bytes, stream, best);
+  }
+  g_timing.armed = armed;
+  const hipError_t es = hipStreamSynchronize(st);
+  if (e == hipSuccess) e = es;
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipFree(orig);
+  if (e != hipSuccess) return hip_fail(e, "bsort_autotune");
+  return rc != BSORT_OK ? rc : best;
+}
+
+// A whole call recorded once into a HIP graph and replayed by one launch.
+struct bsort_graph {
+  hipGraphExec_t exec;
+};
+
+int bsort_graph_create(bsort_graph **out, void *keys, int key_type, int key_bytes,
+                       const int64_t *offsets, uint64_t num_segments, uint64_t n,
+                       uint32_t flags, void *indices, void *scratch, size_t scratch_bytes) {
+  if (!out) return BSORT_EINVAL;
+  *out = nullptr;
+  if (g_capturing) return BSORT_EINVAL;
+  const bool seg = offsets != nullptr;
+  const uint64_t B = seg ? num_segments : 1;
+  int rc = dispatch(keys, key_type, key_bytes, n, offsets, B, seg, flags, indices, scratch,
+                    scratch_bytes, nullptr, CONFIG_DRY_RUN);
+  if (rc != BSORT_OK) return rc;
+  bsort_graph *g = new bsort_graph{nullptr};
+  if (n == 0) {  // nothing to record: launching it does nothing
+    *out = g;
+    return BSORT_OK;
+  }
+  hipStream_t cs = nullptr;
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
+  if (e == hipSuccess) {
+    g_capturing = 1;
+    rc = dispatch(keys, key_type, key_bytes, n, offsets, B, seg, flags, indices, scratch,
+                  scratch_bytes, cs);
+    g_capturing = 0;
+    const hipError_t ee = hipStreamEndCapture(cs, &graph);
+    if (e == hipSuccess) e = ee;
+  }
+  if (e == hipSuccess && rc == BSORT_OK) e = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+  if (graph) (void)hipGraphDestroy(graph);
+  if (cs) (void)hipStreamDestroy(cs);
+  if (e != hipSuccess || rc != BSORT_OK) {
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    delete g;
+    return e != hipSuccess ? hip_fail(e, "bsort_graph_create") : rc;
+  }
+  *out = g;
+  return BSORT_OK;
+}
+
+int bsort_graph_launch(const bsort_graph *graph, void *stream) {
+  if (!graph) return BSORT_EINVAL;
+  if (!graph->exec) return BSORT_OK;
+  const hipError_t e = hipGraphLaunch(graph->exec, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  return BSORT_OK;
+}
+
+int bsort_graph_destroy(bsort_graph *graph) {
+  if (!graph) return BSORT_OK;
+  hipError_t e = hipSuccess;
+  if (graph->exec) e = hipGraphExecDestroy(graph->exec);
+  delete graph;
+  if (e != hipSuccess) return hip_fail(e, "hipGraphExecDestroy");
   return BSORT_OK;
 }
 

@@ -105,3 +105,32 @@ def test_torch_dtype_mapping():
     assert api.key_type(torch.uint8) == (_lib.KEY_U, 1)
     with pytest.raises(TypeError):
         api.key_type(torch.complex64)
+
+
+def test_configurations_and_graph_without_device():
+    import ctypes
+    n = _lib.bsort_config_count()
+    assert n == 12
+    names = {_lib.bsort_config_name(i).decode() for i in range(n)}
+    assert len(names) == n
+    assert _lib.bsort_config_name(n) == b"invalid configuration"
+    assert _lib.bsort_config_override(n) == _lib.EINVAL
+    assert _lib.bsort_config_override(-2) == _lib.EINVAL
+    assert _lib.bsort_config_override(3) == _lib.OK
+    assert _lib.bsort_config_override(-1) == _lib.OK
+    assert _lib.bsort_tuned_config(3, 1, 100, 1) == _lib.EINVAL
+    # graph of an empty sort: no HIP call at all
+    h = ctypes.c_void_p()
+    assert _lib.bsort_graph_create(None, None, 0, 4, None, 1, 0, 0, None, None, 0) == _lib.EINVAL
+    assert _lib.bsort_graph_create(ctypes.byref(h), None, 0, 4, None, 1, 0, 0, None, None,
+                                   0) == _lib.OK
+    assert h.value
+    assert _lib.bsort_graph_launch(h, None) == _lib.OK
+    assert _lib.bsort_graph_destroy(h) == _lib.OK
+    assert _lib.bsort_graph_launch(None, None) == _lib.EINVAL
+    # invalid arguments are refused before any capture
+    fake = 1 << 40
+    assert _lib.bsort_graph_create(ctypes.byref(h), fake, 7, 4, None, 1, 10, 0, None, fake,
+                                   1 << 30) == _lib.EINVAL
+    assert _lib.bsort_autotune(fake, 0, 4, None, 1, 10, 1 << 9, None, fake, 1 << 30, None,
+                               1) == _lib.EINVAL
