@@ -52,8 +52,7 @@ LEVEL_KERNEL = "level_kernel<unsigned int, true"
 CALIB_KERNEL = "bitwise_not"
 CALIB_ELEMS = 1 << 28  # int32: 1 GiB read + 1 GiB written
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "level_kernel_u32_idx_2p26_traffic.txt")
-SOURCES = [os.path.join(ROOT, "paper_2603_08929_amd", "csrc", f)
-           for f in ("bsort_kernels.hpp", "bsort_api.hip")]
+SOURCES = [os.path.join(ROOT, "paper_2603_08929_amd", "csrc", "bsort_kernels.hpp")]  # device code
 
 
 def log(msg: str) -> None:
@@ -261,6 +260,7 @@ def extras_word_size(lib, torch, np, dev, stream):
 
 
 def extras_batched(lib, torch, np, dev, stream):
+    from paper_2603_08929_amd import api
     from paper_2603_08929_amd import workloads as W
     lengths = W.batched_lengths()
     n = int(lengths.sum())
@@ -270,8 +270,10 @@ def extras_batched(lib, torch, np, dev, stream):
     out = []
     for name in ("f32", "i32"):
         log(f"batched {name} n={n} arrays={B}")
+        lib.bsort_autotune_reset()
         kt = lib.KEY_F if name == "f32" else lib.KEY_I
         typed = lib.bsort_f32 if name == "f32" else lib.bsort_i32
+        tdt = torch.float32 if name == "f32" else torch.int32
         bits = W.normal_bits("f32", n, 0) if name == "f32" else W.uniform_bits("i32", n, 0)
         src = torch.from_numpy(bits.view(np.int32)).to(dev)
         del bits
@@ -304,15 +306,66 @@ def extras_batched(lib, torch, np, dev, stream):
         once(per_array)
         t_p = once(per_array)
         same = bool(torch.equal(kb, work) and torch.equal(ib, idx))
+        # autotuned, then the tuned call recorded into a HIP graph
+        work.copy_(src)
+        best = api.autotune(work.view(tdt), offsets=offsets, indices=idx, reps=2,
+                            scratch=scratch)
+        t_t = sorted(once(batched) for _ in range(3))[1]
+        same_t = bool(torch.equal(kb, work) and torch.equal(ib, idx))
+        g = api.SortGraph(work.view(tdt), offsets=offsets, indices=idx, scratch=scratch)
+        t_g = sorted(once(g.launch) for _ in range(3))[1]
+        same_g = bool(torch.equal(kb, work) and torch.equal(ib, idx))
+        g.close()
+        lib.bsort_autotune_reset()
         out.append({"dtype": name, "arrays": B, "keys": n,
                     "batched_ms": round(t_b, 3), "batched_gkeys_s": round(n / t_b / 1e6, 3),
                     "batched_alg_GBps": round(ab / t_b / 1e6, 1),
                     "per_array_ms": round(t_p, 3), "per_array_gkeys_s": round(n / t_p / 1e6, 3),
                     "speedup": round(t_p / t_b, 2), "bit_exact_equal": same,
+                    "autotuned_config": lib.bsort_config_name(best).decode(),
+                    "autotuned_ms": round(t_t, 3), "autotuned_gkeys_s": round(n / t_t / 1e6, 3),
+                    "graph_ms": round(t_g, 3), "graph_gkeys_s": round(n / t_g / 1e6, 3),
+                    "tuned_and_graph_bit_exact_equal": same_t and same_g,
                     "levels_executed": int((live > 0).sum()), "finish_keys": fk})
         del src, work, idx, scratch, kb, ib
         torch.cuda.empty_cache()
     return out
+
+
+def extras_small(lib, torch, np, dev, stream):
+    """64 Ki uint32 keys (seed 0), ascending, with indices: a latency-bound
+    size, one eager call vs one graph launch."""
+    from paper_2603_08929_amd import api
+    from paper_2603_08929_amd import workloads as W
+    log("small array, eager vs graph")
+    n = 1 << 16
+    src = torch.from_numpy(W.uniform_bits("u32", n, 0).view(np.int32)).to(dev)
+    work = torch.empty_like(src)
+    idx = torch.empty(n, dtype=torch.int32, device=dev)
+    need = lib.bsort_scratch_bytes(4, n, 1, 1, 0)
+    scratch = torch.empty(need, dtype=torch.uint8, device=dev)
+
+    def eager():
+        lib.check(lib.bsort_u32(work.data_ptr(), n, 0, idx.data_ptr(), scratch.data_ptr(), need,
+                                stream), "u32")
+
+    def once(fn):
+        work.copy_(src)
+        return timed(fn, 1, torch)
+
+    for _ in range(3):
+        once(eager)
+    t_e = sorted(once(eager) for _ in range(21))[10]
+    ke, ie = work.clone(), idx.clone()
+    g = api.SortGraph(work.view(torch.uint32), indices=idx, scratch=scratch)
+    for _ in range(3):
+        once(g.launch)
+    t_g = sorted(once(g.launch) for _ in range(21))[10]
+    same = bool(torch.equal(ke, work) and torch.equal(ie, idx))
+    g.close()
+    return {"n": n, "eager_us": round(t_e * 1e3, 1), "eager_gkeys_s": round(n / t_e / 1e6, 3),
+            "graph_us": round(t_g * 1e3, 1), "graph_gkeys_s": round(n / t_g / 1e6, 3),
+            "bit_exact_equal": same}
 
 
 def extras_backward(lib, torch, np, dev, stream):
@@ -478,6 +531,7 @@ def main() -> int:
         torch.cuda.empty_cache()
         extras = {"word_size_sweep": extras_word_size(_lib, torch, np, dev, stream),
                   "batched_vs_per_array": extras_batched(_lib, torch, np, dev, stream),
+                  "small_u32_64k": extras_small(_lib, torch, np, dev, stream),
                   "differentiable_sort": extras_backward(_lib, torch, np, dev, stream)}
 
     cpu = None
