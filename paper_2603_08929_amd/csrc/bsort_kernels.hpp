@@ -85,7 +85,6 @@ struct Header {
   uint64_t packed[MAX_LEVELS]; // per level: (live segments << 32) | tiles
   uint64_t rec_packed[MAX_LEVELS]; // per level: (segments << 32) | tiles to recount
   uint64_t live_keys[MAX_LEVELS]; // per level: keys in live segments
-  uint32_t grab[MAX_LEVELS];   // per level: next tile id handed out
 };
 
 // ---------------------------------------------------------------- helpers
@@ -598,27 +597,50 @@ template <typename KT, int IPT>
 struct TileRegs {
   KT key[IPT];
   uint32_t ix[IPT];
-  uint32_t pv;      // wave 0: front keys of earlier tiles (precomputed counts)
-  uint64_t acw[4];  // thread 0: the segment's child AND/OR words as read
+  uint32_t pv0, pv1;  // front keys of earlier tiles: a group sum and a tile count
+  uint64_t pvx;       // the rest, for segments of more than BLOCK tile groups
+  uint64_t acw[4];    // ACC_THREAD: the segment's child AND/OR words as read
 };
 
+// Control work is spread over waves so that no single wave waits on all of
+// it: thread 0 claims tiles, lane 0 of wave 1 updates the AND/OR replicas
+// and the split, lanes 0-3 of wave 2 add the next level's counts.
+constexpr int ACC_THREAD = 64;
+constexpr int CNT_WAVE = 2;
+
+
+// Every load is issued on every path -- an invalid tile or an index
+// that is an iota gets an empty range, whose reads return 0 without a
+// memory access -- so that the number of loads in flight does not depend on
+// the path and the compiler waits only for the loads a use needs (the
+// counter of outstanding loads retires in order).
 template <typename KT, bool IDX, int BLOCK, int IPT>
 __device__ __forceinline__ void issue_loads(const LevelArgs<KT> &a, const TileInfo &ti,
                                             TileRegs<KT, IPT> &r) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x;
+  const bool v = ti.valid;
   const bool rev = (ti.meta & META_REV) != 0;
   const bool iota = (ti.meta & META_IOTA) != 0;
-  r.pv = 0;
-  if (wave == 0) {
-    const uint32_t js = ti.j >> 6;
-    for (uint32_t s = lane; s < js; s += 64) r.pv += a.scnt_in[ti.cbase + s];
-    const uint32_t jt = (js << 6) + lane;
-    if (jt < ti.j) r.pv += a.tcnt_in[ti.cbase + jt];
-  }
+  // front keys before this tile in its segment: the sums of the 64-tile
+  // groups before its group and the counts of its group's earlier tiles,
+  // one load per thread, summed only when the tile is ranked
+  const uint32_t js = v ? (ti.j >> 6) : 0u;
+  const uint32_t jt = v ? (ti.j & 63u) : 0u;
+  const rsrc_t gs = make_rsrc(a.scnt_in + (v ? ti.cbase : 0u),
+                              (js < (uint32_t)BLOCK ? js : (uint32_t)BLOCK) * 4u);
+  const rsrc_t ts = make_rsrc(a.tcnt_in + (v ? ti.cbase + (js << 6) : 0u), jt * 4u);
+  r.pv0 = buf_load<uint32_t>(gs, (uint32_t)tid * 4u);
+  r.pv1 = buf_load<uint32_t>(ts, (uint32_t)tid * 4u);
+  // the segment's child AND/OR words as they stand (for the atomics that
+  // the tile may skip), read by every thread
+  const uint32_t ai = v ? ti.tile0 + ACC_STRIDE * (ti.j % acc_repl(ti.len, (uint32_t)(BLOCK * IPT))) : 0u;
+  const rsrc_t ar = make_rsrc(a.acc + ai, v ? (uint32_t)sizeof(AccRep) : 0u);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) r.acw[k] = buf_load<uint64_t>(ar, (uint32_t)k * 8u);
   // storage of the tile: [sbase, sbase + cnt); logical q is at sbase + q
   // (forward) or sbase + cnt - 1 - q (reversed)
   const uint64_t end = ti.start + ti.len;
-  const uint64_t sbase = rev ? (end - ti.lo - ti.cnt) : (ti.start + ti.lo);
+  const uint64_t sbase = v ? (rev ? (end - ti.lo - ti.cnt) : (ti.start + ti.lo)) : 0u;
   const rsrc_t kr = make_rsrc(a.keys_in + sbase, ti.cnt * (uint32_t)sizeof(KT));
   const rsrc_t ir = make_rsrc(IDX ? a.idx_in + sbase : nullptr, IDX && !iota ? ti.cnt * 4u : 0u);
 #pragma unroll
@@ -626,46 +648,59 @@ __device__ __forceinline__ void issue_loads(const LevelArgs<KT> &a, const TileIn
     const uint32_t q = (uint32_t)(i * BLOCK + tid);
     const uint32_t o = rev ? (ti.cnt - 1 - q) : q;  // past cnt: out of range, reads 0
     r.key[i] = buf_load<KT>(kr, o * (uint32_t)sizeof(KT));
-    if (IDX) r.ix[i] = iota ? (uint32_t)(ti.lo + q) : buf_load<uint32_t>(ir, o * 4u);
+    if (IDX) r.ix[i] = buf_load<uint32_t>(ir, o * 4u);  // an iota is added at use
   }
-  if (tid == 0) {
-    const AccRep *ac =
-        &a.acc[ti.tile0 + ACC_STRIDE * (ti.j % acc_repl(ti.len, (uint32_t)(BLOCK * IPT)))];
-    r.acw[0] = ac->and_lo;
-    r.acw[1] = ac->or_lo;
-    r.acw[2] = ac->and_hi;
-    r.acw[3] = ac->or_hi;
-  }
+  // segments of more than BLOCK groups: the remaining group sums (rare)
+  r.pvx = 0;
+  for (uint32_t s = (uint32_t)(BLOCK + tid); s < js; s += BLOCK) r.pvx += a.scnt_in[ti.cbase + s];
 }
 
-template <int NCNT>
+template <int NCNT, int WAVES>
 struct LevelShared {
   uint32_t cnt[NCNT];  // (item, wave) front counts, position order
+  uint64_t pw[WAVES];  // per-wave sums of the tile's prefix loads
   uint32_t nxt[4];     // next-level front counts of the tile, by child tile
   uint64_t red[4];     // child AND/OR of the tile
-  Seg seg[2];          // descriptor of the next tile (double buffer)
+  Seg seg[2];          // descriptors of the next tiles (double buffer)
   uint32_t tile[2];
-  uint64_t prefix;
 };
 
-// Thread 0's claim pipeline: the tile id and descriptor it will publish.
+// Tiles are dealt out statically: workgroup b takes tiles b, b + G,
+// b + 2G, ... (G workgroups); tiles have equal sizes, so the work is even,
+// and no tile id has to come back from an atomic.  Lanes 0-7 of wave 0
+// fetch the descriptor of the tile after next, one dword each, and put it
+// in LDS at the end of the tile.
 struct Claim {
-  uint32_t t;
-  Seg d;
+  uint32_t t;   // the tile after next
+  uint32_t dw;  // lanes 0-7 of wave 0: one dword of its descriptor
 };
+__device__ __forceinline__ uint32_t seg_dword(const Seg *tiles, uint32_t t, uint32_t ntiles,
+                                             int lane) {
+  // lanes 8 and up, and tiles past the end, read 0 (out of range)
+  const rsrc_t r = make_rsrc(tiles + (t < ntiles ? t : 0u), t < ntiles ? (uint32_t)sizeof(Seg) : 0u);
+  return buf_load<uint32_t>(r, (uint32_t)lane * 4u);
+}
 
-// One tile: rank, publish the next tile and start its loads, then write.
+// One tile.  The next tile's loads go out first (a whole tile ahead of
+// their use); then the tile is ranked and written, and the tile after next
+// is published for the following call.
 template <typename KT, bool IDX, int BLOCK, int IPT>
 __device__ __forceinline__ void level_tile(const LevelArgs<KT> &a, const TileInfo &ti,
                                            TileRegs<KT, IPT> &r, TileInfo &tn,
                                            TileRegs<KT, IPT> &rn,
-                                           LevelShared<IPT * (BLOCK / 64)> &sh, int &cur,
-                                           Claim &cl, uint32_t ntiles) {
+                                           LevelShared<IPT * (BLOCK / 64), BLOCK / 64> &sh,
+                                           int &cur, Claim &cin, Claim &cout, uint32_t ntiles) {
   constexpr int WAVES = BLOCK / 64;
   constexpr int TILE = BLOCK * IPT;
   constexpr int NCNT = IPT * WAVES;
   using RT = typename std::conditional<sizeof(KT) == 8, uint64_t, uint32_t>::type;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  tn = tile_info<TILE>(sh.seg[cur ^ 1], sh.tile[cur ^ 1], ntiles);
+  issue_loads<KT, IDX, BLOCK, IPT>(a, tn, rn);
+  // the tile after next: its id and (lanes 0-7) its descriptor
+  cout.t = cin.t + gridDim.x;
+  cin.dw = seg_dword(a.tiles, cin.t, ntiles, lane);
+
   const int bit = (int)(ti.meta & BIT_MASK);
   const uint32_t f = (uint32_t)flip_of(bit, a.w, a.mode, a.desc, (ti.meta & META_SIGN) ? 1 : 0);
   const uint32_t cnt = ti.cnt;
@@ -690,10 +725,18 @@ __device__ __forceinline__ void level_tile(const LevelArgs<KT> &a, const TileInf
     or_hi |= k & mb;
   }
   {
-    const uint64_t al = wave_and_dpp((uint64_t)and_lo | (sizeof(KT) == 8 ? 0ull : ~0ull << 32));
-    const uint64_t ol = wave_or_dpp((uint64_t)or_lo);
-    const uint64_t ah = wave_and_dpp((uint64_t)and_hi | (sizeof(KT) == 8 ? 0ull : ~0ull << 32));
-    const uint64_t oh = wave_or_dpp((uint64_t)or_hi);
+    uint64_t al, ol, ah, oh;
+    if (sizeof(KT) == 8) {
+      al = wave_and_dpp((uint64_t)and_lo);
+      ol = wave_or_dpp((uint64_t)or_lo);
+      ah = wave_and_dpp((uint64_t)and_hi);
+      oh = wave_or_dpp((uint64_t)or_hi);
+    } else {
+      al = (uint64_t)wave_and_dpp32((uint32_t)and_lo) | (~0ull << 32);
+      ol = (uint64_t)wave_or_dpp32((uint32_t)or_lo);
+      ah = (uint64_t)wave_and_dpp32((uint32_t)and_hi) | (~0ull << 32);
+      oh = (uint64_t)wave_or_dpp32((uint32_t)or_hi);
+    }
     if (lane == 0) {
       atomicAnd((unsigned long long *)&sh.red[0], (unsigned long long)al);
       atomicOr((unsigned long long *)&sh.red[1], (unsigned long long)ol);
@@ -701,22 +744,24 @@ __device__ __forceinline__ void level_tile(const LevelArgs<KT> &a, const TileInf
       atomicOr((unsigned long long *)&sh.red[3], (unsigned long long)oh);
     }
   }
-  if (wave == 0) {
-    const uint32_t p = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan_dpp(r.pv), 63);
-    if (lane == 0) sh.prefix = p;
-  }
-  if (tid == 0) {
-    // publish the next tile (claimed and fetched one tile earlier)
-    sh.tile[cur ^ 1] = cl.t;
-    if (cl.t < ntiles) sh.seg[cur ^ 1] = cl.d;
+  {
+    // this wave's share of the tile's front prefix
+    const uint32_t ws =
+        (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan_dpp(r.pv0 + r.pv1), 63);
+    uint64_t wx = 0;
+    if ((ti.j >> 6) > (uint32_t)BLOCK) wx = wave_sum_u64(r.pvx);  // segments of > BLOCK groups
+    if (lane == 0) sh.pw[wave] = (uint64_t)ws + wx;
   }
   __syncthreads();
 
   const uint32_t cv = lane < NCNT ? sh.cnt[lane] : 0u;
   const uint32_t cinc = wave_incl_scan_dpp(cv);
   const uint32_t c1 = (uint32_t)__builtin_amdgcn_readlane((int)cinc, 63);
-  const uint64_t P1 = uni(sh.prefix);
-  if (tid == 0) {
+  uint64_t pacc = 0;
+#pragma unroll
+  for (int w2 = 0; w2 < WAVES; ++w2) pacc += sh.pw[w2];
+  const uint64_t P1 = uni(pacc);
+  if (tid == ACC_THREAD) {
     // An AND word only loses bits and an OR word only gains them, so an
     // atomic whose value the (even stale) read already absorbs is skipped:
     // big segments would otherwise send every tile's atomics to the same
@@ -734,18 +779,9 @@ __device__ __forceinline__ void level_tile(const LevelArgs<KT> &a, const TileInf
     if (ti.lo + cnt == ti.len) a.split[ti.slot] = P1 + c1;
   }
 
-  // start the next tile's loads before this tile's stores: stores and
-  // loads retire in order, so waiting for them later does not wait for
-  // these stores
-  tn = tile_info<TILE>(sh.seg[cur ^ 1], sh.tile[cur ^ 1], ntiles);
-  if (tn.valid) issue_loads<KT, IDX, BLOCK, IPT>(a, tn, rn);
-  if (tid == 0) {
-    cl.t = atomic_add_u32(&a.hdr->grab[a.level], 1u);
-    if (cl.t < ntiles) cl.d = a.tiles[cl.t];
-  }
-
   const uint32_t c2 = cnt - c1;
   const uint64_t P2 = ti.lo - P1;
+  const bool iota = (ti.meta & META_IOTA) != 0;
   // Front key of tile rank r1 -> start + P1 + r1; back key of tile back
   // rank r2 -> end - 1 - P2 - r2.  Each wave's front lanes and back lanes
   // write two contiguous runs; L2 merges the partial lines.
@@ -772,8 +808,9 @@ __device__ __forceinline__ void level_tile(const LevelArgs<KT> &a, const TileInf
     buf_store(fkr, fo * (uint32_t)sizeof(KT), r.key[i]);
     buf_store(bkr, bo * (uint32_t)sizeof(KT), r.key[i]);
     if (IDX) {
-      buf_store(fir, fo * 4u, r.ix[i]);
-      buf_store(bir, bo * 4u, r.ix[i]);
+      const uint32_t ix = r.ix[i] + (iota ? (uint32_t)(ti.lo + q) : 0u);
+      buf_store(fir, fo * 4u, ix);
+      buf_store(bir, bo * 4u, ix);
     }
     rk[i] = front ? r1 : r2;
   }
@@ -817,55 +854,63 @@ __device__ __forceinline__ void level_tile(const LevelArgs<KT> &a, const TileInf
       if (n3) atomicAdd(&sh.nxt[3], n3);
     }
   }
+  if (wave == 0) {
+    // publish the tile after next into this tile's slot (this tile's
+    // descriptor was read at the start of the previous call)
+    if (lane == 0) sh.tile[cur] = cin.t;
+    if (lane < 8) reinterpret_cast<uint32_t *>(&sh.seg[cur])[lane] = cin.dw;
+  }
   __syncthreads();
-  if (tid == 0 && nxt) {
+  if (nxt && wave == CNT_WAVE && lane < 4) {
     // child c's tile j of the next level counts at 2*tile0 + c*nt + j
+    const int k = lane;
+    const uint32_t c = sh.nxt[k];
+    sh.nxt[k] = 0;
     const uint32_t nt = (uint32_t)((ti.len + TILE - 1) / TILE);
-    const uint32_t base[2] = {2 * ti.tile0, 2 * ti.tile0 + nt};
-    const uint32_t j0[2] = {(uint32_t)(P1 / TILE), (uint32_t)(P2 / TILE)};
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const uint32_t c = sh.nxt[k];
-      sh.nxt[k] = 0;
-      const uint32_t jj = j0[k >> 1] + (k & 1);
-      if (c) {
-        atomic_add_u32(&a.tcnt_out[base[k >> 1] + jj], c);
-        atomic_add_u32(&a.scnt_out[base[k >> 1] + (jj >> 6)], c);
-      }
+    const uint32_t base = (k >> 1) ? 2 * ti.tile0 + nt : 2 * ti.tile0;
+    const uint32_t jj = (uint32_t)(((k >> 1) ? P2 : P1) / TILE) + (uint32_t)(k & 1);
+    if (c) {
+      atomic_add_u32(&a.tcnt_out[base + jj], c);
+      atomic_add_u32(&a.scnt_out[base + (jj >> 6)], c);
     }
   }
   cur ^= 1;
 }
 
 // One global level: every live segment is split on its bit.  Workgroups
-// take tiles in increasing order (claimed and fetched a tile ahead, loaded a
-// tile ahead).  A tile's front offset inside its segment comes from the
-// counts that the previous level (or the level-0 count pass) produced for
-// this bit: the sum over the tile's 64-tile group predecessors plus its own
-// group's earlier tiles.  Segments whose bit was reached by skipping are
-// counted by the count pass before the level.  Front keys go to
-// start + prefix, back keys are placed from the segment's right end
-// leftwards, so the back child is stored reversed.  While writing, each
-// tile also counts, for every child tile of the next level, how many keys
-// will go front on bit - 1 (the usual next bit).
+// take tiles in increasing order (claimed two tiles ahead, loaded one tile
+// ahead).  A tile's front offset inside its segment comes from the counts
+// that the previous level (or the count pass) produced for this bit: the
+// sum over the tile's 64-tile group predecessors plus its own group's
+// earlier tiles.  Segments whose bit was reached by skipping are counted by
+// the count pass before the level.  Front keys go to start + prefix, back
+// keys are placed from the segment's right end leftwards, so the back child
+// is stored reversed.  While writing, each tile also counts, for every
+// child tile of the next level, how many keys will go front on bit - 1
+// (the usual next bit).
 template <typename KT, bool IDX, int BLOCK, int IPT>
 __global__ __launch_bounds__(BLOCK) void level_kernel(LevelArgs<KT> a) {
   constexpr int WAVES = BLOCK / 64;
   constexpr int TILE = BLOCK * IPT;
   constexpr int NCNT = IPT * WAVES;
   static_assert(NCNT <= 64, "one count per lane in the per-wave scan");
-  __shared__ LevelShared<NCNT> sh;
+  static_assert(WAVES > CNT_WAVE && BLOCK > ACC_THREAD, "control lanes exist");
+  __shared__ LevelShared<NCNT, WAVES> sh;
   const int tid = threadIdx.x;
   const uint32_t ntiles = (uint32_t)(a.hdr->packed[a.level] & 0xffffffffu);
 
-  Claim cl;
-  cl.t = 0;
+  Claim ca, cb;
+  const uint32_t t0 = blockIdx.x, t1 = blockIdx.x + gridDim.x;
+  ca.t = blockIdx.x + 2 * gridDim.x;
+  cb.t = 0;
+  ca.dw = cb.dw = 0;
+  if (tid < 8) {
+    reinterpret_cast<uint32_t *>(&sh.seg[0])[tid] = seg_dword(a.tiles, t0, ntiles, tid);
+    reinterpret_cast<uint32_t *>(&sh.seg[1])[tid] = seg_dword(a.tiles, t1, ntiles, tid);
+  }
   if (tid == 0) {
-    const uint32_t t = atomic_add_u32(&a.hdr->grab[a.level], 1u);
-    sh.tile[0] = t;
-    if (t < ntiles) sh.seg[0] = a.tiles[t];
-    cl.t = atomic_add_u32(&a.hdr->grab[a.level], 1u);
-    if (cl.t < ntiles) cl.d = a.tiles[cl.t];
+    sh.tile[0] = t0;
+    sh.tile[1] = t1;
     sh.nxt[0] = sh.nxt[1] = sh.nxt[2] = sh.nxt[3] = 0;
     sh.red[0] = ~0ull;
     sh.red[1] = 0;
@@ -876,12 +921,12 @@ __global__ __launch_bounds__(BLOCK) void level_kernel(LevelArgs<KT> a) {
   int cur = 0;
   TileInfo ta = tile_info<TILE>(sh.seg[0], sh.tile[0], ntiles), tb;
   TileRegs<KT, IPT> ra, rb;
-  if (ta.valid) issue_loads<KT, IDX, BLOCK, IPT>(a, ta, ra);
+  issue_loads<KT, IDX, BLOCK, IPT>(a, ta, ra);
   for (;;) {
     if (!ta.valid) break;
-    level_tile<KT, IDX, BLOCK, IPT>(a, ta, ra, tb, rb, sh, cur, cl, ntiles);
+    level_tile<KT, IDX, BLOCK, IPT>(a, ta, ra, tb, rb, sh, cur, ca, cb, ntiles);
     if (!tb.valid) break;
-    level_tile<KT, IDX, BLOCK, IPT>(a, tb, rb, ta, ra, sh, cur, cl, ntiles);
+    level_tile<KT, IDX, BLOCK, IPT>(a, tb, rb, ta, ra, sh, cur, cb, ca, ntiles);
   }
 }
 
