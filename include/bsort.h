@@ -210,7 +210,9 @@ const char *bsort_strerror(int status);
 /* Device status word written by the last call that used this scratch:
  * 0 = fine; bit 0 = a part handed to the in-LDS finish exceeded its capacity
  * (an internal error: the result is invalid); bit 1 = the segment offsets
- * failed the device-side check (nothing was sorted).  Reads
+ * failed the device-side check (nothing was sorted); bit 2 = a level tile's
+ * precomputed count prefix was inconsistent (an internal error: that tile
+ * wrote nothing, the result is invalid).  Reads
  * it synchronously on `stream`.  Returns the word, or a negative status. */
 int bsort_device_status(const void *scratch, void *stream);
 

@@ -43,6 +43,7 @@ constexpr uint32_t META_PRE = 1u << 11;  // the previous level counted `bit` per
 
 constexpr uint32_t STATUS_OVERSIZE = 1u;  // a finish entry larger than the workgroup's capacity
 constexpr uint32_t STATUS_BAD_OFFSETS = 2u;
+constexpr uint32_t STATUS_BAD_COUNTS = 4u;  // a tile's precomputed prefix exceeded its position
 
 constexpr int MAX_LEVELS = 66;
 
@@ -130,8 +131,6 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
 // 32-bit lane offsets.  Loads past the range return 0 and stores past it
 // are dropped by the hardware.
 using rsrc_t = __amdgpu_buffer_rsrc_t;
-// an element offset past any descriptor's range (x 8 bytes still < 2^31)
-constexpr uint32_t OOR_ELEMS = 0x0FFFFFFFu;
 __device__ __forceinline__ rsrc_t make_rsrc(const void *p, uint32_t bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes,
                                            0x00020000);
@@ -782,35 +781,33 @@ __device__ __forceinline__ void level_tile(const LevelArgs<KT> &a, const TileInf
   const uint32_t c2 = cnt - c1;
   const uint64_t P2 = ti.lo - P1;
   const bool iota = (ti.meta & META_IOTA) != 0;
-  // Front key of tile rank r1 -> start + P1 + r1; back key of tile back
-  // rank r2 -> end - 1 - P2 - r2.  Each wave's front lanes and back lanes
-  // write two contiguous runs; L2 merges the partial lines.
-  const rsrc_t fkr = make_rsrc(a.keys_out + (ti.start + P1), c1 * (uint32_t)sizeof(KT));
-  const rsrc_t bkr = make_rsrc(a.keys_out + (end - P2 - c2), c2 * (uint32_t)sizeof(KT));
-  const rsrc_t fir = make_rsrc(IDX ? a.idx_out + (ti.start + P1) : nullptr, IDX ? c1 * 4u : 0u);
-  const rsrc_t bir = make_rsrc(IDX ? a.idx_out + (end - P2 - c2) : nullptr, IDX ? c2 * 4u : 0u);
+  // Within the tile every front rank is below c1 and every back rank below
+  // c2; with P1 <= lo (no more fronts before the tile than keys) both runs
+  // lie inside the segment, so the per-lane stores below need no bounds.
+  // A prefix that broke this would be an internal error: the tile then
+  // writes nothing and the status word says so.
+  const bool sane = P1 <= ti.lo;
+  if (!sane && tid == ACC_THREAD) atomic_or_u32(&a.hdr->status, STATUS_BAD_COUNTS);
+  const uint32_t wcnt = sane ? cnt : 0u;
+  KT *const kseg = a.keys_out + ti.start;
+  uint32_t *const iseg = IDX ? a.idx_out + ti.start : nullptr;
   uint32_t rk[IPT];  // rank within the key's own side of this tile
 #pragma unroll
   for (int i = 0; i < IPT; ++i) {
     const uint32_t q = (uint32_t)(i * BLOCK + tid);
-    const bool valid = q < cnt;
     const bool front = (fbits >> i) & 1u;
     const uint64_t fm = __ballot(front);
     const uint32_t base = (uint32_t)__builtin_amdgcn_readlane((int)(cinc - cv), i * WAVES + wave);
     const uint32_t r1 = base + lanes_below(fm);
     const uint32_t r2 = q - r1;
-    // both stores are issued by every lane with a uniform descriptor; the
-    // side a lane does not belong to gets an out-of-range offset, which the
-    // hardware drops (a per-lane choice of descriptor would make the
-    // compiler loop over the distinct descriptors)
-    const uint32_t fo = front ? r1 : OOR_ELEMS;
-    const uint32_t bo = (valid && !front) ? (c2 - 1 - r2) : OOR_ELEMS;
-    buf_store(fkr, fo * (uint32_t)sizeof(KT), r.key[i]);
-    buf_store(bkr, bo * (uint32_t)sizeof(KT), r.key[i]);
-    if (IDX) {
-      const uint32_t ix = r.ix[i] + (iota ? (uint32_t)(ti.lo + q) : 0u);
-      buf_store(fir, fo * 4u, ix);
-      buf_store(bir, bo * 4u, ix);
+    // front key of tile rank r1 -> P1 + r1 in the segment; back key of
+    // tile back rank r2 -> len - 1 - P2 - r2 (the back child runs right to
+    // left).  One store per array, per-lane addresses: each wave's front
+    // lanes and back lanes write two contiguous runs, which L2 merges.
+    if (q < wcnt) {
+      const uint64_t rel = front ? (P1 + r1) : (ti.len - 1 - P2 - r2);
+      kseg[rel] = r.key[i];
+      if (IDX) iseg[rel] = r.ix[i] + (iota ? (uint32_t)(ti.lo + q) : 0u);
     }
     rk[i] = front ? r1 : r2;
   }
