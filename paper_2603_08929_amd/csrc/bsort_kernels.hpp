@@ -11,16 +11,22 @@
 // takes how many front keys precede the tile from per-tile counts made
 // before the level (by the previous level while it wrote the keys, or by a
 // count pass for segments whose bit was reached by skipping), and scatters
-// the tile as two contiguous runs.  The split point of a segment is not needed before its back part is
-// written: back keys are placed from the segment's right end leftwards, so
-// the back child is stored in reverse order and the next level reads it
-// right to left (a per-segment "rev" flag).  The same pass folds the AND and
+// the tile as two contiguous runs.  The split point of a segment is not
+// needed before its back part is written: back keys are placed from the
+// segment's right end leftwards, so the back child is stored in reverse
+// order and the next level reads it right to left (a per-segment "rev"
+// flag).  The same pass folds the AND and
 // OR of each child's keys into per-child accumulators, from which the next
 // level picks the child's next bit (bits on which a child is constant are
 // skipped: a split with an empty side is the identity) or retires it.
 // Segments of at most T keys finish all their remaining bits inside one
 // workgroup, in LDS (the hybrid switch to a cache-resident routine that the
 // paper proposes in Sections IV-B and V).
+//
+// Workgroups take tiles round-robin; every load of the next tile is issued
+// on every path (empty ranges where there is nothing to read), so that the
+// in-order counter of outstanding loads lets the current tile's work wait
+// only for its own data.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -207,7 +213,7 @@ __device__ __forceinline__ uint32_t wave_or_dpp32(uint32_t v) {
 }
 __device__ __forceinline__ uint64_t wave_and_dpp(uint64_t v) {
   const uint32_t lo = wave_and_dpp32((uint32_t)v);
-  const uint32_t hi = ((v >> 32) == 0xffffffffull) && false ? 0xffffffffu : wave_and_dpp32((uint32_t)(v >> 32));
+  const uint32_t hi = wave_and_dpp32((uint32_t)(v >> 32));
   return (uint64_t)lo | ((uint64_t)hi << 32);
 }
 __device__ __forceinline__ uint64_t wave_or_dpp(uint64_t v) {
@@ -759,6 +765,10 @@ __device__ __forceinline__ void level_tile(const LevelArgs<KT> &a, const TileInf
   uint64_t pacc = 0;
 #pragma unroll
   for (int w2 = 0; w2 < WAVES; ++w2) pacc += sh.pw[w2];
+  // the front flags are re-read from this register below: without the
+  // empty asm the compiler keeps every item's lane mask alive in scalar
+  // registers across the barrier, and spills
+  asm volatile("" : "+v"(fbits));
   const uint64_t P1 = uni(pacc);
   if (tid == ACC_THREAD) {
     // An AND word only loses bits and an OR word only gains them, so an
@@ -1066,7 +1076,10 @@ __global__ __launch_bounds__(BLOCK) void finish_kernel(FinishArgs<KT> a) {
   using RT = typename std::conditional<sizeof(KT) == 8, uint64_t, uint32_t>::type;
   __shared__ RT s_code[T];
   __shared__ uint32_t s_idx[IDX ? T : 1];
-  __shared__ uint32_t s_hist[NH];
+  // (digit, thread) counters of the 4-byte-and-narrower passes, or the
+  // (digit, chunk) histogram of the 8-byte passes
+  __shared__ uint32_t s_cnt[sizeof(KT) <= 4 ? 16 * BLOCK : NH];
+  uint32_t *const s_hist = s_cnt;
   __shared__ uint64_t s_red[2][WAVES];
   __shared__ uint32_t s_wsum[WAVES];
   __shared__ Seg s_seg;
@@ -1152,76 +1165,154 @@ __global__ __launch_bounds__(BLOCK) void finish_kernel(FinishArgs<KT> a) {
           m &= ~(RT)(rmask << lo);
         }
       }
-      for (int sh = 0; sh < nbits; sh += RB) {
-#pragma unroll
-        for (int h = 0; h < HPT; ++h) {
-          const int x = h * BLOCK + tid;
-          if (x < NH) s_hist[x] = 0;
-        }
-        __syncthreads();
-        uint32_t dg[IPT], rk[IPT];
+      if constexpr (sizeof(KT) <= 4) {
+        // Stable LSD passes of CRB bits over the packed codes, ranked in
+        // blocked order (thread t holds positions t*IPT .. t*IPT + IPT - 1):
+        // each item bumps its (digit, thread) counter in LDS in position
+        // order -- an LDS atomic that returns the count so far -- then an
+        // exclusive scan over the counters in (digit, thread) order turns
+        // every counter into its base, and an item's rank is its counter's
+        // base plus its count so far.  Positions past the segment's end
+        // carry the largest code and stay last.
+        constexpr int CRB = 4, CDIG = 1 << CRB;
+        const RT maxc = (nbits >= (int)(8 * sizeof(RT))) ? (RT)~(RT)0 : (RT)(((RT)1 << nbits) - 1);
 #pragma unroll
         for (int i = 0; i < IPT; ++i) {
-          const bool valid = (uint32_t)(i * BLOCK + tid) < len;
-          const uint32_t d = (uint32_t)(code[i] >> sh) & (uint32_t)(NDIG - 1);
-          // lanes of this 64-key chunk holding the same digit
-          uint64_t peers = __ballot(valid);
-#pragma unroll
-          for (int k = 0; k < RB; ++k) {
-            const uint64_t bk = __ballot((d >> k) & 1u);
-            peers &= ((d >> k) & 1u) ? bk : ~bk;
-          }
-          dg[i] = d;
-          rk[i] = (uint32_t)__popcll(peers & lt);
-          if (valid && (peers & lt) == 0)
-            s_hist[d * NCH + i * WAVES + wave] = (uint32_t)__popcll(peers);
+          const uint32_t p = (uint32_t)(i * BLOCK + tid);
+          s_code[p] = p < len ? code[i] : maxc;
+          if (IDX) s_idx[p] = ix[i];
         }
-        __syncthreads();
-        // exclusive scan of the histogram in (digit, chunk) order
-        {
-          uint32_t v[HPT];
-          uint32_t sum = 0;
-#pragma unroll
-          for (int h = 0; h < HPT; ++h) {
-            const int x = tid * HPT + h;
-            v[h] = x < NH ? s_hist[x] : 0u;
-            sum += v[h];
-          }
-          const uint32_t inc = wave_incl_scan_dpp(sum);
-          if (lane == 63) s_wsum[wave] = inc;
+        for (int sh = 0; sh < nbits; sh += CRB) {
           __syncthreads();
-          uint32_t base = 0;
+          RT c[IPT];
+          uint32_t x[IPT], loc[IPT];
 #pragma unroll
-          for (int w2 = 0; w2 < WAVES; ++w2)
-            if (w2 < wave) base += s_wsum[w2];
-          uint32_t ex = base + inc - sum;
+          for (int j = 0; j < IPT; ++j) {
+            c[j] = s_code[tid * IPT + j];
+            if (IDX) x[j] = s_idx[tid * IPT + j];
+          }
+#pragma unroll
+          for (int d = 0; d < CDIG; ++d) s_cnt[d * BLOCK + tid] = 0;
+#pragma unroll
+          for (int j = 0; j < IPT; ++j) {
+            const uint32_t d = (uint32_t)(c[j] >> sh) & (uint32_t)(CDIG - 1);
+            loc[j] = atomicAdd(&s_cnt[d * BLOCK + tid], 1u);
+          }
+          __syncthreads();
+          {
+            // exclusive scan of the CDIG * BLOCK counters, CDIG per thread
+            uint32_t v[CDIG];
+            uint32_t sum = 0;
+#pragma unroll
+            for (int k = 0; k < CDIG; ++k) {
+              v[k] = s_cnt[tid * CDIG + k];
+              sum += v[k];
+            }
+            const uint32_t inc = wave_incl_scan_dpp(sum);
+            if (lane == 63) s_wsum[wave] = inc;
+            __syncthreads();
+            uint32_t ex = inc - sum;
+#pragma unroll
+            for (int w2 = 0; w2 < WAVES; ++w2)
+              if (w2 < wave) ex += s_wsum[w2];
+#pragma unroll
+            for (int k = 0; k < CDIG; ++k) {
+              s_cnt[tid * CDIG + k] = ex;
+              ex += v[k];
+            }
+          }
+          __syncthreads();
+#pragma unroll
+          for (int j = 0; j < IPT; ++j) {
+            const uint32_t d = (uint32_t)(c[j] >> sh) & (uint32_t)(CDIG - 1);
+            const uint32_t dst = s_cnt[d * BLOCK + tid] + loc[j];
+            s_code[dst] = c[j];
+            if (IDX) s_idx[dst] = x[j];
+          }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < IPT; ++i) {
+          const uint32_t p = (uint32_t)(i * BLOCK + tid);
+          code[i] = s_code[p];
+          if (IDX) ix[i] = s_idx[p];
+        }
+        __syncthreads();
+      } else {
+        // 8-byte keys (up to 60 varying bits) take fewer, wider passes: lanes
+        // holding the same RB-bit digit found with RB ballots, per-(digit,
+        // chunk) counts and one block-wide scan.
+        for (int sh = 0; sh < nbits; sh += RB) {
 #pragma unroll
           for (int h = 0; h < HPT; ++h) {
-            const int x = tid * HPT + h;
-            if (x < NH) s_hist[x] = ex;
-            ex += v[h];
+            const int x = h * BLOCK + tid;
+            if (x < NH) s_hist[x] = 0;
           }
-        }
-        __syncthreads();
+          __syncthreads();
+          uint32_t dg[IPT], rk[IPT];
 #pragma unroll
-        for (int i = 0; i < IPT; ++i) {
-          const uint32_t p = (uint32_t)(i * BLOCK + tid);
-          if (p < len) {
-            const uint32_t dst = s_hist[dg[i] * NCH + i * WAVES + wave] + rk[i];
-            s_code[dst] = code[i];
-            if (IDX) s_idx[dst] = ix[i];
-          }
-        }
-        __syncthreads();
+          for (int i = 0; i < IPT; ++i) {
+            const bool valid = (uint32_t)(i * BLOCK + tid) < len;
+            const uint32_t d = (uint32_t)(code[i] >> sh) & (uint32_t)(NDIG - 1);
+            // lanes of this 64-key chunk holding the same digit
+            uint64_t peers = __ballot(valid);
 #pragma unroll
-        for (int i = 0; i < IPT; ++i) {
-          const uint32_t p = (uint32_t)(i * BLOCK + tid);
-          if (p < len) {
-            code[i] = s_code[p];
-            if (IDX) ix[i] = s_idx[p];
+            for (int k = 0; k < RB; ++k) {
+              const uint64_t bk = __ballot((d >> k) & 1u);
+              peers &= ((d >> k) & 1u) ? bk : ~bk;
+            }
+            dg[i] = d;
+            rk[i] = (uint32_t)__popcll(peers & lt);
+            if (valid && (peers & lt) == 0)
+              s_hist[d * NCH + i * WAVES + wave] = (uint32_t)__popcll(peers);
           }
+          __syncthreads();
+          // exclusive scan of the histogram in (digit, chunk) order
+          {
+            uint32_t v[HPT];
+            uint32_t sum = 0;
+#pragma unroll
+            for (int h = 0; h < HPT; ++h) {
+              const int x = tid * HPT + h;
+              v[h] = x < NH ? s_hist[x] : 0u;
+              sum += v[h];
+            }
+            const uint32_t inc = wave_incl_scan_dpp(sum);
+            if (lane == 63) s_wsum[wave] = inc;
+            __syncthreads();
+            uint32_t base = 0;
+#pragma unroll
+            for (int w2 = 0; w2 < WAVES; ++w2)
+              if (w2 < wave) base += s_wsum[w2];
+            uint32_t ex = base + inc - sum;
+#pragma unroll
+            for (int h = 0; h < HPT; ++h) {
+              const int x = tid * HPT + h;
+              if (x < NH) s_hist[x] = ex;
+              ex += v[h];
+            }
+          }
+          __syncthreads();
+#pragma unroll
+          for (int i = 0; i < IPT; ++i) {
+            const uint32_t p = (uint32_t)(i * BLOCK + tid);
+            if (p < len) {
+              const uint32_t dst = s_hist[dg[i] * NCH + i * WAVES + wave] + rk[i];
+              s_code[dst] = code[i];
+              if (IDX) s_idx[dst] = ix[i];
+            }
+          }
+          __syncthreads();
+#pragma unroll
+          for (int i = 0; i < IPT; ++i) {
+            const uint32_t p = (uint32_t)(i * BLOCK + tid);
+            if (p < len) {
+              code[i] = s_code[p];
+              if (IDX) ix[i] = s_idx[p];
+            }
+          }
+          __syncthreads();
         }
-        __syncthreads();
       }
       // unpack: the sorted bits back into place, the shared bits around them
       {
