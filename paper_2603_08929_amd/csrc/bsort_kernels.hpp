@@ -604,7 +604,7 @@ struct TileRegs {
   uint32_t ix[IPT];
   uint32_t pv0, pv1;  // front keys of earlier tiles: a group sum and a tile count
   uint64_t pvx;       // the rest, for segments of more than BLOCK tile groups
-  uint64_t acw[4];    // ACC_THREAD: the segment's child AND/OR words as read
+  uint32_t acd;       // lanes 0-7: one dword of the segment's child AND/OR words
 };
 
 // Control work is spread over waves so that no single wave waits on all of
@@ -637,11 +637,11 @@ __device__ __forceinline__ void issue_loads(const LevelArgs<KT> &a, const TileIn
   r.pv0 = buf_load<uint32_t>(gs, (uint32_t)tid * 4u);
   r.pv1 = buf_load<uint32_t>(ts, (uint32_t)tid * 4u);
   // the segment's child AND/OR words as they stand (for the atomics that
-  // the tile may skip), read by every thread
-  const uint32_t ai = v ? ti.tile0 + ACC_STRIDE * (ti.j % acc_repl(ti.len, (uint32_t)(BLOCK * IPT))) : 0u;
+  // the tile may skip): lanes 0-7 read one dword each, published in LDS
+  const uint32_t ai =
+      v ? ti.tile0 + ACC_STRIDE * (ti.j % acc_repl(ti.len, (uint32_t)(BLOCK * IPT))) : 0u;
   const rsrc_t ar = make_rsrc(a.acc + ai, v ? (uint32_t)sizeof(AccRep) : 0u);
-#pragma unroll
-  for (int k = 0; k < 4; ++k) r.acw[k] = buf_load<uint64_t>(ar, (uint32_t)k * 8u);
+  r.acd = buf_load<uint32_t>(ar, (uint32_t)(tid & 63) * 4u);
   // storage of the tile: [sbase, sbase + cnt); logical q is at sbase + q
   // (forward) or sbase + cnt - 1 - q (reversed)
   const uint64_t end = ti.start + ti.len;
@@ -666,6 +666,7 @@ struct LevelShared {
   uint64_t pw[WAVES];  // per-wave sums of the tile's prefix loads
   uint32_t nxt[4];     // next-level front counts of the tile, by child tile
   uint64_t red[4];     // child AND/OR of the tile
+  uint64_t acw[2][4];  // the segment's child AND/OR words as read, per tile slot
   Seg seg[2];          // descriptors of the next tiles (double buffer)
   uint32_t tile[2];
 };
@@ -781,10 +782,11 @@ __device__ __forceinline__ void level_tile(const LevelArgs<KT> &a, const TileInf
     sh.red[1] = 0;
     sh.red[2] = ~0ull;
     sh.red[3] = 0;
-    if ((r.acw[0] & al) != r.acw[0]) atomic_and_u64(&ac->and_lo, al);
-    if ((r.acw[1] | ol) != r.acw[1]) atomic_or_u64(&ac->or_lo, ol);
-    if ((r.acw[2] & ah) != r.acw[2]) atomic_and_u64(&ac->and_hi, ah);
-    if ((r.acw[3] | oh) != r.acw[3]) atomic_or_u64(&ac->or_hi, oh);
+    const uint64_t *acw = sh.acw[cur];
+    if ((acw[0] & al) != acw[0]) atomic_and_u64(&ac->and_lo, al);
+    if ((acw[1] | ol) != acw[1]) atomic_or_u64(&ac->or_lo, ol);
+    if ((acw[2] & ah) != acw[2]) atomic_and_u64(&ac->and_hi, ah);
+    if ((acw[3] | oh) != acw[3]) atomic_or_u64(&ac->or_hi, oh);
     if (ti.lo + cnt == ti.len) a.split[ti.slot] = P1 + c1;
   }
 
@@ -863,9 +865,13 @@ __device__ __forceinline__ void level_tile(const LevelArgs<KT> &a, const TileInf
   }
   if (wave == 0) {
     // publish the tile after next into this tile's slot (this tile's
-    // descriptor was read at the start of the previous call)
+    // descriptor was read at the start of the previous call), and the next
+    // tile's AND/OR words into its slot
     if (lane == 0) sh.tile[cur] = cin.t;
-    if (lane < 8) reinterpret_cast<uint32_t *>(&sh.seg[cur])[lane] = cin.dw;
+    if (lane < 8) {
+      reinterpret_cast<uint32_t *>(&sh.seg[cur])[lane] = cin.dw;
+      reinterpret_cast<uint32_t *>(sh.acw[cur ^ 1])[lane] = rn.acd;
+    }
   }
   __syncthreads();
   if (nxt && wave == CNT_WAVE && lane < 4) {
@@ -929,6 +935,7 @@ __global__ __launch_bounds__(BLOCK) void level_kernel(LevelArgs<KT> a) {
   TileInfo ta = tile_info<TILE>(sh.seg[0], sh.tile[0], ntiles), tb;
   TileRegs<KT, IPT> ra, rb;
   issue_loads<KT, IDX, BLOCK, IPT>(a, ta, ra);
+  if (tid < 8) reinterpret_cast<uint32_t *>(sh.acw[0])[tid] = ra.acd;  // seen after the first barrier
   for (;;) {
     if (!ta.valid) break;
     level_tile<KT, IDX, BLOCK, IPT>(a, ta, ra, tb, rb, sh, cur, ca, cb, ntiles);
