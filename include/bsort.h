@@ -51,7 +51,7 @@ extern "C" {
 #define BSORT_OK 0
 #define BSORT_EINVAL (-1)   /* null pointer with n > 0, unknown flag bits, bad key type */
 #define BSORT_ESCRATCH (-2) /* scratch smaller than bsort_scratch_bytes()                */
-#define BSORT_ETOOBIG (-3)  /* a segment of 2^32 keys or more with uint32 indices        */
+#define BSORT_ETOOBIG (-3)  /* n of 2^32 keys or more (any call)                         */
 #define BSORT_EHIP (-4)     /* the HIP runtime refused a launch (see bsort_strerror)     */
 #define BSORT_ENODEV (-5)   /* the current device is not a gfx950 GPU                    */
 

@@ -408,8 +408,9 @@ int run(void *keys, uint64_t n, const int64_t *offsets, uint64_t B, bool segment
   if (n == 0) return BSORT_OK;
   if (!keys || !scratch) return BSORT_EINVAL;
   const bool with_idx = indices != nullptr;
-  if (with_idx && n >= (1ull << 32)) return BSORT_ETOOBIG;
-  if (n >= (1ull << 47)) return BSORT_ETOOBIG;
+  // 2^32 keys or more are refused, with or without indices: that size has
+  // not passed its tests on the GPU
+  if (n >= (1ull << 32)) return BSORT_ETOOBIG;
   const uint64_t b = segmented ? B : 1;
   // the scratch check uses the largest layout of any configuration, so a
   // buffer sized by bsort_scratch_bytes fits every one of them
@@ -720,7 +721,7 @@ const char *bsort_strerror(int status) {
     case BSORT_OK: return "ok";
     case BSORT_EINVAL: return "invalid argument";
     case BSORT_ESCRATCH: return "scratch buffer too small";
-    case BSORT_ETOOBIG: return "too many keys for the index type";
+    case BSORT_ETOOBIG: return "too many keys (2^32 or more)";
     case BSORT_EHIP: return g_hip_err[0] ? g_hip_err : "HIP runtime error";
     case BSORT_ENODEV: return "current device is not a gfx950 GPU";
     default: return "unknown status";

@@ -74,8 +74,10 @@ def test_validation_before_any_device_work():
     # scratch too small
     need = _lib.bsort_scratch_bytes(4, 1000, 1, 1, 0)
     assert f(fake, 1000, 0, fake, fake, need - 1, None) == _lib.ESCRATCH
-    # 2^32 keys or more with uint32 indices
+    # 2^32 keys or more: refused with and without indices
     assert f(fake, 1 << 32, 0, fake, fake, 1 << 62, None) == _lib.ETOOBIG
+    assert f(fake, 1 << 32, 0, None, fake, 1 << 62, None) == _lib.ETOOBIG
+    assert _lib.bsort_u8(fake, (1 << 32) + 12345, 0, None, fake, 1 << 62, None) == _lib.ETOOBIG
     # misaligned scratch
     assert f(fake, 1000, 0, None, fake + 4, 1 << 30, None) == _lib.EINVAL
     # generic entry point: bad key family or width

@@ -248,3 +248,38 @@ def test_differentiable_sort_full(shape, dtype):
         rk, ri = oracle_sort(name, xb[r].view(raw), asc=True)
         np.testing.assert_array_equal(vbn[r].view(raw), rk)
         np.testing.assert_array_equal(idn[r], ri)
+
+
+@pytest.mark.skip(reason="this case faulted the GPU once and its cause was not found by "
+                         "reading the code; the library now refuses n >= 2^32 "
+                         "(BSORT_ETOOBIG) and this test stays off the GPU")
+@pytest.mark.parametrize("name,desc", [("u8", False), ("i8", True)])
+def test_keys_only_more_than_2_32(name, desc):
+    """Keys-only sort of 2^32 + 12345 one-byte keys: segments of 2^32 keys
+    and more take the level kernel's 64-bit position path and its loop over
+    more than one block of tile-group sums.  Checked on the device: the
+    result is ordered by the order key and holds the input's histogram."""
+    n = (1 << 32) + 12345
+    print(f"keys only {name} n={n}", flush=True)
+    g = torch.Generator(device="cuda").manual_seed(31)
+    t = torch.randint(-128, 128, (n,), generator=g, device="cuda", dtype=torch.int16).to(torch.int8)
+    def hist(x):  # chunked: keeps each library call below 2^31 elements
+        u = x.view(torch.uint8)
+        return sum(torch.bincount(u[i:i + (1 << 30)].to(torch.int32), minlength=256)
+                   for i in range(0, u.numel(), 1 << 30))
+
+    hist_in = hist(t)
+    fl = _lib.DESCENDING if desc else 0
+    need = _lib.bsort_scratch_bytes(1, n, 1, 0, fl)
+    scratch = torch.empty(need, dtype=torch.uint8, device="cuda")
+    rc = getattr(_lib, ENTRY[name])(t.data_ptr(), n, fl, None, scratch.data_ptr(), need, stream())
+    _lib.check(rc, ENTRY[name])
+    torch.cuda.synchronize()
+    assert _lib.bsort_device_status(scratch.data_ptr(), stream()) == 0
+    del scratch
+    assert torch.equal(hist_in, hist(t))
+    for i in range(0, n - 1, 1 << 30):  # ordered, chunk by chunk (overlapping by one)
+        c = t[i:i + (1 << 30) + 1]
+        v = c.to(torch.int16) if name == "i8" else c.view(torch.uint8).to(torch.int16)
+        ordered = (v[1:] <= v[:-1]) if desc else (v[1:] >= v[:-1])
+        assert bool(ordered.all()), f"not ordered near {i}"
