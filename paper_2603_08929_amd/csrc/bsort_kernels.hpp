@@ -1061,6 +1061,14 @@ __device__ __forceinline__ KT key_of_rank_word(KT u, int w, int mode, int desc) 
   return (KT)(u ^ m);
 }
 
+// Waves per SIMD the finish kernel is built for: narrow keys with at most
+// 8192 per block are held to 128 registers so that two blocks share a CU
+// (their LDS fits twice); the rest take what they need.
+template <typename KT>
+constexpr int finish_waves_per_eu(int block, int ipt) {
+  return (sizeof(KT) <= 4 && block * ipt <= 8192) ? 4 : 1;
+}
+
 // One workgroup per segment of at most BLOCK*IPT keys: the keys are loaded
 // once, all remaining bits are resolved in LDS, and the final keys and
 // indices go to the caller's buffers (the switch to a cache-resident routine
@@ -1073,7 +1081,9 @@ __device__ __forceinline__ KT key_of_rank_word(KT u, int w, int mode, int desc) 
 // digit), per-(digit, chunk) counts and one block-wide scan.  The constant
 // bits are put back at the end.
 template <typename KT, bool IDX, int BLOCK, int IPT, int RB>
-__global__ __launch_bounds__(BLOCK) void finish_kernel(FinishArgs<KT> a) {
+__global__ __launch_bounds__(BLOCK)
+__attribute__((amdgpu_waves_per_eu(finish_waves_per_eu<KT>(BLOCK, IPT))))
+void finish_kernel(FinishArgs<KT> a) {
   constexpr int WAVES = BLOCK / 64;
   constexpr int T = BLOCK * IPT;
   constexpr int NCH = IPT * WAVES;  // 64-key chunks, in position order
@@ -1081,15 +1091,27 @@ __global__ __launch_bounds__(BLOCK) void finish_kernel(FinishArgs<KT> a) {
   constexpr int NH = NDIG * NCH;
   constexpr int HPT = (NH + BLOCK - 1) / BLOCK;  // histogram entries per thread
   using RT = typename std::conditional<sizeof(KT) == 8, uint64_t, uint32_t>::type;
+  // LDS: the codes, the indices, then the (digit, thread) counters of the
+  // 4-byte-and-narrower passes (two 16-bit counters a word) or the (digit,
+  // chunk) histogram of the 8-byte passes.  For the narrow keys the segment
+  // record and the AND/OR partials live in the counter words, which are
+  // unused until the first pass, and the per-wave scan totals in the code
+  // words, which every pass has read into registers before it writes them;
+  // so two 8192-key blocks fit one CU's LDS.
+  constexpr bool NARROW = sizeof(KT) <= 4;
+  constexpr int CNTW = NARROW ? 8 * BLOCK : NH;
+  constexpr int SEGW = (int)(sizeof(Seg) / 4);
+  constexpr int XW = SEGW + 4 * WAVES + WAVES;  // segment record, AND/OR partials, scan totals
   __shared__ RT s_code[T];
   __shared__ uint32_t s_idx[IDX ? T : 1];
-  // (digit, thread) counters of the 4-byte-and-narrower passes, or the
-  // (digit, chunk) histogram of the 8-byte passes
-  __shared__ uint32_t s_cnt[sizeof(KT) <= 4 ? 16 * BLOCK : NH];
+  __shared__ __attribute__((aligned(16))) uint32_t s_cnt[CNTW + (NARROW ? 0 : XW)];
+  static_assert(!NARROW || CNTW >= SEGW + 4 * WAVES, "segment record and partials fit the counters");
   uint32_t *const s_hist = s_cnt;
-  __shared__ uint64_t s_red[2][WAVES];
-  __shared__ uint32_t s_wsum[WAVES];
-  __shared__ Seg s_seg;
+  Seg &s_seg = *reinterpret_cast<Seg *>(NARROW ? s_cnt : s_cnt + CNTW);
+  uint64_t(*const s_red)[WAVES] =
+      reinterpret_cast<uint64_t(*)[WAVES]>(s_cnt + (NARROW ? SEGW : CNTW + SEGW));
+  uint32_t *const s_wsum =
+      NARROW ? reinterpret_cast<uint32_t *>(s_code) : s_cnt + CNTW + SEGW + 4 * WAVES;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const uint32_t nf = a.hdr->n_finish;
@@ -1180,8 +1202,13 @@ __global__ __launch_bounds__(BLOCK) void finish_kernel(FinishArgs<KT> a) {
         // exclusive scan over the counters in (digit, thread) order turns
         // every counter into its base, and an item's rank is its counter's
         // base plus its count so far.  Positions past the segment's end
-        // carry the largest code and stay last.
-        constexpr int CRB = 4, CDIG = 1 << CRB;
+        // carry the largest code and stay last.  Digit d's counter of thread
+        // t is the (d >> 3) half of word (d & 7) * BLOCK + t: one scan of the
+        // words in (word, thread) order yields, in the low halves, the bases
+        // of digits 0..7 and, in the high halves, those of digits 8..15 less
+        // the count of digits 0..7 (the low half of the total).
+        constexpr int CRB = 4, CDIG = 1 << CRB, CW = CDIG / 2;
+        static_assert(T < 65536, "16-bit counter halves");
         const RT maxc = (nbits >= (int)(8 * sizeof(RT))) ? (RT)~(RT)0 : (RT)(((RT)1 << nbits) - 1);
 #pragma unroll
         for (int i = 0; i < IPT; ++i) {
@@ -1199,32 +1226,37 @@ __global__ __launch_bounds__(BLOCK) void finish_kernel(FinishArgs<KT> a) {
             if (IDX) x[j] = s_idx[tid * IPT + j];
           }
 #pragma unroll
-          for (int d = 0; d < CDIG; ++d) s_cnt[d * BLOCK + tid] = 0;
+          for (int d = 0; d < CW; ++d) s_cnt[d * BLOCK + tid] = 0;
 #pragma unroll
           for (int j = 0; j < IPT; ++j) {
             const uint32_t d = (uint32_t)(c[j] >> sh) & (uint32_t)(CDIG - 1);
-            loc[j] = atomicAdd(&s_cnt[d * BLOCK + tid], 1u);
+            const uint32_t hs = (d >> 3) << 4;
+            loc[j] = (atomicAdd(&s_cnt[(d & (CW - 1)) * BLOCK + tid], 1u << hs) >> hs) & 0xffffu;
           }
           __syncthreads();
+          uint32_t lowtot;
           {
-            // exclusive scan of the CDIG * BLOCK counters, CDIG per thread
-            uint32_t v[CDIG];
+            uint32_t v[CW];
             uint32_t sum = 0;
 #pragma unroll
-            for (int k = 0; k < CDIG; ++k) {
-              v[k] = s_cnt[tid * CDIG + k];
+            for (int k = 0; k < CW; ++k) {
+              v[k] = s_cnt[tid * CW + k];
               sum += v[k];
             }
             const uint32_t inc = wave_incl_scan_dpp(sum);
             if (lane == 63) s_wsum[wave] = inc;
             __syncthreads();
-            uint32_t ex = inc - sum;
+            uint32_t ex = inc - sum, tot = 0;
 #pragma unroll
-            for (int w2 = 0; w2 < WAVES; ++w2)
-              if (w2 < wave) ex += s_wsum[w2];
+            for (int w2 = 0; w2 < WAVES; ++w2) {
+              const uint32_t ws = s_wsum[w2];
+              if (w2 < wave) ex += ws;
+              tot += ws;
+            }
+            lowtot = tot & 0xffffu;
 #pragma unroll
-            for (int k = 0; k < CDIG; ++k) {
-              s_cnt[tid * CDIG + k] = ex;
+            for (int k = 0; k < CW; ++k) {
+              s_cnt[tid * CW + k] = ex;
               ex += v[k];
             }
           }
@@ -1232,7 +1264,9 @@ __global__ __launch_bounds__(BLOCK) void finish_kernel(FinishArgs<KT> a) {
 #pragma unroll
           for (int j = 0; j < IPT; ++j) {
             const uint32_t d = (uint32_t)(c[j] >> sh) & (uint32_t)(CDIG - 1);
-            const uint32_t dst = s_cnt[d * BLOCK + tid] + loc[j];
+            const uint32_t wv = s_cnt[(d & (CW - 1)) * BLOCK + tid];
+            const uint32_t base = (d >> 3) ? (wv >> 16) + lowtot : (wv & 0xffffu);
+            const uint32_t dst = base + loc[j];
             s_code[dst] = c[j];
             if (IDX) s_idx[dst] = x[j];
           }
