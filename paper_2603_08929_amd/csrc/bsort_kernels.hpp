@@ -34,6 +34,8 @@
 
 #include <type_traits>
 
+#include <cstddef>
+
 namespace bsort {
 
 enum : int { MODE_U = 0, MODE_I = 1, MODE_F = 2 };
@@ -498,12 +500,26 @@ __global__ void plan_kernel(PlanArgs a) {
       const Seg p = a.live[q];
       uint64_t and_lo = ~0ull, or_lo = 0, and_hi = ~0ull, or_hi = 0;
       const uint32_t nr = acc_repl(p.len, a.l.tile);
-      for (uint32_t k = 0; k < nr; ++k) {
-        const AccRep *acp = &a.acc[p.tile0 + ACC_STRIDE * k];
-        and_lo &= acp->and_lo;
-        or_lo |= acp->or_lo;
-        and_hi &= acp->and_hi;
-        or_hi |= acp->or_hi;
+      if (nr == 1) {
+        const AccRep r0 = a.acc[p.tile0];
+        and_lo = r0.and_lo;
+        or_lo = r0.or_lo;
+        and_hi = r0.and_hi;
+        or_hi = r0.or_hi;
+      } else {
+        // all replicas in flight at once; indices past the last replica
+        // read the last one again, which AND and OR absorb
+        AccRep rep[ACC_REPL];
+#pragma unroll
+        for (uint32_t k = 0; k < (uint32_t)ACC_REPL; ++k)
+          rep[k] = a.acc[p.tile0 + ACC_STRIDE * (k < nr ? k : nr - 1)];
+#pragma unroll
+        for (uint32_t k = 0; k < (uint32_t)ACC_REPL; ++k) {
+          and_lo &= rep[k].and_lo;
+          or_lo |= rep[k].or_lo;
+          and_hi &= rep[k].and_hi;
+          or_hi |= rep[k].or_hi;
+        }
       }
       const int bit = (int)(p.meta & BIT_MASK);
       const uint64_t F = a.split[q];
@@ -572,6 +588,17 @@ struct LevelArgs {
   int w, mode, desc, level;
 };
 
+// Kernel arguments read where they are used (a scalar load from the
+// argument segment) instead of held in scalar registers across the tile
+// loop, whose other uniform values already fill them.
+template <typename T>
+__device__ __forceinline__ T karg_at(size_t off) {
+  const __attribute__((address_space(4))) char *k =
+      (const __attribute__((address_space(4))) char *)__builtin_amdgcn_kernarg_segment_ptr();
+  return *(const volatile __attribute__((address_space(4))) T *)(k + off);
+}
+#define LARG(f) karg_at<decltype(LevelArgs<KT>::f)>(offsetof(LevelArgs<KT>, f))
+
 // Uniform description of one tile of a level (every lane holds the same).
 struct TileInfo {
   uint64_t start, len, lo;
@@ -631,23 +658,23 @@ __device__ __forceinline__ void issue_loads(const LevelArgs<KT> &a, const TileIn
   // one load per thread, summed only when the tile is ranked
   const uint32_t js = v ? (ti.j >> 6) : 0u;
   const uint32_t jt = v ? (ti.j & 63u) : 0u;
-  const rsrc_t gs = make_rsrc(a.scnt_in + (v ? ti.cbase : 0u),
+  const rsrc_t gs = make_rsrc(LARG(scnt_in) + (v ? ti.cbase : 0u),
                               (js < (uint32_t)BLOCK ? js : (uint32_t)BLOCK) * 4u);
-  const rsrc_t ts = make_rsrc(a.tcnt_in + (v ? ti.cbase + (js << 6) : 0u), jt * 4u);
+  const rsrc_t ts = make_rsrc(LARG(tcnt_in) + (v ? ti.cbase + (js << 6) : 0u), jt * 4u);
   r.pv0 = buf_load<uint32_t>(gs, (uint32_t)tid * 4u);
   r.pv1 = buf_load<uint32_t>(ts, (uint32_t)tid * 4u);
   // the segment's child AND/OR words as they stand (for the atomics that
   // the tile may skip): lanes 0-7 read one dword each, published in LDS
   const uint32_t ai =
       v ? ti.tile0 + ACC_STRIDE * (ti.j % acc_repl(ti.len, (uint32_t)(BLOCK * IPT))) : 0u;
-  const rsrc_t ar = make_rsrc(a.acc + ai, v ? (uint32_t)sizeof(AccRep) : 0u);
+  const rsrc_t ar = make_rsrc(LARG(acc) + ai, v ? (uint32_t)sizeof(AccRep) : 0u);
   r.acd = buf_load<uint32_t>(ar, (uint32_t)(tid & 63) * 4u);
   // storage of the tile: [sbase, sbase + cnt); logical q is at sbase + q
   // (forward) or sbase + cnt - 1 - q (reversed)
   const uint64_t end = ti.start + ti.len;
   const uint64_t sbase = v ? (rev ? (end - ti.lo - ti.cnt) : (ti.start + ti.lo)) : 0u;
-  const rsrc_t kr = make_rsrc(a.keys_in + sbase, ti.cnt * (uint32_t)sizeof(KT));
-  const rsrc_t ir = make_rsrc(IDX ? a.idx_in + sbase : nullptr, IDX && !iota ? ti.cnt * 4u : 0u);
+  const rsrc_t kr = make_rsrc(LARG(keys_in) + sbase, ti.cnt * (uint32_t)sizeof(KT));
+  const rsrc_t ir = make_rsrc(IDX ? LARG(idx_in) + sbase : nullptr, IDX && !iota ? ti.cnt * 4u : 0u);
 #pragma unroll
   for (int i = 0; i < IPT; ++i) {
     const uint32_t q = (uint32_t)(i * BLOCK + tid);
@@ -657,7 +684,7 @@ __device__ __forceinline__ void issue_loads(const LevelArgs<KT> &a, const TileIn
   }
   // segments of more than BLOCK groups: the remaining group sums (rare)
   r.pvx = 0;
-  for (uint32_t s = (uint32_t)(BLOCK + tid); s < js; s += BLOCK) r.pvx += a.scnt_in[ti.cbase + s];
+  for (uint32_t s = (uint32_t)(BLOCK + tid); s < js; s += BLOCK) r.pvx += LARG(scnt_in)[ti.cbase + s];
 }
 
 template <int NCNT, int WAVES>
@@ -700,15 +727,16 @@ __device__ __forceinline__ void level_tile(const LevelArgs<KT> &a, const TileInf
   constexpr int TILE = BLOCK * IPT;
   constexpr int NCNT = IPT * WAVES;
   using RT = typename std::conditional<sizeof(KT) == 8, uint64_t, uint32_t>::type;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   tn = tile_info<TILE>(sh.seg[cur ^ 1], sh.tile[cur ^ 1], ntiles);
   issue_loads<KT, IDX, BLOCK, IPT>(a, tn, rn);
   // the tile after next: its id and (lanes 0-7) its descriptor
   cout.t = cin.t + gridDim.x;
-  cin.dw = seg_dword(a.tiles, cin.t, ntiles, lane);
+  cin.dw = seg_dword(LARG(tiles), cin.t, ntiles, lane);
 
   const int bit = (int)(ti.meta & BIT_MASK);
-  const uint32_t f = (uint32_t)flip_of(bit, a.w, a.mode, a.desc, (ti.meta & META_SIGN) ? 1 : 0);
+  const uint32_t f = (uint32_t)flip_of(bit, LARG(w), LARG(mode), LARG(desc), (ti.meta & META_SIGN) ? 1 : 0);
   const uint32_t cnt = ti.cnt;
   const uint64_t end = ti.start + ti.len;
 
@@ -776,7 +804,7 @@ __device__ __forceinline__ void level_tile(const LevelArgs<KT> &a, const TileInf
     // atomic whose value the (even stale) read already absorbs is skipped:
     // big segments would otherwise send every tile's atomics to the same
     // four words.
-    AccRep *ac = &a.acc[ti.tile0 + ACC_STRIDE * (ti.j % acc_repl(ti.len, (uint32_t)TILE))];
+    AccRep *ac = &LARG(acc)[ti.tile0 + ACC_STRIDE * (ti.j % acc_repl(ti.len, (uint32_t)TILE))];
     const uint64_t al = sh.red[0], ol = sh.red[1], ah = sh.red[2], oh = sh.red[3];
     sh.red[0] = ~0ull;
     sh.red[1] = 0;
@@ -787,7 +815,7 @@ __device__ __forceinline__ void level_tile(const LevelArgs<KT> &a, const TileInf
     if ((acw[1] | ol) != acw[1]) atomic_or_u64(&ac->or_lo, ol);
     if ((acw[2] & ah) != acw[2]) atomic_and_u64(&ac->and_hi, ah);
     if ((acw[3] | oh) != acw[3]) atomic_or_u64(&ac->or_hi, oh);
-    if (ti.lo + cnt == ti.len) a.split[ti.slot] = P1 + c1;
+    if (ti.lo + cnt == ti.len) LARG(split)[ti.slot] = P1 + c1;
   }
 
   const uint32_t c2 = cnt - c1;
@@ -799,29 +827,59 @@ __device__ __forceinline__ void level_tile(const LevelArgs<KT> &a, const TileInf
   // A prefix that broke this would be an internal error: the tile then
   // writes nothing and the status word says so.
   const bool sane = P1 <= ti.lo;
-  if (!sane && tid == ACC_THREAD) atomic_or_u32(&a.hdr->status, STATUS_BAD_COUNTS);
+  if (!sane && tid == ACC_THREAD) atomic_or_u32(&LARG(hdr)->status, STATUS_BAD_COUNTS);
   const uint32_t wcnt = sane ? cnt : 0u;
-  KT *const kseg = a.keys_out + ti.start;
-  uint32_t *const iseg = IDX ? a.idx_out + ti.start : nullptr;
   uint32_t rk[IPT];  // rank within the key's own side of this tile
+  // index of an iota input: the tile position, added to the zero that the
+  // empty load range returned
+  const uint32_t ibase = iota ? (uint32_t)ti.lo + (uint32_t)tid : 0u;
+  if (ti.len <= (uint64_t)(0xffffffffu / (sizeof(KT) > 4 ? sizeof(KT) : 4))) {
+    // Byte offsets from the front run's start fit 32 bits: one uniform base
+    // per array and a 32-bit offset per lane.  A back key's place,
+    // len - 1 - P2 - r2, is at least len - lo - cnt + P1 >= P1 when the
+    // prefix is sane, so its offset does not wrap.
+    char *const kb = reinterpret_cast<char *>(LARG(keys_out) + ti.start + P1);
+    char *const ib = IDX ? reinterpret_cast<char *>(LARG(idx_out) + ti.start + P1) : nullptr;
+    const uint32_t dback = (uint32_t)(ti.len - 1 - P2 - P1);
 #pragma unroll
-  for (int i = 0; i < IPT; ++i) {
-    const uint32_t q = (uint32_t)(i * BLOCK + tid);
-    const bool front = (fbits >> i) & 1u;
-    const uint64_t fm = __ballot(front);
-    const uint32_t base = (uint32_t)__builtin_amdgcn_readlane((int)(cinc - cv), i * WAVES + wave);
-    const uint32_t r1 = base + lanes_below(fm);
-    const uint32_t r2 = q - r1;
-    // front key of tile rank r1 -> P1 + r1 in the segment; back key of
-    // tile back rank r2 -> len - 1 - P2 - r2 (the back child runs right to
-    // left).  One store per array, per-lane addresses: each wave's front
-    // lanes and back lanes write two contiguous runs, which L2 merges.
-    if (q < wcnt) {
-      const uint64_t rel = front ? (P1 + r1) : (ti.len - 1 - P2 - r2);
-      kseg[rel] = r.key[i];
-      if (IDX) iseg[rel] = r.ix[i] + (iota ? (uint32_t)(ti.lo + q) : 0u);
+    for (int i = 0; i < IPT; ++i) {
+      const uint32_t q = (uint32_t)(i * BLOCK + tid);
+      const bool front = (fbits >> i) & 1u;
+      const uint64_t fm = __ballot(front);
+      const uint32_t base = (uint32_t)__builtin_amdgcn_readlane((int)(cinc - cv), i * WAVES + wave);
+      const uint32_t r1 = base + lanes_below(fm);
+      const uint32_t r2 = q - r1;
+      if (q < wcnt) {
+        const uint32_t off = front ? r1 : dback - r2;
+        *reinterpret_cast<KT *>(kb + off * (uint32_t)sizeof(KT)) = r.key[i];
+        if (IDX)
+          *reinterpret_cast<uint32_t *>(ib + off * 4u) =
+              r.ix[i] + ibase + (iota ? (uint32_t)(i * BLOCK) : 0u);
+      }
+      rk[i] = front ? r1 : r2;
     }
-    rk[i] = front ? r1 : r2;
+  } else {
+    KT *const kseg = LARG(keys_out) + ti.start;
+    uint32_t *const iseg = IDX ? LARG(idx_out) + ti.start : nullptr;
+#pragma unroll
+    for (int i = 0; i < IPT; ++i) {
+      const uint32_t q = (uint32_t)(i * BLOCK + tid);
+      const bool front = (fbits >> i) & 1u;
+      const uint64_t fm = __ballot(front);
+      const uint32_t base = (uint32_t)__builtin_amdgcn_readlane((int)(cinc - cv), i * WAVES + wave);
+      const uint32_t r1 = base + lanes_below(fm);
+      const uint32_t r2 = q - r1;
+      // front key of tile rank r1 -> P1 + r1 in the segment; back key of
+      // tile back rank r2 -> len - 1 - P2 - r2 (the back child runs right to
+      // left).  One store per array, per-lane addresses: each wave's front
+      // lanes and back lanes write two contiguous runs, which L2 merges.
+      if (q < wcnt) {
+        const uint64_t rel = front ? (P1 + r1) : (ti.len - 1 - P2 - r2);
+        kseg[rel] = r.key[i];
+        if (IDX) iseg[rel] = r.ix[i] + ibase + (iota ? (uint32_t)(i * BLOCK) : 0u);
+      }
+      rk[i] = front ? r1 : r2;
+    }
   }
 
   // next level (bit - 1): for each child tile it will read, the number of
@@ -831,12 +889,12 @@ __device__ __forceinline__ void level_tile(const LevelArgs<KT> &a, const TileInf
   if (nxt) {
     const int nbit = bit - 1;
     uint32_t sgn_f = (ti.meta & META_SIGN) ? 1u : 0u, sgn_b = sgn_f;
-    if (bit == a.w - 1) {
+    if (bit == LARG(w) - 1) {
       sgn_f = f;
       sgn_b = 1u - f;
     }
-    const uint32_t fnf = (uint32_t)a.desc ^ (uint32_t)(a.mode == MODE_F && sgn_f);
-    const uint32_t fnb = (uint32_t)a.desc ^ (uint32_t)(a.mode == MODE_F && sgn_b);
+    const uint32_t fnf = (uint32_t)LARG(desc) ^ (uint32_t)(LARG(mode) == MODE_F && sgn_f);
+    const uint32_t fnb = (uint32_t)LARG(desc) ^ (uint32_t)(LARG(mode) == MODE_F && sgn_b);
     // ranks from which a key lies in its child's following tile
     const uint32_t xf = (uint32_t)((P1 / TILE + 1) * TILE - P1);
     const uint32_t xb = (uint32_t)((P2 / TILE + 1) * TILE - P2);
@@ -883,8 +941,8 @@ __device__ __forceinline__ void level_tile(const LevelArgs<KT> &a, const TileInf
     const uint32_t base = (k >> 1) ? 2 * ti.tile0 + nt : 2 * ti.tile0;
     const uint32_t jj = (uint32_t)(((k >> 1) ? P2 : P1) / TILE) + (uint32_t)(k & 1);
     if (c) {
-      atomic_add_u32(&a.tcnt_out[base + jj], c);
-      atomic_add_u32(&a.scnt_out[base + (jj >> 6)], c);
+      atomic_add_u32(&LARG(tcnt_out)[base + jj], c);
+      atomic_add_u32(&LARG(scnt_out)[base + (jj >> 6)], c);
     }
   }
   cur ^= 1;

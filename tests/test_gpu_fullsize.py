@@ -176,6 +176,23 @@ def test_word_size_sweep(case):
         del t, idx
 
 
+def test_u8_with_indices_over_2_30():
+    """2^30 + 12345 one-byte keys with uint32 indices.  Segments longer than
+    2^30 keys are written with 64-bit addresses (the level kernel's 32-bit
+    store offsets cover segments of less than 4 GiB of 4-byte words), and
+    the index payload's byte offsets pass 2^32.  Checked by the properties
+    and at the middle rank by the oracle."""
+    name, n = "u8", (1 << 30) + 12345
+    print(f"full size {name} n={n} with indices", flush=True)
+    bits = W.uniform_bits(name, n, 33)
+    src = to_device(bits, name)
+    t = src.clone()
+    idx = sort_call(name, t, False)
+    check_properties(name, src, t, idx, False)
+    check_samples(name, bits, t.cpu().numpy().view(DTYPES[name][2]), idx.cpu().numpy(), False,
+                  sample_ranks(n, 0, 9))
+
+
 @pytest.mark.parametrize("name", ["f32", "i32"])
 def test_batched_4096(name):
     """4096 arrays with log-uniform lengths in [1, 2^20] in one segmented
