@@ -1267,74 +1267,96 @@ void finish_kernel(FinishArgs<KT> a) {
         // the count of digits 0..7 (the low half of the total).
         constexpr int CRB = 4, CDIG = 1 << CRB, CW = CDIG / 2;
         static_assert(T < 65536, "16-bit counter halves");
+        static_assert((T & (T - 1)) == 0, "power-of-two finish size");
+        constexpr int PB = __builtin_ctz((unsigned)T);  // bits of a position
         const RT maxc = (nbits >= (int)(8 * sizeof(RT))) ? (RT)~(RT)0 : (RT)(((RT)1 << nbits) - 1);
+        // With indices, a code of at most 32 - PB bits travels with its
+        // position in one word (code above, position below): the passes
+        // then move one word per key, and each index is fetched once, by
+        // position, at the end.
+        const bool pk = IDX && nbits + PB <= 32;
+        const int dsh = pk ? PB : 0;
 #pragma unroll
         for (int i = 0; i < IPT; ++i) {
           const uint32_t p = (uint32_t)(i * BLOCK + tid);
-          s_code[p] = p < len ? code[i] : maxc;
+          const RT c = p < len ? code[i] : maxc;
+          s_code[p] = pk ? (RT)((c << PB) | p) : c;
           if (IDX) s_idx[p] = ix[i];
         }
-        for (int sh = 0; sh < nbits; sh += CRB) {
-          __syncthreads();
-          RT c[IPT];
-          uint32_t x[IPT], loc[IPT];
-#pragma unroll
-          for (int j = 0; j < IPT; ++j) {
-            c[j] = s_code[tid * IPT + j];
-            if (IDX) x[j] = s_idx[tid * IPT + j];
-          }
-#pragma unroll
-          for (int d = 0; d < CW; ++d) s_cnt[d * BLOCK + tid] = 0;
-#pragma unroll
-          for (int j = 0; j < IPT; ++j) {
-            const uint32_t d = (uint32_t)(c[j] >> sh) & (uint32_t)(CDIG - 1);
-            const uint32_t hs = (d >> 3) << 4;
-            loc[j] = (atomicAdd(&s_cnt[(d & (CW - 1)) * BLOCK + tid], 1u << hs) >> hs) & 0xffffu;
-          }
-          __syncthreads();
-          uint32_t lowtot;
-          {
-            uint32_t v[CW];
-            uint32_t sum = 0;
-#pragma unroll
-            for (int k = 0; k < CW; ++k) {
-              v[k] = s_cnt[tid * CW + k];
-              sum += v[k];
-            }
-            const uint32_t inc = wave_incl_scan_dpp(sum);
-            if (lane == 63) s_wsum[wave] = inc;
+        auto passes = [&](auto carry) {
+          constexpr bool CARRY = decltype(carry)::value;
+          for (int sh = 0; sh < nbits; sh += CRB) {
             __syncthreads();
-            uint32_t ex = inc - sum, tot = 0;
+            RT c[IPT];
+            uint32_t x[IPT], loc[IPT];
 #pragma unroll
-            for (int w2 = 0; w2 < WAVES; ++w2) {
-              const uint32_t ws = s_wsum[w2];
-              if (w2 < wave) ex += ws;
-              tot += ws;
+            for (int j = 0; j < IPT; ++j) {
+              c[j] = s_code[tid * IPT + j];
+              if (CARRY) x[j] = s_idx[tid * IPT + j];
             }
-            lowtot = tot & 0xffffu;
 #pragma unroll
-            for (int k = 0; k < CW; ++k) {
-              s_cnt[tid * CW + k] = ex;
-              ex += v[k];
+            for (int d = 0; d < CW; ++d) s_cnt[d * BLOCK + tid] = 0;
+#pragma unroll
+            for (int j = 0; j < IPT; ++j) {
+              const uint32_t d = (uint32_t)(c[j] >> (sh + dsh)) & (uint32_t)(CDIG - 1);
+              const uint32_t hs = (d >> 3) << 4;
+              loc[j] = (atomicAdd(&s_cnt[(d & (CW - 1)) * BLOCK + tid], 1u << hs) >> hs) & 0xffffu;
+            }
+            __syncthreads();
+            uint32_t lowtot;
+            {
+              uint32_t v[CW];
+              uint32_t sum = 0;
+#pragma unroll
+              for (int k = 0; k < CW; ++k) {
+                v[k] = s_cnt[tid * CW + k];
+                sum += v[k];
+              }
+              const uint32_t inc = wave_incl_scan_dpp(sum);
+              if (lane == 63) s_wsum[wave] = inc;
+              __syncthreads();
+              uint32_t ex = inc - sum, tot = 0;
+#pragma unroll
+              for (int w2 = 0; w2 < WAVES; ++w2) {
+                const uint32_t ws = s_wsum[w2];
+                if (w2 < wave) ex += ws;
+                tot += ws;
+              }
+              lowtot = tot & 0xffffu;
+#pragma unroll
+              for (int k = 0; k < CW; ++k) {
+                s_cnt[tid * CW + k] = ex;
+                ex += v[k];
+              }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < IPT; ++j) {
+              const uint32_t d = (uint32_t)(c[j] >> (sh + dsh)) & (uint32_t)(CDIG - 1);
+              const uint32_t wv = s_cnt[(d & (CW - 1)) * BLOCK + tid];
+              const uint32_t base = (d >> 3) ? (wv >> 16) + lowtot : (wv & 0xffffu);
+              const uint32_t dst = base + loc[j];
+              s_code[dst] = c[j];
+              if (CARRY) s_idx[dst] = x[j];
             }
           }
-          __syncthreads();
-#pragma unroll
-          for (int j = 0; j < IPT; ++j) {
-            const uint32_t d = (uint32_t)(c[j] >> sh) & (uint32_t)(CDIG - 1);
-            const uint32_t wv = s_cnt[(d & (CW - 1)) * BLOCK + tid];
-            const uint32_t base = (d >> 3) ? (wv >> 16) + lowtot : (wv & 0xffffu);
-            const uint32_t dst = base + loc[j];
-            s_code[dst] = c[j];
-            if (IDX) s_idx[dst] = x[j];
-          }
-        }
+        };
+        if (IDX && !pk)
+          passes(std::true_type{});
+        else
+          passes(std::false_type{});
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < IPT; ++i) {
           const uint32_t p = (uint32_t)(i * BLOCK + tid);
-          code[i] = s_code[p];
-          if (IDX) ix[i] = s_idx[p];
+          const RT wv = s_code[p];
+          if (pk) {
+            code[i] = wv >> PB;
+            ix[i] = s_idx[wv & (RT)(T - 1)];
+          } else {
+            code[i] = wv;
+            if (IDX) ix[i] = s_idx[p];
+          }
         }
         __syncthreads();
       } else {
