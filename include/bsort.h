@@ -61,6 +61,8 @@ extern "C" {
 #define BSORT_NO_FINISH 4u  /* no in-LDS finish of small parts: every bit is a global pass */
 #define BSORT_PLAIN (BSORT_NO_SKIP | BSORT_NO_FINISH) /* the paper's w full passes         */
 #define BSORT_IDX64 8u      /* indices are int64 instead of uint32                         */
+#define BSORT_KEYS_UNCHANGED 16u /* argsort: only the indices are written (indices required);
+                                  * the keys are sorted in a scratch copy                  */
 
 /* ---- key types (for bsort_scratch_bytes and the generic entry point) ---- */
 #define BSORT_KEY_U 0 /* unsigned integer                     */
@@ -73,7 +75,8 @@ extern "C" {
  * when `indices` will be non-NULL.  The figure is O(n): a second key buffer
  * (n * key_bytes), a second index buffer (4n, or 8n with BSORT_IDX64), and
  * O(n/4096 + num_segments) bytes of work lists; BSORT_NO_FINISH raises the
- * work-list part to O(n).  Returns 0 for invalid arguments.
+ * work-list part to O(n), and BSORT_KEYS_UNCHANGED adds n * key_bytes for
+ * the copy that is sorted.  Returns 0 for invalid arguments.
  */
 size_t bsort_scratch_bytes(int key_bytes, uint64_t n, uint64_t num_segments,
                            int with_indices, uint32_t flags);
@@ -150,6 +153,42 @@ int bsort_sort(void *keys, int key_type, int key_bytes, uint64_t n, uint32_t fla
 int bsort_backward_scatter(const void *grad_sorted, const void *indices, uint64_t rows,
                            uint64_t cols, int elem_bytes, void *grad_in, uint32_t flags,
                            void *stream);
+
+/* ---- values that travel with the keys ----
+ *
+ * A key-value sort permutes a payload exactly as the keys: after the sort,
+ * values[j] holds the value that came with keys[j] (the stable order of
+ * Section II's splits, so equal keys keep their values in input order).
+ * value_bytes in {1, 2, 4, 8, 16}; values are moved as raw bits, in place.
+ * `values` must be aligned to value_bytes.  `indices` (nullable) receives the
+ * permutation as in the sorts above; without it the permutation is kept in
+ * scratch.  Flags as for the sorts (BSORT_KEYS_UNCHANGED leaves the keys as
+ * they were and permutes only the values).  Scratch: at least
+ * bsort_pairs_scratch_bytes(...) bytes, 256-byte aligned.  Offsets as for
+ * bsort_segmented.  Arguments are validated before anything is enqueued.
+ */
+size_t bsort_pairs_scratch_bytes(int key_bytes, uint64_t n, uint64_t num_segments,
+                                 int value_bytes, int with_indices, uint32_t flags);
+int bsort_sort_pairs(void *keys, int key_type, int key_bytes, uint64_t n, uint32_t flags,
+                     void *values, int value_bytes, void *indices, void *scratch,
+                     size_t scratch_bytes, void *stream);
+int bsort_segmented_pairs(void *keys, int key_type, int key_bytes, const int64_t *offsets,
+                          uint64_t num_segments, uint64_t n, uint32_t flags, void *values,
+                          int value_bytes, void *indices, void *scratch, size_t scratch_bytes,
+                          void *stream);
+
+/*
+ * Applies a permutation from a sort to another tensor (a second payload):
+ *   out[j] = values[base(j) + indices[j]]     for j < n,
+ * base(j) = 0 without offsets, else offsets[s] for the segment s holding
+ * position j (indices are segment-local, as the sorts return them).
+ * value_bytes in {1, 2, 4, 8, 16}; values and out aligned to value_bytes and
+ * not overlapping; indices uint32, or int64 with BSORT_IDX64 (the only flag).
+ * Positions whose index falls outside their segment are not written.
+ */
+int bsort_gather(const void *values, int value_bytes, const void *indices,
+                 const int64_t *offsets, uint64_t num_segments, uint64_t n, uint32_t flags,
+                 void *out, void *stream);
 
 /* ---- launch configurations and the autotuner ----
  *

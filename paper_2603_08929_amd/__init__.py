@@ -5,10 +5,12 @@ as HIP kernels for gfx950 behind a C ABI (include/bsort.h).
     values, indices = bsort.sort(x)               # 1-D, stable
     idx = bsort.sort_(x, descending=True)         # in place
     idx = bsort.segmented_sort_(x, offsets)       # many arrays, one pass
+    idx = bsort.argsort(x)                        # keys left unchanged
+    bsort.sort_pairs_(keys, values)               # values follow the keys
     y = bsort.BSortFunction.apply(x, -1, False)   # differentiable
 """
 from ._lib import (DESCENDING, IDX64, NO_FINISH, NO_SKIP, PLAIN, KEY_F, KEY_I,  # noqa: F401
                    KEY_U, lib, strerror)
-from .api import (backward_scatter, device_status, scratch_bytes, segmented_sort_,  # noqa: F401
-                  sort, sort_, key_type)
+from .api import (argsort, backward_scatter, device_status, gather, scratch_bytes,  # noqa: F401
+                  segmented_sort_, sort, sort_, sort_pairs_, key_type)
 from .autograd import BSortFunction, sort_along  # noqa: F401

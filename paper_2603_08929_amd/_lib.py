@@ -23,7 +23,7 @@ lib = ctypes.CDLL(LIB)
 
 # status codes and flags (include/bsort.h)
 OK, EINVAL, ESCRATCH, ETOOBIG, EHIP, ENODEV = 0, -1, -2, -3, -4, -5
-DESCENDING, NO_SKIP, NO_FINISH, IDX64 = 1, 2, 4, 8
+DESCENDING, NO_SKIP, NO_FINISH, IDX64, KEYS_UNCHANGED = 1, 2, 4, 8, 16
 PLAIN = NO_SKIP | NO_FINISH
 KEY_U, KEY_I, KEY_F = 0, 1, 2
 
@@ -36,7 +36,8 @@ SYMBOLS = ["bsort_scratch_bytes", "bsort_sort", "bsort_segmented", "bsort_segmen
            "bsort_timing_read", "bsort_timing_disarm", "bsort_config_count",
            "bsort_config_name", "bsort_config_override", "bsort_tuned_config",
            "bsort_autotune", "bsort_autotune_reset", "bsort_graph_create",
-           "bsort_graph_launch", "bsort_graph_destroy"] + [f"bsort_{t}" for t in TYPED]
+           "bsort_graph_launch", "bsort_graph_destroy", "bsort_pairs_scratch_bytes",
+           "bsort_sort_pairs", "bsort_segmented_pairs", "bsort_gather"] + [f"bsort_{t}" for t in TYPED]
 
 lib.bsort_scratch_bytes.argtypes = [_i, _u64, _u64, _i, _u32]
 lib.bsort_scratch_bytes.restype = _sz
@@ -54,6 +55,15 @@ for t in ("f32", "i32"):
     fn.restype = _i
 lib.bsort_backward_scatter.argtypes = [_vp, _vp, _u64, _u64, _i, _vp, _u32, _vp]
 lib.bsort_backward_scatter.restype = _i
+lib.bsort_pairs_scratch_bytes.argtypes = [_i, _u64, _u64, _i, _i, _u32]
+lib.bsort_pairs_scratch_bytes.restype = _sz
+lib.bsort_sort_pairs.argtypes = [_vp, _i, _i, _u64, _u32, _vp, _i, _vp, _vp, _sz, _vp]
+lib.bsort_sort_pairs.restype = _i
+lib.bsort_segmented_pairs.argtypes = [_vp, _i, _i, _vp, _u64, _u64, _u32, _vp, _i, _vp, _vp,
+                                      _sz, _vp]
+lib.bsort_segmented_pairs.restype = _i
+lib.bsort_gather.argtypes = [_vp, _i, _vp, _vp, _u64, _u64, _u32, _vp, _vp]
+lib.bsort_gather.restype = _i
 lib.bsort_strerror.argtypes = [_i]
 lib.bsort_strerror.restype = ctypes.c_char_p
 lib.bsort_device_status.argtypes = [_vp, _vp]
@@ -118,5 +128,9 @@ bsort_autotune_reset = lib.bsort_autotune_reset
 bsort_graph_create = lib.bsort_graph_create
 bsort_graph_launch = lib.bsort_graph_launch
 bsort_graph_destroy = lib.bsort_graph_destroy
+bsort_pairs_scratch_bytes = lib.bsort_pairs_scratch_bytes
+bsort_sort_pairs = lib.bsort_sort_pairs
+bsort_segmented_pairs = lib.bsort_segmented_pairs
+bsort_gather = lib.bsort_gather
 for _t in TYPED:
     globals()[f"bsort_{_t}"] = getattr(lib, f"bsort_{_t}")

@@ -7,7 +7,8 @@ from typing import Optional, Tuple
 import torch
 
 from . import _lib
-from ._lib import DESCENDING, IDX64, KEY_F, KEY_I, KEY_U, NO_FINISH, NO_SKIP, PLAIN  # noqa
+from ._lib import (DESCENDING, IDX64, KEY_F, KEY_I, KEY_U, KEYS_UNCHANGED,  # noqa
+                   NO_FINISH, NO_SKIP, PLAIN)
 
 # torch dtype -> (key family, key bytes)
 KEY_TYPES = {
@@ -121,6 +122,92 @@ def backward_scatter(grad_sorted: torch.Tensor, indices: torch.Tensor,
     rc = _lib.bsort_backward_scatter(g.data_ptr(), ix.data_ptr(), rows, cols,
                                      g.element_size(), out.data_ptr(), fl, _stream(g.device))
     _lib.check(rc, "bsort_backward_scatter")
+    return out
+
+
+def argsort(keys: torch.Tensor, offsets: Optional[torch.Tensor] = None,
+            descending: bool = False, idx64: bool = False, flags: int = 0) -> torch.Tensor:
+    """The stable permutation that sorts a contiguous 1-D tensor (or each
+    segment of it), keys left unchanged: int32 storage of uint32 indices, or
+    int64 with idx64."""
+    kt, kb = key_type(keys.dtype)
+    B, off = _segment_args(keys, offsets)
+    n = keys.numel()
+    fl = _flags(descending, flags | KEYS_UNCHANGED, idx64)
+    idx = torch.empty(n, dtype=torch.int64 if idx64 else torch.int32, device=keys.device)
+    need = _lib.bsort_scratch_bytes(kb, n, max(B, 1), 1, fl)
+    scratch = torch.empty(max(need, 256), dtype=torch.uint8, device=keys.device)
+    if offsets is None:
+        rc = _lib.bsort_sort(keys.data_ptr(), kt, kb, n, fl, idx.data_ptr(), scratch.data_ptr(),
+                             scratch.numel(), _stream(keys.device))
+    else:
+        rc = _lib.bsort_segmented(keys.data_ptr(), kt, kb, off, B, n, fl, idx.data_ptr(),
+                                  scratch.data_ptr(), scratch.numel(), _stream(keys.device))
+    _lib.check(rc, "argsort")
+    return idx
+
+
+def _value_bytes(values: torch.Tensor, n: int) -> int:
+    """Bytes of one element's payload: a 1-D tensor of n, or n rows of a
+    contiguous tensor (the row moves as one word)."""
+    if not values.is_cuda or not values.is_contiguous() or values.dim() < 1 \
+            or values.shape[0] != n:
+        raise ValueError("bsort: values must be a contiguous GPU tensor with one row per key")
+    vb = values[0].numel() * values.element_size() if n else values.element_size()
+    if vb not in (1, 2, 4, 8, 16):
+        raise ValueError(f"bsort: a value row of {vb} bytes; 1, 2, 4, 8 or 16 are supported")
+    return vb
+
+
+def sort_pairs_(keys: torch.Tensor, values: torch.Tensor, offsets: Optional[torch.Tensor] = None,
+                descending: bool = False, return_indices: bool = False, idx64: bool = False,
+                flags: int = 0) -> Optional[torch.Tensor]:
+    """Sorts keys (1-D, or each segment) in place and permutes values (one
+    row of 1, 2, 4, 8 or 16 bytes per key) the same way; returns the
+    permutation when asked."""
+    kt, kb = key_type(keys.dtype)
+    B, off = _segment_args(keys, offsets)
+    n = keys.numel()
+    vb = _value_bytes(values, n)
+    fl = _flags(descending, flags, idx64 and return_indices)
+    idx = None
+    if return_indices:
+        idx = torch.empty(n, dtype=torch.int64 if idx64 else torch.int32, device=keys.device)
+    need = _lib.bsort_pairs_scratch_bytes(kb, n, max(B, 1), vb, int(return_indices), fl)
+    scratch = torch.empty(max(need, 256), dtype=torch.uint8, device=keys.device)
+    ip = idx.data_ptr() if idx is not None else None
+    if offsets is None:
+        rc = _lib.bsort_sort_pairs(keys.data_ptr(), kt, kb, n, fl, values.data_ptr(), vb, ip,
+                                   scratch.data_ptr(), scratch.numel(), _stream(keys.device))
+    else:
+        rc = _lib.bsort_segmented_pairs(keys.data_ptr(), kt, kb, off, B, n, fl,
+                                        values.data_ptr(), vb, ip, scratch.data_ptr(),
+                                        scratch.numel(), _stream(keys.device))
+    _lib.check(rc, "sort_pairs")
+    return idx
+
+
+def gather(values: torch.Tensor, indices: torch.Tensor,
+           offsets: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """out[j] = values[base(j) + indices[j]] (base: the start of j's segment
+    with offsets, else 0) -- applies a sort's permutation to another tensor
+    with one row per key."""
+    n = indices.numel()
+    vb = _value_bytes(values, n)
+    if not indices.is_cuda or indices.dim() != 1 or not indices.is_contiguous():
+        raise ValueError("bsort.gather: indices must be a contiguous 1-D GPU tensor")
+    if indices.dtype == torch.int64:
+        fl = IDX64
+    elif indices.dtype == torch.int32:
+        fl = 0
+    else:
+        raise TypeError("indices must be int32 (uint32 payload) or int64")
+    B, off = _segment_args(indices, offsets)
+    out = torch.empty_like(values)
+    rc = _lib.bsort_gather(values.data_ptr(), vb, indices.data_ptr(), off,
+                           B if offsets is not None else 0, n, fl, out.data_ptr(),
+                           _stream(values.device))
+    _lib.check(rc, "bsort_gather")
     return out
 
 

@@ -118,7 +118,7 @@ uint32_t tfin_of(int key_bytes, int fv) {
 }
 
 constexpr uint32_t ALL_FLAGS =
-    BSORT_DESCENDING | BSORT_NO_SKIP | BSORT_NO_FINISH | BSORT_IDX64;
+    BSORT_DESCENDING | BSORT_NO_SKIP | BSORT_NO_FINISH | BSORT_IDX64 | BSORT_KEYS_UNCHANGED;
 
 size_t up256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -129,7 +129,7 @@ size_t up256(size_t x) { return (x + 255) & ~(size_t)255; }
 // hold more than T keys each.
 struct Layout {
   size_t hdr, cnts, segs[2], recs[2], acc[2], split[2], tmap[2], fin, cpy, keys1, idx0, idx1,
-      total;
+      keys0, total;
   uint64_t smax, tmax, fmax, cmax;
 };
 
@@ -162,6 +162,9 @@ bool make_layout(int key_bytes, uint64_t n, uint64_t B, bool with_idx, uint32_t 
     if (flags & BSORT_IDX64) { L->idx0 = off; off = up256(off + n * 4); }
     L->idx1 = off; off = up256(off + n * 4);
   }
+  // BSORT_KEYS_UNCHANGED: the keys are sorted in a copy
+  L->keys0 = 0;
+  if (flags & BSORT_KEYS_UNCHANGED) { L->keys0 = off; off = up256(off + n * (size_t)key_bytes); }
   L->total = off;
   return true;
 }
@@ -408,6 +411,7 @@ int run(void *keys, uint64_t n, const int64_t *offsets, uint64_t B, bool segment
   if (n == 0) return BSORT_OK;
   if (!keys || !scratch) return BSORT_EINVAL;
   const bool with_idx = indices != nullptr;
+  if ((flags & BSORT_KEYS_UNCHANGED) && !with_idx) return BSORT_EINVAL;
   // 2^32 keys or more are refused, with or without indices: that size has
   // not passed its tests on the GPU
   if (n >= (1ull << 32)) return BSORT_ETOOBIG;
@@ -432,6 +436,11 @@ int run(void *keys, uint64_t n, const int64_t *offsets, uint64_t B, bool segment
   hipStream_t st = static_cast<hipStream_t>(stream);
   char *scr = static_cast<char *>(scratch);
   KT *k = static_cast<KT *>(keys);
+  if (flags & BSORT_KEYS_UNCHANGED) {
+    k = reinterpret_cast<KT *>(scr + L.keys0);
+    const hipError_t e = hipMemcpyAsync(k, keys, n * sizeof(KT), hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "key copy");
+  }
   const int64_t *off = segmented ? offsets : nullptr;
   if (with_idx) return launch_cfg<KT, true>(c, k, n, off, b, mode, flags, indices, scr, L, cus, st);
   return launch_cfg<KT, false>(c, k, n, off, b, mode, flags, indices, scr, L, cus, st);
@@ -458,6 +467,106 @@ int dispatch(void *keys, int key_type, int key_bytes, uint64_t n, const int64_t 
     default:
       return BSORT_EINVAL;
   }
+}
+
+// Validation shared by the gather and the key-value entry points.
+bool value_args_ok(const void *p, int value_bytes) {
+  if (value_bytes != 1 && value_bytes != 2 && value_bytes != 4 && value_bytes != 8 &&
+      value_bytes != 16)
+    return false;
+  return (reinterpret_cast<uintptr_t>(p) & (uintptr_t)(value_bytes - 1)) == 0;
+}
+
+int launch_gather(const void *values, int value_bytes, const void *indices, bool i64,
+                  const int64_t *offsets, uint64_t B, uint64_t n, void *out, int cus,
+                  hipStream_t st) {
+  const uint32_t grid = clamp_grid((n + GCH - 1) / GCH, (uint64_t)cus * 8);
+#define BG_LAUNCH(VT)                                                                       \
+  do {                                                                                      \
+    if (i64)                                                                                \
+      hipLaunchKernelGGL((gather_kernel<VT, true>), dim3(grid), dim3(256), 0, st,           \
+                         static_cast<const VT *>(values), indices, offsets, B, n,           \
+                         static_cast<VT *>(out));                                           \
+    else                                                                                    \
+      hipLaunchKernelGGL((gather_kernel<VT, false>), dim3(grid), dim3(256), 0, st,          \
+                         static_cast<const VT *>(values), indices, offsets, B, n,           \
+                         static_cast<VT *>(out));                                           \
+  } while (0)
+  switch (value_bytes) {
+    case 1: BG_LAUNCH(uint8_t); break;
+    case 2: BG_LAUNCH(uint16_t); break;
+    case 4: BG_LAUNCH(uint32_t); break;
+    case 8: BG_LAUNCH(uint64_t); break;
+    default: BG_LAUNCH(uint4); break;
+  }
+#undef BG_LAUNCH
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  return BSORT_OK;
+}
+
+// Scratch of a key-value call: the sort's own, then the index buffer when
+// the caller passes none, then the gathered values.
+struct PairLayout {
+  size_t sort, idx, vals, total;
+};
+bool pair_layout(int key_bytes, uint64_t n, uint64_t B, int value_bytes, bool caller_idx,
+                 uint32_t flags, PairLayout *P) {
+  if (flags & ~ALL_FLAGS) return false;
+  if (key_bytes != 1 && key_bytes != 2 && key_bytes != 4 && key_bytes != 8) return false;
+  if (value_bytes != 1 && value_bytes != 2 && value_bytes != 4 && value_bytes != 8 &&
+      value_bytes != 16)
+    return false;
+  Layout L;
+  if (!make_layout(key_bytes, n, B ? B : 1, true, flags, tile_of(key_bytes, 1),
+                   tfin_of(key_bytes, 1), &L))
+    return false;
+  P->sort = L.total;
+  size_t off = up256(L.total);
+  P->idx = off;
+  if (!caller_idx) off = up256(off + n * ((flags & BSORT_IDX64) ? 8 : 4));
+  P->vals = off;
+  off = up256(off + n * (size_t)value_bytes);
+  P->total = off;
+  return true;
+}
+
+int sort_pairs(void *keys, int key_type, int key_bytes, const int64_t *offsets, uint64_t B,
+               bool segmented, uint64_t n, uint32_t flags, void *values, int value_bytes,
+               void *indices, void *scratch, size_t scratch_bytes, void *stream) {
+  if (flags & ~ALL_FLAGS) return BSORT_EINVAL;
+  if (value_bytes != 1 && value_bytes != 2 && value_bytes != 4 && value_bytes != 8 &&
+      value_bytes != 16)
+    return BSORT_EINVAL;
+  if (segmented && B > 0 && !offsets) return BSORT_EINVAL;
+  if (segmented && B == 0 && n != 0) return BSORT_EINVAL;
+  if (n == 0) return BSORT_OK;
+  if (!keys || !values || !scratch || !value_args_ok(values, value_bytes)) return BSORT_EINVAL;
+  if (n >= (1ull << 32)) return BSORT_ETOOBIG;
+  PairLayout P;
+  if (!pair_layout(key_bytes, n, segmented ? B : 1, value_bytes, indices != nullptr, flags, &P))
+    return BSORT_EINVAL;
+  if (scratch_bytes < P.total) return BSORT_ESCRATCH;
+  char *scr = static_cast<char *>(scratch);
+  void *idx = indices ? indices : static_cast<void *>(scr + P.idx);
+  int rc = dispatch(keys, key_type, key_bytes, n, offsets, segmented ? B : 1, segmented, flags,
+                    idx, scratch, P.sort, stream, CONFIG_DRY_RUN);
+  if (rc != BSORT_OK) return rc;
+  rc = dispatch(keys, key_type, key_bytes, n, offsets, segmented ? B : 1, segmented, flags, idx,
+                scratch, P.sort, stream);
+  if (rc != BSORT_OK) return rc;
+  int cus = 0;
+  rc = device_check(&cus);
+  if (rc != BSORT_OK) return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  void *tmp = scr + P.vals;
+  rc = launch_gather(values, value_bytes, idx, (flags & BSORT_IDX64) != 0,
+                     segmented ? offsets : nullptr, segmented ? B : 1, n, tmp, cus, st);
+  if (rc != BSORT_OK) return rc;
+  const hipError_t e =
+      hipMemcpyAsync(values, tmp, n * (size_t)value_bytes, hipMemcpyDeviceToDevice, st);
+  if (e != hipSuccess) return hip_fail(e, "value copy");
+  return BSORT_OK;
 }
 
 }  // namespace
@@ -555,6 +664,47 @@ int bsort_backward_scatter(const void *grad_sorted, const void *indices, uint64_
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
   return BSORT_OK;
+}
+
+size_t bsort_pairs_scratch_bytes(int key_bytes, uint64_t n, uint64_t num_segments,
+                                 int value_bytes, int with_indices, uint32_t flags) {
+  PairLayout P;
+  if (!pair_layout(key_bytes, n, num_segments ? num_segments : 1, value_bytes, with_indices != 0,
+                   flags, &P))
+    return 0;
+  return P.total;
+}
+
+int bsort_sort_pairs(void *keys, int key_type, int key_bytes, uint64_t n, uint32_t flags,
+                     void *values, int value_bytes, void *indices, void *scratch,
+                     size_t scratch_bytes, void *stream) {
+  return sort_pairs(keys, key_type, key_bytes, nullptr, 1, false, n, flags, values, value_bytes,
+                    indices, scratch, scratch_bytes, stream);
+}
+
+int bsort_segmented_pairs(void *keys, int key_type, int key_bytes, const int64_t *offsets,
+                          uint64_t num_segments, uint64_t n, uint32_t flags, void *values,
+                          int value_bytes, void *indices, void *scratch, size_t scratch_bytes,
+                          void *stream) {
+  return sort_pairs(keys, key_type, key_bytes, offsets, num_segments, true, n, flags, values,
+                    value_bytes, indices, scratch, scratch_bytes, stream);
+}
+
+int bsort_gather(const void *values, int value_bytes, const void *indices,
+                 const int64_t *offsets, uint64_t num_segments, uint64_t n, uint32_t flags,
+                 void *out, void *stream) {
+  if (flags & ~(uint32_t)BSORT_IDX64) return BSORT_EINVAL;
+  if (offsets && num_segments == 0 && n != 0) return BSORT_EINVAL;
+  if (n == 0) return BSORT_OK;
+  if (!values || !indices || !out) return BSORT_EINVAL;
+  if (!value_args_ok(values, value_bytes) || !value_args_ok(out, value_bytes))
+    return BSORT_EINVAL;
+  if (n >= (1ull << 32)) return BSORT_ETOOBIG;
+  int cus = 0;
+  const int rc = device_check(&cus);
+  if (rc != BSORT_OK) return rc;
+  return launch_gather(values, value_bytes, indices, (flags & BSORT_IDX64) != 0, offsets,
+                       offsets ? num_segments : 1, n, out, cus, static_cast<hipStream_t>(stream));
 }
 
 int bsort_config_count(void) { return N_CONFIGS; }

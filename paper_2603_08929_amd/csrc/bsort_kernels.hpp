@@ -934,13 +934,14 @@ __device__ __forceinline__ void level_tile(const LevelArgs<KT> &a, const TileInf
   __syncthreads();
   if (nxt && wave == CNT_WAVE && lane < 4) {
     // child c's tile j of the next level counts at 2*tile0 + c*nt + j
+    // (added only with a sane prefix, from which P2 and the index derive)
     const int k = lane;
     const uint32_t c = sh.nxt[k];
     sh.nxt[k] = 0;
     const uint32_t nt = (uint32_t)((ti.len + TILE - 1) / TILE);
     const uint32_t base = (k >> 1) ? 2 * ti.tile0 + nt : 2 * ti.tile0;
     const uint32_t jj = (uint32_t)(((k >> 1) ? P2 : P1) / TILE) + (uint32_t)(k & 1);
-    if (c) {
+    if (c && sane) {
       atomic_add_u32(&LARG(tcnt_out)[base + jj], c);
       atomic_add_u32(&LARG(scnt_out)[base + (jj >> 6)], c);
     }
@@ -1537,6 +1538,62 @@ __global__ void backward_scatter_kernel(const ET *g, const void *idx, uint64_t r
       const uint64_t d = I64 ? (uint64_t) static_cast<const int64_t *>(idx)[row + c]
                              : (uint64_t) static_cast<const uint32_t *>(idx)[row + c];
       if (d < cols) out[row + d] = g[row + c];
+    }
+  }
+}
+
+// ---------------------------------------------------------- payload gather
+
+// Segment of position x: the last s < B with offsets[s] <= x, searched in
+// [lo, hi].  With offsets that are not non-decreasing the answer is some s in
+// [lo, hi]; every read stays inside offsets[0, B].
+__device__ __forceinline__ uint64_t segment_of(const int64_t *offsets, uint64_t lo, uint64_t hi,
+                                               uint64_t x) {
+  while (lo < hi) {
+    const uint64_t m = lo + (hi - lo + 1) / 2;
+    if ((uint64_t)offsets[m] <= x) lo = m;
+    else hi = m - 1;
+  }
+  return lo;
+}
+
+// Values that travel with the keys (a key-value sort, or any further tensor
+// permuted like the keys): out[j] = values[base + idx[j]], base being 0 for
+// a single array and the start of j's segment otherwise.  VT is the value
+// word (1, 2, 4, 8 or 16 bytes), moved as raw bits.  A block takes chunks
+// of GCH positions; thread 0 finds the segments of the chunk's first and
+// last position, and each position searches only between them.  A source
+// outside its segment (indices that are not a permutation) is skipped.
+constexpr uint32_t GCH = 4096;
+template <typename VT, bool I64>
+__global__ __launch_bounds__(256) void gather_kernel(const VT *values, const void *indices,
+                                                     const int64_t *offsets, uint64_t B,
+                                                     uint64_t n, VT *out) {
+  __shared__ uint64_t s_rng[2];
+  for (uint64_t c0 = (uint64_t)blockIdx.x * GCH; c0 < n; c0 += (uint64_t)gridDim.x * GCH) {
+    const uint64_t c1 = c0 + GCH < n ? c0 + GCH : n;
+    uint64_t lo = 0, hi = 0;
+    if (offsets) {
+      if (threadIdx.x == 0) {
+        s_rng[0] = segment_of(offsets, 0, B - 1, c0);
+        s_rng[1] = segment_of(offsets, 0, B - 1, c1 - 1);
+      }
+      __syncthreads();
+      lo = s_rng[0];
+      hi = s_rng[1] < lo ? lo : s_rng[1];
+      __syncthreads();
+    }
+    for (uint64_t j = c0 + threadIdx.x; j < c1; j += blockDim.x) {
+      const uint64_t ix = I64 ? (uint64_t) static_cast<const int64_t *>(indices)[j]
+                              : (uint64_t) static_cast<const uint32_t *>(indices)[j];
+      uint64_t base = 0, len = n;
+      if (offsets) {
+        const uint64_t s = segment_of(offsets, lo, hi, j);
+        base = (uint64_t)offsets[s];
+        len = (uint64_t)offsets[s + 1] - base;
+      }
+      const uint64_t src = base + ix;
+      if (ix < len && src < n) out[j] = values[src];
     }
   }
 }

@@ -98,6 +98,45 @@ def test_validation_before_any_device_work():
     assert _lib.bsort_device_status(None, None) == _lib.EINVAL
 
 
+def test_pairs_argsort_gather_validation():
+    """Argsort, key-value and gather arguments are refused before any device
+    work; scratch sizes grow by what each mode adds."""
+    fake = 1 << 40
+    sb, psb = _lib.bsort_scratch_bytes, _lib.bsort_pairs_scratch_bytes
+    n = 1 << 20
+    # argsort keeps a copy of the keys in scratch
+    assert sb(4, n, 1, 1, _lib.KEYS_UNCHANGED) - sb(4, n, 1, 1, 0) >= 4 * n
+    # ... and needs the index output
+    assert _lib.bsort_u32(fake, 10, _lib.KEYS_UNCHANGED, None, fake, 1 << 30, None) == _lib.EINVAL
+    # key-value scratch: the sort's, the permutation when the caller keeps
+    # none, and the gathered values
+    assert psb(4, n, 1, 3, 0, 0) == 0                       # value width
+    assert psb(3, n, 1, 8, 0, 0) == 0                       # key width
+    with_idx = psb(4, n, 1, 8, 1, 0)
+    assert with_idx - sb(4, n, 1, 1, 0) >= 8 * n
+    assert psb(4, n, 1, 8, 0, 0) - with_idx >= 4 * n
+    assert psb(4, n, 1, 16, 1, 0) - with_idx >= 8 * n
+    sp = _lib.bsort_sort_pairs
+    assert sp(None, 0, 4, 0, 0, None, 8, None, None, 0, None) == _lib.OK   # n = 0
+    assert sp(fake, 0, 4, 10, 0, fake, 3, None, fake, 1 << 30, None) == _lib.EINVAL
+    assert sp(fake, 0, 4, 10, 1 << 7, fake, 8, None, fake, 1 << 30, None) == _lib.EINVAL
+    assert sp(fake, 0, 4, 10, 0, None, 8, None, fake, 1 << 30, None) == _lib.EINVAL
+    assert sp(fake, 0, 4, 10, 0, fake + 4, 8, None, fake, 1 << 30, None) == _lib.EINVAL
+    need = psb(4, 1000, 1, 8, 0, 0)
+    assert sp(fake, 0, 4, 1000, 0, fake, 8, None, fake, need - 1, None) == _lib.ESCRATCH
+    assert sp(fake, 0, 4, 1 << 32, 0, fake, 8, None, fake, 1 << 62, None) == _lib.ETOOBIG
+    spg = _lib.bsort_segmented_pairs
+    assert spg(fake, 0, 4, None, 3, 10, 0, fake, 8, None, fake, 1 << 30, None) == _lib.EINVAL
+    assert spg(fake, 0, 4, fake, 0, 10, 0, fake, 8, None, fake, 1 << 30, None) == _lib.EINVAL
+    g = _lib.bsort_gather
+    assert g(None, 8, None, None, 0, 0, 0, None, None) == _lib.OK          # n = 0
+    assert g(fake, 8, fake, None, 0, 10, 1, fake, None) == _lib.EINVAL      # flag
+    assert g(fake, 12, fake, None, 0, 10, 0, fake, None) == _lib.EINVAL     # width
+    assert g(fake, 8, fake, None, 0, 10, 0, fake + 2, None) == _lib.EINVAL  # alignment
+    assert g(fake, 8, None, None, 0, 10, 0, fake, None) == _lib.EINVAL      # no indices
+    assert g(fake, 8, fake, fake, 0, 10, 0, fake, None) == _lib.EINVAL      # offsets, no segments
+
+
 def test_torch_dtype_mapping():
     import torch
     from paper_2603_08929_amd import api
