@@ -368,6 +368,92 @@ def extras_small(lib, torch, np, dev, stream):
             "bit_exact_equal": same}
 
 
+def extras_pairs(lib, torch, np, dev, stream):
+    """Argsort and key-value modes on the f32 N(0,1) 2^26-key array (the
+    indexed sort beside them, outputs compared bit for bit), the payload
+    gather alone, and a small-key-width workload: 2^24 tokens routed by an
+    8-bit id (256 ids) and a 16-bit id (4096 ids) with 8-byte payloads,
+    checked against torch's stable sort."""
+    from paper_2603_08929_amd import workloads as W
+    log("argsort and key-value modes")
+    n = 1 << 26
+    src = torch.from_numpy(W.normal_bits("f32", n, 0).view(np.int32)).to(dev)
+    keys = torch.empty_like(src)
+    idx = torch.empty(n, dtype=torch.int32, device=dev)
+    idx2 = torch.empty_like(idx)
+    vals0 = torch.arange(n, dtype=torch.int64, device=dev) * 2654435761
+    vals = torch.empty_like(vals0)
+    out = torch.empty_like(vals0)
+    need = max(lib.bsort_scratch_bytes(4, n, 1, 1, 0),
+               lib.bsort_scratch_bytes(4, n, 1, 1, lib.KEYS_UNCHANGED),
+               lib.bsort_pairs_scratch_bytes(4, n, 1, 8, 0, 0))
+    scratch = torch.empty(need, dtype=torch.uint8, device=dev)
+    sp, sn = scratch.data_ptr(), scratch.numel()
+
+    def med(prep, fn, reps=5):
+        ts = []
+        for _ in range(reps + 1):
+            prep()
+            torch.cuda.synchronize()
+            ts.append(timed(fn, 1, torch))
+        return sorted(ts[1:])[reps // 2]
+
+    def cp_keys():
+        keys.copy_(src)
+
+    def cp_both():
+        keys.copy_(src)
+        vals.copy_(vals0)
+
+    t_idx = med(cp_keys, lambda: lib.check(lib.bsort_f32(keys.data_ptr(), n, 0, idx.data_ptr(),
+                                                          sp, sn, stream), "f32"))
+    ref_keys = keys.clone()
+    t_arg = med(cp_keys, lambda: lib.check(lib.bsort_f32(keys.data_ptr(), n, lib.KEYS_UNCHANGED,
+                                                          idx2.data_ptr(), sp, sn, stream), "arg"))
+    arg_ok = bool(torch.equal(keys, src) and torch.equal(idx2, idx))
+    t_pair = med(cp_both, lambda: lib.check(lib.bsort_sort_pairs(
+        keys.data_ptr(), lib.KEY_F, 4, n, 0, vals.data_ptr(), 8, None, sp, sn, stream), "pairs"))
+    pair_ok = bool(torch.equal(keys, ref_keys) and torch.equal(vals, vals0[idx.long()]))
+    t_g = med(lambda: None, lambda: lib.check(lib.bsort_gather(
+        vals0.data_ptr(), 8, idx.data_ptr(), None, 0, n, 0, out.data_ptr(), stream), "gather"))
+    gather_ok = bool(torch.equal(out, vals0[idx.long()]))
+    res = {"f32_normal_2p26": {
+        "indexed_sort_ms": round(t_idx, 3), "argsort_ms": round(t_arg, 3),
+        "pairs_8B_ms": round(t_pair, 3), "pairs_8B_gkeys_s": round(n / t_pair / 1e6, 3),
+        "gather_8B_ms": round(t_g, 3),
+        "gather_alg_GBps": round(20.0 * n / t_g / 1e6, 1),  # 4 B index + 8 B read + 8 B write
+        "bit_exact_equal": arg_ok and pair_ok and gather_ok}}
+    del keys, idx, idx2, vals0, vals, out, scratch
+    torch.cuda.empty_cache()
+    routing = []
+    m = 1 << 24
+    rng = np.random.default_rng(0)
+    for kname, kb, kt, hi, tdt in (("u8", 1, lib.KEY_U, 256, torch.uint8),
+                                   ("i16", 2, lib.KEY_I, 4096, torch.int16)):
+        ids = torch.from_numpy(rng.integers(0, hi, size=m).astype(np.int64)).to(dev).to(tdt)
+        tok0 = torch.arange(m, dtype=torch.int64, device=dev)
+        k = torch.empty_like(ids)
+        v = torch.empty_like(tok0)
+        need = lib.bsort_pairs_scratch_bytes(kb, m, 1, 8, 0, 0)
+        scr = torch.empty(need, dtype=torch.uint8, device=dev)
+
+        def prep():
+            k.copy_(ids)
+            v.copy_(tok0)
+
+        t = med(prep, lambda: lib.check(lib.bsort_sort_pairs(
+            k.data_ptr(), kt, kb, m, 0, v.data_ptr(), 8, None, scr.data_ptr(), scr.numel(),
+            stream), "routing"))
+        rv, ri = torch.sort(ids.to(torch.int32), stable=True)
+        ok = bool(torch.equal(k.to(torch.int32), rv) and torch.equal(v, ri))
+        routing.append({"key": f"{kname} ids in [0, {hi})", "tokens": m, "value_bytes": 8,
+                        "ms": round(t, 3), "gkeys_s": round(m / t / 1e6, 3),
+                        "equal_torch_stable_sort": ok})
+        del ids, tok0, k, v, scr, rv, ri
+    res["token_routing"] = routing
+    return res
+
+
 def extras_backward(lib, torch, np, dev, stream):
     from paper_2603_08929_amd.autograd import sort_along
     out = []
@@ -532,7 +618,8 @@ def main() -> int:
         extras = {"word_size_sweep": extras_word_size(_lib, torch, np, dev, stream),
                   "batched_vs_per_array": extras_batched(_lib, torch, np, dev, stream),
                   "small_u32_64k": extras_small(_lib, torch, np, dev, stream),
-                  "differentiable_sort": extras_backward(_lib, torch, np, dev, stream)}
+                  "differentiable_sort": extras_backward(_lib, torch, np, dev, stream),
+                  "argsort_and_pairs": extras_pairs(_lib, torch, np, dev, stream)}
 
     cpu = None
     if not args.no_cpu_baseline:
