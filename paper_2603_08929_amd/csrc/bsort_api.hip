@@ -98,7 +98,6 @@ template <typename KT, int V>
 struct FinishShape {
   static constexpr int FB = V == 1 ? 256 : 512;
   static constexpr int FIPT = (V == 2 ? 8 : 16) / (sizeof(KT) == 8 ? 2 : 1);
-  static constexpr int FRB = 5;
   static constexpr uint32_t TFIN = FB * FIPT;
 };
 
@@ -353,7 +352,7 @@ int launch_all(KT *keys, uint64_t n, const int64_t *offsets, uint64_t B, int mod
   fa.desc = desc;
   fa.idx64 = idx64;
   fa.no_skip = no_skip;
-  auto fk = finish_kernel<KT, IDX, FS::FB, FS::FIPT, FS::FRB>;
+  auto fk = finish_kernel<KT, IDX, FS::FB, FS::FIPT>;
   static const int occ_fin = occupancy(fk, FS::FB);
   const uint32_t fgrid = clamp_grid(L.fmax, (uint64_t)cus * occ_fin / gdiv);
   hipLaunchKernelGGL(fk, dim3(fgrid), dim3(FS::FB), 0, st, fa);

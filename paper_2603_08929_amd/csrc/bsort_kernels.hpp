@@ -1135,37 +1135,30 @@ constexpr int finish_waves_per_eu(int block, int ipt) {
 // segment's keys share every bit above its current bit, so a stable sort of
 // the rank words on the bits where the segment's keys differ is the same
 // result as the remaining bit-by-bit splits.  Those bits are packed into a
-// contiguous code, sorted in stable passes of RB bits, least significant
-// first; each pass ranks keys with wave ballots (the lanes holding the same
-// digit), per-(digit, chunk) counts and one block-wide scan.  The constant
-// bits are put back at the end.
-template <typename KT, bool IDX, int BLOCK, int IPT, int RB>
+// contiguous code, sorted in stable passes of 4 bits, least significant
+// first, with per-(digit, thread) counters in LDS and one block-wide scan per
+// pass.  The constant bits are put back at the end.
+template <typename KT, bool IDX, int BLOCK, int IPT>
 __global__ __launch_bounds__(BLOCK)
 __attribute__((amdgpu_waves_per_eu(finish_waves_per_eu<KT>(BLOCK, IPT))))
 void finish_kernel(FinishArgs<KT> a) {
   constexpr int WAVES = BLOCK / 64;
   constexpr int T = BLOCK * IPT;
-  constexpr int NCH = IPT * WAVES;  // 64-key chunks, in position order
-  constexpr int NDIG = 1 << RB;
-  constexpr int NH = NDIG * NCH;
-  constexpr int HPT = (NH + BLOCK - 1) / BLOCK;  // histogram entries per thread
   using RT = typename std::conditional<sizeof(KT) == 8, uint64_t, uint32_t>::type;
-  // LDS: the codes, the indices, then the (digit, thread) counters of the
-  // 4-byte-and-narrower passes (two 16-bit counters a word) or the (digit,
-  // chunk) histogram of the 8-byte passes.  For the narrow keys the segment
-  // record and the AND/OR partials live in the counter words, which are
-  // unused until the first pass, and the per-wave scan totals in the code
-  // words, which every pass has read into registers before it writes them;
-  // so two 8192-key blocks fit one CU's LDS.
+  // LDS: the codes, the indices, then the (digit, thread) counters (two
+  // 16-bit counters a word).  For keys of at most 4 bytes the segment record
+  // and the AND/OR partials live in the counter words, which are unused
+  // until the first pass, and the per-wave scan totals in the code words,
+  // which every pass has read into registers before it writes them; so two
+  // 8192-key blocks fit one CU's LDS.
   constexpr bool NARROW = sizeof(KT) <= 4;
-  constexpr int CNTW = NARROW ? 8 * BLOCK : NH;
+  constexpr int CNTW = 8 * BLOCK;
   constexpr int SEGW = (int)(sizeof(Seg) / 4);
   constexpr int XW = SEGW + 4 * WAVES + WAVES;  // segment record, AND/OR partials, scan totals
   __shared__ RT s_code[T];
   __shared__ uint32_t s_idx[IDX ? T : 1];
   __shared__ __attribute__((aligned(16))) uint32_t s_cnt[CNTW + (NARROW ? 0 : XW)];
   static_assert(!NARROW || CNTW >= SEGW + 4 * WAVES, "segment record and partials fit the counters");
-  uint32_t *const s_hist = s_cnt;
   Seg &s_seg = *reinterpret_cast<Seg *>(NARROW ? s_cnt : s_cnt + CNTW);
   uint64_t(*const s_red)[WAVES] =
       reinterpret_cast<uint64_t(*)[WAVES]>(s_cnt + (NARROW ? SEGW : CNTW + SEGW));
@@ -1174,7 +1167,6 @@ void finish_kernel(FinishArgs<KT> a) {
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const uint32_t nf = a.hdr->n_finish;
-  const uint64_t lt = (1ull << lane) - 1;
 
   for (uint32_t e = blockIdx.x; e < nf; e += gridDim.x) {
     if (tid == 0) s_seg = a.list[e];
@@ -1253,7 +1245,7 @@ void finish_kernel(FinishArgs<KT> a) {
           m &= ~(RT)(rmask << lo);
         }
       }
-      if constexpr (sizeof(KT) <= 4) {
+      {
         // Stable LSD passes of CRB bits over the packed codes, ranked in
         // blocked order (thread t holds positions t*IPT .. t*IPT + IPT - 1):
         // each item bumps its (digit, thread) counter in LDS in position
@@ -1271,11 +1263,11 @@ void finish_kernel(FinishArgs<KT> a) {
         static_assert((T & (T - 1)) == 0, "power-of-two finish size");
         constexpr int PB = __builtin_ctz((unsigned)T);  // bits of a position
         const RT maxc = (nbits >= (int)(8 * sizeof(RT))) ? (RT)~(RT)0 : (RT)(((RT)1 << nbits) - 1);
-        // With indices, a code of at most 32 - PB bits travels with its
-        // position in one word (code above, position below): the passes
+        // With indices, a code that leaves PB bits of its word free travels
+        // with its position in one word (code above, position below): the passes
         // then move one word per key, and each index is fetched once, by
         // position, at the end.
-        const bool pk = IDX && nbits + PB <= 32;
+        const bool pk = IDX && nbits + PB <= (int)(8 * sizeof(RT));
         const int dsh = pk ? PB : 0;
 #pragma unroll
         for (int i = 0; i < IPT; ++i) {
@@ -1360,81 +1352,6 @@ void finish_kernel(FinishArgs<KT> a) {
           }
         }
         __syncthreads();
-      } else {
-        // 8-byte keys (up to 60 varying bits) take fewer, wider passes: lanes
-        // holding the same RB-bit digit found with RB ballots, per-(digit,
-        // chunk) counts and one block-wide scan.
-        for (int sh = 0; sh < nbits; sh += RB) {
-#pragma unroll
-          for (int h = 0; h < HPT; ++h) {
-            const int x = h * BLOCK + tid;
-            if (x < NH) s_hist[x] = 0;
-          }
-          __syncthreads();
-          uint32_t dg[IPT], rk[IPT];
-#pragma unroll
-          for (int i = 0; i < IPT; ++i) {
-            const bool valid = (uint32_t)(i * BLOCK + tid) < len;
-            const uint32_t d = (uint32_t)(code[i] >> sh) & (uint32_t)(NDIG - 1);
-            // lanes of this 64-key chunk holding the same digit
-            uint64_t peers = __ballot(valid);
-#pragma unroll
-            for (int k = 0; k < RB; ++k) {
-              const uint64_t bk = __ballot((d >> k) & 1u);
-              peers &= ((d >> k) & 1u) ? bk : ~bk;
-            }
-            dg[i] = d;
-            rk[i] = (uint32_t)__popcll(peers & lt);
-            if (valid && (peers & lt) == 0)
-              s_hist[d * NCH + i * WAVES + wave] = (uint32_t)__popcll(peers);
-          }
-          __syncthreads();
-          // exclusive scan of the histogram in (digit, chunk) order
-          {
-            uint32_t v[HPT];
-            uint32_t sum = 0;
-#pragma unroll
-            for (int h = 0; h < HPT; ++h) {
-              const int x = tid * HPT + h;
-              v[h] = x < NH ? s_hist[x] : 0u;
-              sum += v[h];
-            }
-            const uint32_t inc = wave_incl_scan_dpp(sum);
-            if (lane == 63) s_wsum[wave] = inc;
-            __syncthreads();
-            uint32_t base = 0;
-#pragma unroll
-            for (int w2 = 0; w2 < WAVES; ++w2)
-              if (w2 < wave) base += s_wsum[w2];
-            uint32_t ex = base + inc - sum;
-#pragma unroll
-            for (int h = 0; h < HPT; ++h) {
-              const int x = tid * HPT + h;
-              if (x < NH) s_hist[x] = ex;
-              ex += v[h];
-            }
-          }
-          __syncthreads();
-#pragma unroll
-          for (int i = 0; i < IPT; ++i) {
-            const uint32_t p = (uint32_t)(i * BLOCK + tid);
-            if (p < len) {
-              const uint32_t dst = s_hist[dg[i] * NCH + i * WAVES + wave] + rk[i];
-              s_code[dst] = code[i];
-              if (IDX) s_idx[dst] = ix[i];
-            }
-          }
-          __syncthreads();
-#pragma unroll
-          for (int i = 0; i < IPT; ++i) {
-            const uint32_t p = (uint32_t)(i * BLOCK + tid);
-            if (p < len) {
-              code[i] = s_code[p];
-              if (IDX) ix[i] = s_idx[p];
-            }
-          }
-          __syncthreads();
-        }
       }
       // unpack: the sorted bits back into place, the shared bits around them
       {
