@@ -58,6 +58,9 @@ def _load(mutant: int = 0) -> ctypes.CDLL:
     lib.bso_select.restype = ctypes.c_int
     lib.bso_permute_backward.argtypes = [dp, i64p, ctypes.c_uint64, ctypes.c_uint64, dp]
     lib.bso_permute_backward.restype = ctypes.c_int
+    lib.bso_sort128.argtypes = [u64p, u64p, i64p, ctypes.c_uint64, ctypes.c_int, ctypes.c_int,
+                                ctypes.c_int]
+    lib.bso_sort128.restype = ctypes.c_int
     _libs[mutant] = lib
     return lib
 
@@ -102,6 +105,22 @@ def select(keys, w: int, mode: int, asc: bool, j: int, mant_bits: int = 0) -> Tu
     return int(ko.value), int(io.value)
 
 
+def sort128(lo, hi, mode: int, asc: bool = True, mant_bits: int = 112):
+    """Stable sort of 128-bit patterns hi * 2^64 + lo (uint64 arrays).
+    Returns (lo, hi, idx)."""
+    lib = _load()
+    lo = np.ascontiguousarray(np.asarray(lo, dtype=np.uint64)).copy()
+    hi = np.ascontiguousarray(np.asarray(hi, dtype=np.uint64)).copy()
+    if lo.shape != hi.shape:
+        raise ValueError("lo and hi differ in shape")
+    idx = np.arange(lo.size, dtype=np.int64)
+    rc = lib.bso_sort128(_ptr(lo, ctypes.c_uint64), _ptr(hi, ctypes.c_uint64),
+                         _ptr(idx, ctypes.c_int64), lo.size, mode, mant_bits, int(bool(asc)))
+    if rc != 0:
+        raise ValueError(f"bso_sort128 rejected its arguments (rc={rc})")
+    return lo, hi, idx
+
+
 def permute_backward(grad_out: np.ndarray, idx: np.ndarray) -> np.ndarray:
     """grad_in[r, idx[r, j]] = grad_out[r, j] (float64)."""
     lib = _load()
@@ -125,6 +144,8 @@ DTYPES = {
     "e4m3": (8, FLOAT, 3), "e5m2": (8, FLOAT, 2), "f16": (16, FLOAT, 10),
     "bf16": (16, FLOAT, 7), "f32": (32, FLOAT, 23), "f64": (64, FLOAT, 52),
 }
+# 128-bit keys (sort128): mode and mantissa bits
+DTYPES128 = {"u128": (UNSIGNED, 0), "i128": (SIGNED, 0), "f128": (FLOAT, 112)}
 
 
 def sort_dtype(bits: np.ndarray, dtype: str, asc: bool = True, flavour: int = STABLE):

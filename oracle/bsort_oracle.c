@@ -261,6 +261,103 @@ int bso_sort(uint64_t *keys, int64_t *idx, uint64_t n, int w, int mode,
   return 0;
 }
 
+/* ---------------------------------------------------------------- w = 128
+ * The same steps for 128-bit patterns (Section III-C: the method holds for
+ * any word size), stable flavour: Algorithm 1 splits on a single-bit mask
+ * m, Algorithm 2 recurses to the next lower bit, Algorithm 3 inverts the
+ * sign pass, Algorithms 4 and 5 also invert the negative half. */
+typedef unsigned __int128 bso_u128;
+
+typedef struct {
+  bso_u128 *a;
+  int64_t *idx;
+  bso_u128 *tmp_a;
+  int64_t *tmp_i;
+} bso_ctx128;
+
+static uint64_t split128(bso_ctx128 *c, bso_u128 m, uint64_t ps, uint64_t pe, int asc) {
+  uint64_t k = ps, nsecond = 0;
+  for (uint64_t i = ps; i < pe; ++i) {
+    const int set = (c->a[i] & m) != 0;
+    if ((asc && !set) || (!asc && set)) {
+      c->a[k] = c->a[i];
+      if (c->idx) c->idx[k] = c->idx[i];
+      k++;
+    } else {
+      c->tmp_a[nsecond] = c->a[i];
+      if (c->idx) c->tmp_i[nsecond] = c->idx[i];
+      nsecond++;
+    }
+  }
+  memcpy(c->a + k, c->tmp_a, nsecond * sizeof(bso_u128));
+  if (c->idx) memcpy(c->idx + k, c->tmp_i, nsecond * sizeof(int64_t));
+  return k;
+}
+
+static void bqs128(bso_ctx128 *c, bso_u128 m, uint64_t ps, uint64_t pe, int asc) {
+  if (pe - ps < 2 || m == 0) return;
+  const uint64_t k = split128(c, m, ps, pe, asc);
+  bqs128(c, m >> 1, ps, k, asc);
+  bqs128(c, m >> 1, k, pe, asc);
+}
+
+static void bsortf128(bso_ctx128 *c, bso_u128 m, uint64_t ps, uint64_t pe, int asc,
+                      int mant_bits) {
+  if (pe - ps < 2 || m == 0) return;
+  const uint64_t k = split128(c, m, ps, pe, asc);
+  if (m == ((bso_u128)1 << mant_bits)) {
+    bqs128(c, m >> 1, ps, k, asc);
+    bqs128(c, m >> 1, k, pe, asc);
+    return;
+  }
+  bsortf128(c, m >> 1, ps, k, asc, mant_bits);
+  bsortf128(c, m >> 1, k, pe, asc, mant_bits);
+}
+
+int bso_sort128(uint64_t *lo, uint64_t *hi, int64_t *idx, uint64_t n, int mode,
+                int mant_bits, int asc) {
+  if (mode != BSO_UNSIGNED && mode != BSO_SIGNED && mode != BSO_FLOAT) return -1;
+  if (mode == BSO_FLOAT && (mant_bits < 0 || mant_bits > 126)) return -1;
+  if (n > 0 && (!lo || !hi)) return -1;
+  bso_ctx128 c;
+  memset(&c, 0, sizeof c);
+  c.idx = idx;
+  if (n > 0) {
+    c.a = (bso_u128 *)malloc(n * sizeof(bso_u128));
+    c.tmp_a = (bso_u128 *)malloc(n * sizeof(bso_u128));
+    c.tmp_i = (int64_t *)malloc(n * sizeof(int64_t));
+    if (!c.a || !c.tmp_a || !c.tmp_i) {
+      free(c.a); free(c.tmp_a); free(c.tmp_i);
+      return -1;
+    }
+    for (uint64_t i = 0; i < n; ++i) c.a[i] = ((bso_u128)hi[i] << 64) | lo[i];
+  }
+  const bso_u128 top = (bso_u128)1 << 127;
+  if (n >= 2) {
+    if (mode == BSO_UNSIGNED) {
+      bqs128(&c, top, 0, n, asc);
+    } else if (mode == BSO_SIGNED) {
+      const uint64_t k = split128(&c, top, 0, n, !asc);
+      bqs128(&c, top >> 1, 0, k, asc);
+      bqs128(&c, top >> 1, k, n, asc);
+    } else {
+      const uint64_t k = split128(&c, top, 0, n, !asc);
+      const uint64_t neg_ps = asc ? 0 : k, neg_pe = asc ? k : n;
+      const uint64_t pos_ps = asc ? k : 0, pos_pe = asc ? n : k;
+      bsortf128(&c, top >> 1, neg_ps, neg_pe, !asc, mant_bits);
+      bsortf128(&c, top >> 1, pos_ps, pos_pe, asc, mant_bits);
+    }
+  }
+  for (uint64_t i = 0; i < n; ++i) {
+    lo[i] = (uint64_t)c.a[i];
+    hi[i] = (uint64_t)(c.a[i] >> 64);
+  }
+  free(c.a);
+  free(c.tmp_a);
+  free(c.tmp_i);
+  return 0;
+}
+
 /*
  * Quickselect with the paper's partition: run the same sequence of
  * partitions as bso_sort (stable flavour) but descend only into the side

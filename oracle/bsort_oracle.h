@@ -59,6 +59,16 @@ int bso_select(const uint64_t *keys, uint64_t n, int w, int mode,
                int mant_bits, int asc, uint64_t j, uint64_t *key_out,
                int64_t *idx_out);
 
+/*
+ * 128-bit keys: the same algorithms with w = 128, stable flavour.  Key i is
+ * the pattern hi[i] * 2^64 + lo[i]; lo and hi are sorted in place, idx
+ * (nullable) is permuted with them.  Float mode: sign bit 127, mantissa of
+ * mant_bits bits (0 <= mant_bits <= 126; 112 for IEEE binary128).
+ * Returns 0 or -1.
+ */
+int bso_sort128(uint64_t *lo, uint64_t *hi, int64_t *idx, uint64_t n, int mode,
+                int mant_bits, int asc);
+
 /* Backward of values = x[idx] along each row: grad_in[r, idx[r,j]] =
  * grad_out[r,j] (the derivative of a gather by a permutation).  Doubles.
  * Returns 0, or -1 if a row of idx is not a permutation. */
