@@ -190,6 +190,24 @@ int bsort_gather(const void *values, int value_bytes, const void *indices,
                  const int64_t *offsets, uint64_t num_segments, uint64_t n, uint32_t flags,
                  void *out, void *stream);
 
+/* ---- 128-bit keys ----
+ *
+ * Section III-C notes that the method carries over to any word size.  Key i
+ * is the 16 bytes keys[2i] (low word) and keys[2i+1] (high word), 16-byte
+ * aligned; key_type BSORT_KEY_U, BSORT_KEY_I (two's complement) or
+ * BSORT_KEY_F (sign | exponent | mantissa, e.g. IEEE binary128).  The order
+ * and the stable permutation are those of the sorts above at w = 128.  The
+ * keys are sorted most significant word first: the high words (the low
+ * words moving with them), then the low words within each run of equal high
+ * words.  Flags: BSORT_DESCENDING, BSORT_IDX64, BSORT_KEYS_UNCHANGED (then
+ * indices are required) and BSORT_NO_SKIP / BSORT_NO_FINISH, which apply to
+ * both word sorts.  Scratch: at least bsort_scratch_bytes128(...) bytes,
+ * 256-byte aligned; indices aligned to their width.
+ */
+size_t bsort_scratch_bytes128(uint64_t n, int with_indices, uint32_t flags);
+int bsort_sort128(void *keys, int key_type, uint64_t n, uint32_t flags, void *indices,
+                  void *scratch, size_t scratch_bytes, void *stream);
+
 /* ---- launch configurations and the autotuner ----
  *
  * Section V proposes handing partitions to a cache-resident routine once

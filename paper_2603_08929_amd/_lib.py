@@ -37,7 +37,8 @@ SYMBOLS = ["bsort_scratch_bytes", "bsort_sort", "bsort_segmented", "bsort_segmen
            "bsort_config_name", "bsort_config_override", "bsort_tuned_config",
            "bsort_autotune", "bsort_autotune_reset", "bsort_graph_create",
            "bsort_graph_launch", "bsort_graph_destroy", "bsort_pairs_scratch_bytes",
-           "bsort_sort_pairs", "bsort_segmented_pairs", "bsort_gather"] + [f"bsort_{t}" for t in TYPED]
+           "bsort_sort_pairs", "bsort_segmented_pairs", "bsort_gather",
+           "bsort_scratch_bytes128", "bsort_sort128"] + [f"bsort_{t}" for t in TYPED]
 
 lib.bsort_scratch_bytes.argtypes = [_i, _u64, _u64, _i, _u32]
 lib.bsort_scratch_bytes.restype = _sz
@@ -64,6 +65,10 @@ lib.bsort_segmented_pairs.argtypes = [_vp, _i, _i, _vp, _u64, _u64, _u32, _vp, _
 lib.bsort_segmented_pairs.restype = _i
 lib.bsort_gather.argtypes = [_vp, _i, _vp, _vp, _u64, _u64, _u32, _vp, _vp]
 lib.bsort_gather.restype = _i
+lib.bsort_scratch_bytes128.argtypes = [_u64, _i, _u32]
+lib.bsort_scratch_bytes128.restype = _sz
+lib.bsort_sort128.argtypes = [_vp, _i, _u64, _u32, _vp, _vp, _sz, _vp]
+lib.bsort_sort128.restype = _i
 lib.bsort_strerror.argtypes = [_i]
 lib.bsort_strerror.restype = ctypes.c_char_p
 lib.bsort_device_status.argtypes = [_vp, _vp]
@@ -132,5 +137,7 @@ bsort_pairs_scratch_bytes = lib.bsort_pairs_scratch_bytes
 bsort_sort_pairs = lib.bsort_sort_pairs
 bsort_segmented_pairs = lib.bsort_segmented_pairs
 bsort_gather = lib.bsort_gather
+bsort_scratch_bytes128 = lib.bsort_scratch_bytes128
+bsort_sort128 = lib.bsort_sort128
 for _t in TYPED:
     globals()[f"bsort_{_t}"] = getattr(lib, f"bsort_{_t}")

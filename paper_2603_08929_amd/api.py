@@ -211,6 +211,30 @@ def gather(values: torch.Tensor, indices: torch.Tensor,
     return out
 
 
+def sort128_(keys: torch.Tensor, family: str = "u", descending: bool = False,
+             return_indices: bool = True, idx64: bool = False, flags: int = 0
+             ) -> Optional[torch.Tensor]:
+    """Sorts 128-bit keys in place: a contiguous (n, 2) 64-bit tensor, row i
+    being key i's low and high words.  family: 'u' unsigned, 'i' two's
+    complement, 'f' sign | exponent | mantissa (IEEE binary128).  Returns
+    the stable permutation or None."""
+    if not keys.is_cuda or keys.dim() != 2 or keys.shape[1] != 2 or not keys.is_contiguous() \
+            or keys.element_size() != 8:
+        raise ValueError("bsort.sort128_: need a contiguous (n, 2) 64-bit GPU tensor")
+    kt = {"u": KEY_U, "i": KEY_I, "f": KEY_F}[family]
+    n = keys.shape[0]
+    fl = _flags(descending, flags, idx64 and return_indices)
+    idx = None
+    if return_indices:
+        idx = torch.empty(n, dtype=torch.int64 if idx64 else torch.int32, device=keys.device)
+    need = _lib.bsort_scratch_bytes128(n, int(return_indices), fl)
+    scratch = torch.empty(max(need, 256), dtype=torch.uint8, device=keys.device)
+    rc = _lib.bsort_sort128(keys.data_ptr(), kt, n, fl, idx.data_ptr() if idx is not None else None,
+                            scratch.data_ptr(), scratch.numel(), _stream(keys.device))
+    _lib.check(rc, "bsort_sort128")
+    return idx
+
+
 def device_status(scratch: torch.Tensor) -> int:
     return int(_lib.bsort_device_status(scratch.data_ptr(), _stream(scratch.device)))
 

@@ -568,6 +568,105 @@ int sort_pairs(void *keys, int key_type, int key_bytes, const int64_t *offsets, 
   return BSORT_OK;
 }
 
+// 128-bit keys: scratch for the high and low words, the two permutations,
+// the run offsets, the block maxima of their scan, then the scratch of the
+// inner sorts (the larger of the key-value sort and the segmented sort).
+struct WideLayout {
+  size_t hi, lo, idx1, idx2, offs, bmax, inner, inner_bytes, total;
+};
+constexpr uint32_t WIDE_FLAGS = BSORT_DESCENDING | BSORT_NO_SKIP | BSORT_NO_FINISH |
+                                BSORT_IDX64 | BSORT_KEYS_UNCHANGED;
+bool wide_layout(uint64_t n, uint32_t flags, WideLayout *W) {
+  if (flags & ~WIDE_FLAGS) return false;
+  const uint32_t inner = flags & (BSORT_NO_SKIP | BSORT_NO_FINISH | BSORT_IDX64);
+  const size_t ib = (flags & BSORT_IDX64) ? 8 : 4;
+  size_t off = 0;
+  W->hi = off; off = up256(off + n * 8);
+  W->lo = off; off = up256(off + n * 8);
+  W->idx1 = off; off = up256(off + n * ib);
+  W->idx2 = off; off = up256(off + n * ib);
+  W->offs = off; off = up256(off + (n + 1) * 8);
+  W->bmax = off; off = up256(off + ((n + RCH - 1) / RCH + 1) * 8);
+  PairLayout P;
+  if (!pair_layout(8, n, 1, 8, true, inner, &P)) return false;
+  Layout L;
+  if (!make_layout(8, n, n ? n : 1, true, inner, tile_of(8, 1), tfin_of(8, 1), &L)) return false;
+  W->inner = off;
+  W->inner_bytes = P.total > L.total ? P.total : L.total;
+  off = up256(off + W->inner_bytes);
+  W->total = off;
+  return true;
+}
+
+int sort128(void *keys, int key_type, uint64_t n, uint32_t flags, void *indices, void *scratch,
+            size_t scratch_bytes, void *stream) {
+  if (key_type != BSORT_KEY_U && key_type != BSORT_KEY_I && key_type != BSORT_KEY_F)
+    return BSORT_EINVAL;
+  if (flags & ~WIDE_FLAGS) return BSORT_EINVAL;
+  if (n == 0) return BSORT_OK;
+  if (!keys || !scratch) return BSORT_EINVAL;
+  if ((flags & BSORT_KEYS_UNCHANGED) && !indices) return BSORT_EINVAL;
+  if ((reinterpret_cast<uintptr_t>(keys) & 15) || (reinterpret_cast<uintptr_t>(scratch) & 255) ||
+      (reinterpret_cast<uintptr_t>(indices) & ((flags & BSORT_IDX64) ? 7 : 3)))
+    return BSORT_EINVAL;
+  if (n >= (1ull << 32)) return BSORT_ETOOBIG;
+  WideLayout W;
+  if (!wide_layout(n, flags, &W)) return BSORT_EINVAL;
+  if (scratch_bytes < W.total) return BSORT_ESCRATCH;
+  int cus = 0;
+  int rc = device_check(&cus);
+  if (rc != BSORT_OK) return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char *scr = static_cast<char *>(scratch);
+  uint64_t *hi = reinterpret_cast<uint64_t *>(scr + W.hi);
+  uint64_t *lo = reinterpret_cast<uint64_t *>(scr + W.lo);
+  void *idx1 = scr + W.idx1;
+  void *idx2 = scr + W.idx2;
+  int64_t *offs = reinterpret_cast<int64_t *>(scr + W.offs);
+  int64_t *bmax = reinterpret_cast<int64_t *>(scr + W.bmax);
+  void *inner = scr + W.inner;
+  const uint32_t iflags = flags & (BSORT_NO_SKIP | BSORT_NO_FINISH | BSORT_IDX64);
+  const int desc = (flags & BSORT_DESCENDING) ? 1 : 0;
+  // the inner calls are validated before anything is enqueued
+  rc = dispatch(lo, BSORT_KEY_U, 8, n, offs, n, true, iflags, idx2, inner, W.inner_bytes,
+                stream, CONFIG_DRY_RUN);
+  if (rc != BSORT_OK) return rc;
+  const uint32_t g = clamp_grid((n + 255) / 256, (uint64_t)cus * 8);
+  hipLaunchKernelGGL(wide_split_kernel, dim3(g), dim3(256), 0, st,
+                     static_cast<const uint64_t *>(keys), n, key_type, desc, hi, lo);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  // high words first, the low words moving with them
+  rc = sort_pairs(hi, BSORT_KEY_U, 8, nullptr, 1, false, n, iflags, lo, 8, idx1, inner,
+                  W.inner_bytes, stream);
+  if (rc != BSORT_OK) return rc;
+  // runs of equal high words -> segments; the low words sorted within them
+  const uint64_t nb = (n + RCH - 1) / RCH;
+  hipLaunchKernelGGL(run_start_local_kernel, dim3((uint32_t)nb), dim3(256), 0, st, hi, n, offs,
+                     bmax);
+  hipLaunchKernelGGL(run_start_blocks_kernel, dim3(1), dim3(1024), 0, st, bmax, nb);
+  hipLaunchKernelGGL(run_start_final_kernel, dim3(clamp_grid((n + 256) / 256, (uint64_t)cus * 8)),
+                     dim3(256), 0, st, offs, bmax, n);
+  e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  rc = dispatch(lo, BSORT_KEY_U, 8, n, offs, n, true, iflags, idx2, inner, W.inner_bytes, stream);
+  if (rc != BSORT_OK) return rc;
+  // the key's permutation: first the high-word sort's, within each run the
+  // low-word sort's
+  if (indices) {
+    rc = launch_gather(idx1, (flags & BSORT_IDX64) ? 8 : 4, idx2, (flags & BSORT_IDX64) != 0,
+                       offs, n, n, indices, cus, st);
+    if (rc != BSORT_OK) return rc;
+  }
+  if (!(flags & BSORT_KEYS_UNCHANGED)) {
+    hipLaunchKernelGGL(wide_merge_kernel, dim3(g), dim3(256), 0, st, hi, lo, n, key_type, desc,
+                       static_cast<uint64_t *>(keys));
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  }
+  return BSORT_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -704,6 +803,18 @@ int bsort_gather(const void *values, int value_bytes, const void *indices,
   if (rc != BSORT_OK) return rc;
   return launch_gather(values, value_bytes, indices, (flags & BSORT_IDX64) != 0, offsets,
                        offsets ? num_segments : 1, n, out, cus, static_cast<hipStream_t>(stream));
+}
+
+size_t bsort_scratch_bytes128(uint64_t n, int with_indices, uint32_t flags) {
+  (void)with_indices;  // the permutation is always built
+  WideLayout W;
+  if (!wide_layout(n, flags, &W)) return 0;
+  return W.total;
+}
+
+int bsort_sort128(void *keys, int key_type, uint64_t n, uint32_t flags, void *indices,
+                  void *scratch, size_t scratch_bytes, void *stream) {
+  return sort128(keys, key_type, n, flags, indices, scratch, scratch_bytes, stream);
 }
 
 int bsort_config_count(void) { return N_CONFIGS; }

@@ -1515,4 +1515,142 @@ __global__ __launch_bounds__(256) void gather_kernel(const VT *values, const voi
   }
 }
 
+// ------------------------------------------------------------ 128-bit keys
+//
+// A 128-bit key (low word first) is sorted most significant word first, as
+// the method recurses on the lower bits within each part that agrees on the
+// higher ones: the high words are sorted (the low words travel with them),
+// the runs of equal high words become segments, and the low words are sorted
+// within them.  Both sorts run on the rank word v of the key, whose bit b is
+// 1 exactly when the key goes back in a split on bit b (Algorithms 1 and 3-5
+// with the direction rules of Section III), so the words are sorted as
+// unsigned in ascending order.
+
+__device__ __forceinline__ void rank_word128(uint64_t &lo, uint64_t &hi, int mode, int desc) {
+  const uint64_t top = 1ull << 63;
+  uint64_t ml = desc ? ~0ull : 0ull, mh = ml;
+  if (mode != MODE_U) mh ^= top;
+  if (mode == MODE_F && (hi & top)) {
+    ml = ~ml;
+    mh ^= ~top;
+  }
+  lo ^= ml;
+  hi ^= mh;
+}
+
+__global__ void wide_split_kernel(const uint64_t *keys, uint64_t n, int mode, int desc,
+                                  uint64_t *hi, uint64_t *lo) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    uint64_t l = keys[2 * i], h = keys[2 * i + 1];
+    rank_word128(l, h, mode, desc);
+    lo[i] = l;
+    hi[i] = h;
+  }
+}
+
+// Keys back from sorted rank words: the rank word is the key with bits
+// flipped by a mask that depends only on the sign, so flipping again by the
+// mask of the key's sign restores it.
+__global__ void wide_merge_kernel(const uint64_t *hi, const uint64_t *lo, uint64_t n, int mode,
+                                  int desc, uint64_t *keys) {
+  const uint64_t top = 1ull << 63;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    uint64_t l = lo[i], h = hi[i];
+    if (desc) {
+      l = ~l;
+      h = ~h;
+    }
+    if (mode == MODE_I) {
+      h ^= top;
+    } else if (mode == MODE_F) {
+      if (h & top) {
+        h ^= top;  // was a non-negative key
+      } else {
+        l = ~l;  // was negative: every bit was flipped
+        h = ~h;
+      }
+    }
+    keys[2 * i] = l;
+    keys[2 * i + 1] = h;
+  }
+}
+
+// Segments of the low-word sort: offs[j] = start of the run of equal high
+// words holding position j (a prefix maximum of the run starts), offs[n] =
+// n.  Segment j is then [offs[j], offs[j + 1]): empty inside a run, the
+// whole run at its last position.  Three steps: a maximum within each block
+// of RCH positions, an exclusive maximum over the blocks, and the final
+// maximum of both.
+constexpr uint32_t RCH = 4096;
+__global__ __launch_bounds__(256) void run_start_local_kernel(const uint64_t *hi, uint64_t n,
+                                                              int64_t *offs, int64_t *bmax) {
+  __shared__ int64_t s_m[256];
+  constexpr uint32_t PER = RCH / 256;
+  const uint64_t b0 = (uint64_t)blockIdx.x * RCH;
+  const uint64_t t0 = b0 + (uint64_t)threadIdx.x * PER;
+  int64_t m = 0;
+  for (uint32_t k = 0; k < PER; ++k) {
+    const uint64_t j = t0 + k;
+    if (j < n && (j == 0 || hi[j] != hi[j - 1])) m = (int64_t)j;
+  }
+  s_m[threadIdx.x] = m;
+  __syncthreads();
+  // inclusive maximum scan over the threads (Hillis-Steele)
+  for (int d = 1; d < 256; d <<= 1) {
+    const int64_t o = threadIdx.x >= (unsigned)d ? s_m[threadIdx.x - d] : 0;
+    __syncthreads();
+    if (o > s_m[threadIdx.x]) s_m[threadIdx.x] = o;
+    __syncthreads();
+  }
+  int64_t run = threadIdx.x ? s_m[threadIdx.x - 1] : 0;
+  for (uint32_t k = 0; k < PER; ++k) {
+    const uint64_t j = t0 + k;
+    if (j < n) {
+      if (j == 0 || hi[j] != hi[j - 1]) run = (int64_t)j;
+      offs[j] = run;
+    }
+  }
+  if (threadIdx.x == 255) bmax[blockIdx.x] = s_m[255];
+}
+
+__global__ __launch_bounds__(1024) void run_start_blocks_kernel(int64_t *bmax, uint64_t nb) {
+  // exclusive maximum over the block maxima, one block, PER blocks a thread
+  __shared__ int64_t s_m[1024];
+  const uint64_t per = (nb + 1023) / 1024;
+  const uint64_t t0 = (uint64_t)threadIdx.x * per;
+  int64_t m = 0;
+  for (uint64_t k = 0; k < per; ++k)
+    if (t0 + k < nb && bmax[t0 + k] > m) m = bmax[t0 + k];
+  s_m[threadIdx.x] = m;
+  __syncthreads();
+  for (int d = 1; d < 1024; d <<= 1) {
+    const int64_t o = threadIdx.x >= (unsigned)d ? s_m[threadIdx.x - d] : 0;
+    __syncthreads();
+    if (o > s_m[threadIdx.x]) s_m[threadIdx.x] = o;
+    __syncthreads();
+  }
+  int64_t run = threadIdx.x ? s_m[threadIdx.x - 1] : 0;
+  for (uint64_t k = 0; k < per; ++k) {
+    if (t0 + k < nb) {
+      const int64_t v = bmax[t0 + k];
+      bmax[t0 + k] = run;
+      if (v > run) run = v;
+    }
+  }
+}
+
+__global__ void run_start_final_kernel(int64_t *offs, const int64_t *bexc, uint64_t n) {
+  for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j <= n;
+       j += (uint64_t)gridDim.x * blockDim.x) {
+    if (j == n) {
+      offs[n] = (int64_t)n;
+    } else {
+      const int64_t e = bexc[j / RCH];
+      if (e > offs[j]) offs[j] = e;
+    }
+  }
+}
+
 }  // namespace bsort

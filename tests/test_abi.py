@@ -175,3 +175,23 @@ def test_configurations_and_graph_without_device():
                                    1 << 30) == _lib.EINVAL
     assert _lib.bsort_autotune(fake, 0, 4, None, 1, 10, 1 << 9, None, fake, 1 << 30, None,
                                1) == _lib.EINVAL
+
+
+def test_sort128_validation():
+    fake = 1 << 40
+    sb = _lib.bsort_scratch_bytes128
+    n = 1 << 20
+    assert sb(n, 1, 1 << 7) == 0                       # unknown flag
+    base = sb(n, 1, 0)
+    assert base >= 16 * n + 8 * n                      # words, permutations, offsets
+    assert sb(n, 1, _lib.IDX64) - base >= 8 * n        # wider permutations
+    f = _lib.bsort_sort128
+    assert f(None, 0, 0, 0, None, None, 0, None) == _lib.OK                        # n = 0
+    assert f(fake, 3, 10, 0, fake, fake, 1 << 30, None) == _lib.EINVAL              # key type
+    assert f(fake, 0, 10, 1 << 7, fake, fake, 1 << 30, None) == _lib.EINVAL         # flag
+    assert f(fake + 8, 0, 10, 0, fake, fake, 1 << 30, None) == _lib.EINVAL          # alignment
+    assert f(fake, 0, 10, 0, fake + 2, fake, 1 << 30, None) == _lib.EINVAL          # idx alignment
+    assert f(fake, 0, 10, _lib.KEYS_UNCHANGED, None, fake, 1 << 30, None) == _lib.EINVAL
+    assert f(fake, 0, 1000, 0, fake, fake, sb(1000, 1, 0) - 1, None) == _lib.ESCRATCH
+    assert f(fake, 0, 1 << 32, 0, fake, fake, 1 << 62, None) == _lib.ETOOBIG
+
