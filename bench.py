@@ -454,6 +454,50 @@ def extras_pairs(lib, torch, np, dev, stream):
     return res
 
 
+def extras_wide(lib, torch, np, dev, stream):
+    """128-bit keys, 2^26 of them with u32 indices: uniform patterns (every
+    high word distinct, so the low-word pass has nothing to do), and high
+    words drawn from 1024 values (runs of ~2^16 keys that the low-word pass
+    sorts)."""
+    log("128-bit keys")
+    n = 1 << 26
+    rng = np.random.default_rng(0)
+    out = []
+    for name, nhi in (("u128 uniform", 0), ("u128, 1024 distinct high words", 1024)):
+        lo = rng.integers(0, 1 << 64, size=n, dtype=np.uint64)
+        if nhi:
+            hi = rng.integers(0, 1 << 64, size=nhi, dtype=np.uint64)[rng.integers(0, nhi, size=n)]
+        else:
+            hi = rng.integers(0, 1 << 64, size=n, dtype=np.uint64)
+        src = torch.from_numpy(np.stack([lo, hi], axis=1).view(np.int64)).to(dev)
+        del lo, hi
+        keys = torch.empty_like(src)
+        idx = torch.empty(n, dtype=torch.int32, device=dev)
+        need = lib.bsort_scratch_bytes128(n, 1, 0)
+        scratch = torch.empty(need, dtype=torch.uint8, device=dev)
+        ts = []
+        for _ in range(4):
+            keys.copy_(src)
+            torch.cuda.synchronize()
+            ts.append(timed(lambda: lib.check(lib.bsort_sort128(
+                keys.data_ptr(), lib.KEY_U, n, 0, idx.data_ptr(), scratch.data_ptr(), need,
+                stream), "sort128"), 1, torch))
+        t = sorted(ts[1:])[1]
+        # ordered as 128-bit unsigned (words compared as signed after flipping
+        # their top bits), and the output is the input gathered by idx
+        flip = torch.tensor(-(1 << 63), dtype=torch.int64, device=dev)
+        h, lw = keys[:, 1] ^ flip, keys[:, 0] ^ flip
+        ordered = bool(((h[1:] > h[:-1]) | ((h[1:] == h[:-1]) & (lw[1:] >= lw[:-1]))).all())
+        il = idx.long()
+        same = bool(torch.equal(src[:, 0].contiguous()[il], keys[:, 0].contiguous())
+                    and torch.equal(src[:, 1].contiguous()[il], keys[:, 1].contiguous()))
+        out.append({"keys": name, "n": n, "ms": round(t, 3), "gkeys_s": round(n / t / 1e6, 3),
+                    "ordered": ordered, "gather_of_input_equals_output": same})
+        del src, keys, idx, scratch
+        torch.cuda.empty_cache()
+    return out
+
+
 def extras_backward(lib, torch, np, dev, stream):
     from paper_2603_08929_amd.autograd import sort_along
     out = []
@@ -619,7 +663,8 @@ def main() -> int:
                   "batched_vs_per_array": extras_batched(_lib, torch, np, dev, stream),
                   "small_u32_64k": extras_small(_lib, torch, np, dev, stream),
                   "differentiable_sort": extras_backward(_lib, torch, np, dev, stream),
-                  "argsort_and_pairs": extras_pairs(_lib, torch, np, dev, stream)}
+                  "argsort_and_pairs": extras_pairs(_lib, torch, np, dev, stream),
+                  "keys_128_bit": extras_wide(_lib, torch, np, dev, stream)}
 
     cpu = None
     if not args.no_cpu_baseline:

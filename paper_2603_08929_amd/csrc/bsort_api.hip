@@ -249,6 +249,8 @@ int launch_all(KT *keys, uint64_t n, const int64_t *offsets, uint64_t B, int mod
   sa.w = w;
   sa.with_idx = IDX ? 1 : 0;
   sa.no_finish = no_finish;
+  sa.idx_final = indices;
+  sa.idx64 = idx64;
   hipLaunchKernelGGL(seed_kernel, dim3(clamp_grid((B + 255) / 256, cap)), dim3(256), 0, st, sa);
 
   auto lk = level_kernel<KT, IDX, LS::LB, LS::LIPT>;

@@ -423,6 +423,8 @@ struct SeedArgs {
   int w;
   int with_idx;
   int no_finish;
+  void *idx_final;  // the caller's indices (uint32, or int64 with idx64)
+  int idx64;
 };
 
 __global__ void seed_kernel(SeedArgs a) {
@@ -449,7 +451,11 @@ __global__ void seed_kernel(SeedArgs a) {
       ch[0].len = len;
       ch[0].meta = META_IOTA | (uint32_t)(a.w - 1);
       if (len == 1) {
-        if (a.with_idx) { ch[0].kind = KIND_FINISH; ch[0].meta = META_IOTA | BIT_NONE; }
+        // sorted as it stands: only its index (0) is written
+        if (a.with_idx) {
+          if (a.idx64) static_cast<int64_t *>(a.idx_final)[st] = 0;
+          else static_cast<uint32_t *>(a.idx_final)[st] = 0;
+        }
       } else if (len >= 2) {
         if (!a.no_finish && len <= a.l.t_fin) {
           ch[0].kind = KIND_FINISH;
