@@ -190,6 +190,23 @@ int bsort_gather(const void *values, int value_bytes, const void *indices,
                  const int64_t *offsets, uint64_t num_segments, uint64_t n, uint32_t flags,
                  void *out, void *stream);
 
+/* ---- keys whose order bits are stored in another layout ----
+ *
+ * Section III-C notes that other bit arrangements (a sign that is not the
+ * top bit, fields in another order) sort with small changes.  bit_order
+ * (HOST array of 8 * key_bytes entries, a permutation of 0 .. w-1) lists,
+ * from the most significant order bit down, the stored bit that holds it:
+ * the key is sorted as the w-bit word whose bit w-1-i is stored bit
+ * bit_order[i], read as key_type (for BSORT_KEY_I / BSORT_KEY_F, bit_order[0]
+ * is the sign).  The keys' stored layout is kept in the result.  The bits
+ * are rearranged in place before and after the sort (with
+ * BSORT_KEYS_UNCHANGED the keys come back as they were).  Flags, indices and
+ * scratch as for bsort_sort (scratch from bsort_scratch_bytes).
+ */
+int bsort_sort_layout(void *keys, int key_type, int key_bytes, uint64_t n, uint32_t flags,
+                      const uint8_t *bit_order, void *indices, void *scratch,
+                      size_t scratch_bytes, void *stream);
+
 /* ---- 128-bit keys ----
  *
  * Section III-C notes that the method carries over to any word size.  Key i

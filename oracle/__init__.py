@@ -121,6 +121,49 @@ def sort128(lo, hi, mode: int, asc: bool = True, mant_bits: int = 112):
     return lo, hi, idx
 
 
+def sort_layout(keys, w: int, mode: int, bit_order, asc: bool = True):
+    """Stable sort of w-bit patterns whose order bits are stored in another
+    layout: order bit w-1-i lives in stored bit bit_order[i].  Pure Python
+    (small inputs): Algorithm 1's split on the stored bit of each order bit,
+    Algorithm 2's recursion to the next lower order bit, and the top levels
+    of Algorithms 3 and 4 (sign pass in the inverse direction; for floats
+    the negative half also inverted).  Returns (keys, idx)."""
+    a = [int(k) for k in np.asarray(keys, dtype=np.uint64)]
+    idx = list(range(len(a)))
+    stored = [int(bit_order[w - 1 - b]) for b in range(w)]  # stored bit of order bit b
+
+    def split(b, ps, pe, up):
+        m = 1 << stored[b]
+        first = [i for i in range(ps, pe) if ((a[i] & m) == 0) == up]
+        second = [i for i in range(ps, pe) if ((a[i] & m) == 0) != up]
+        ka = [a[i] for i in first + second]
+        ki = [idx[i] for i in first + second]
+        a[ps:pe], idx[ps:pe] = ka, ki
+        return ps + len(first)
+
+    def bqs(b, ps, pe, up):
+        if pe - ps < 2 or b < 0:
+            return
+        k = split(b, ps, pe, up)
+        bqs(b - 1, ps, k, up)
+        bqs(b - 1, k, pe, up)
+
+    n = len(a)
+    if mode == UNSIGNED:
+        bqs(w - 1, 0, n, asc)
+    elif n >= 2:
+        k = split(w - 1, 0, n, not asc)
+        if mode == SIGNED:
+            bqs(w - 2, 0, k, asc)
+            bqs(w - 2, k, n, asc)
+        else:
+            neg = (0, k) if asc else (k, n)
+            pos = (k, n) if asc else (0, k)
+            bqs(w - 2, neg[0], neg[1], not asc)
+            bqs(w - 2, pos[0], pos[1], asc)
+    return np.array(a, dtype=np.uint64), np.array(idx, dtype=np.int64)
+
+
 def permute_backward(grad_out: np.ndarray, idx: np.ndarray) -> np.ndarray:
     """grad_in[r, idx[r, j]] = grad_out[r, j] (float64)."""
     lib = _load()

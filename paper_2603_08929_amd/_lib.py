@@ -38,7 +38,8 @@ SYMBOLS = ["bsort_scratch_bytes", "bsort_sort", "bsort_segmented", "bsort_segmen
            "bsort_autotune", "bsort_autotune_reset", "bsort_graph_create",
            "bsort_graph_launch", "bsort_graph_destroy", "bsort_pairs_scratch_bytes",
            "bsort_sort_pairs", "bsort_segmented_pairs", "bsort_gather",
-           "bsort_scratch_bytes128", "bsort_sort128"] + [f"bsort_{t}" for t in TYPED]
+           "bsort_scratch_bytes128", "bsort_sort128", "bsort_sort_layout"] + \
+    [f"bsort_{t}" for t in TYPED]
 
 lib.bsort_scratch_bytes.argtypes = [_i, _u64, _u64, _i, _u32]
 lib.bsort_scratch_bytes.restype = _sz
@@ -69,6 +70,9 @@ lib.bsort_scratch_bytes128.argtypes = [_u64, _i, _u32]
 lib.bsort_scratch_bytes128.restype = _sz
 lib.bsort_sort128.argtypes = [_vp, _i, _u64, _u32, _vp, _vp, _sz, _vp]
 lib.bsort_sort128.restype = _i
+lib.bsort_sort_layout.argtypes = [_vp, _i, _i, _u64, _u32, ctypes.POINTER(ctypes.c_uint8), _vp,
+                                  _vp, _sz, _vp]
+lib.bsort_sort_layout.restype = _i
 lib.bsort_strerror.argtypes = [_i]
 lib.bsort_strerror.restype = ctypes.c_char_p
 lib.bsort_device_status.argtypes = [_vp, _vp]
@@ -139,5 +143,6 @@ bsort_segmented_pairs = lib.bsort_segmented_pairs
 bsort_gather = lib.bsort_gather
 bsort_scratch_bytes128 = lib.bsort_scratch_bytes128
 bsort_sort128 = lib.bsort_sort128
+bsort_sort_layout = lib.bsort_sort_layout
 for _t in TYPED:
     globals()[f"bsort_{_t}"] = getattr(lib, f"bsort_{_t}")

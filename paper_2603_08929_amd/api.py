@@ -235,6 +235,34 @@ def sort128_(keys: torch.Tensor, family: str = "u", descending: bool = False,
     return idx
 
 
+def sort_layout_(keys: torch.Tensor, bit_order, family: Optional[str] = None,
+                 descending: bool = False, return_indices: bool = True, idx64: bool = False,
+                 flags: int = 0) -> Optional[torch.Tensor]:
+    """Sorts a contiguous 1-D tensor in place as keys whose order bits are
+    stored in another layout: bit_order[i] is the stored bit of order bit
+    w-1-i (a permutation of 0..w-1).  family: 'u', 'i' or 'f' (default: the
+    dtype's).  Returns the stable permutation or None."""
+    import ctypes
+    kt, kb = key_type(keys.dtype)
+    if family is not None:
+        kt = {"u": KEY_U, "i": KEY_I, "f": KEY_F}[family]
+    if not keys.is_cuda or keys.dim() != 1 or not keys.is_contiguous():
+        raise ValueError("bsort.sort_layout_: need a contiguous 1-D GPU tensor")
+    order = (ctypes.c_uint8 * len(bit_order))(*[int(b) for b in bit_order])
+    n = keys.numel()
+    fl = _flags(descending, flags, idx64 and return_indices)
+    idx = None
+    if return_indices:
+        idx = torch.empty(n, dtype=torch.int64 if idx64 else torch.int32, device=keys.device)
+    need = _lib.bsort_scratch_bytes(kb, n, 1, int(return_indices), fl)
+    scratch = torch.empty(max(need, 256), dtype=torch.uint8, device=keys.device)
+    rc = _lib.bsort_sort_layout(keys.data_ptr(), kt, kb, n, fl, order,
+                                idx.data_ptr() if idx is not None else None, scratch.data_ptr(),
+                                scratch.numel(), _stream(keys.device))
+    _lib.check(rc, "bsort_sort_layout")
+    return idx
+
+
 def device_status(scratch: torch.Tensor) -> int:
     return int(_lib.bsort_device_status(scratch.data_ptr(), _stream(scratch.device)))
 

@@ -819,6 +819,54 @@ int bsort_sort128(void *keys, int key_type, uint64_t n, uint32_t flags, void *in
   return sort128(keys, key_type, n, flags, indices, scratch, scratch_bytes, stream);
 }
 
+int bsort_sort_layout(void *keys, int key_type, int key_bytes, uint64_t n, uint32_t flags,
+                      const uint8_t *bit_order, void *indices, void *scratch,
+                      size_t scratch_bytes, void *stream) {
+  if (key_bytes != 1 && key_bytes != 2 && key_bytes != 4 && key_bytes != 8) return BSORT_EINVAL;
+  if (n == 0) return BSORT_OK;
+  if (!bit_order) return BSORT_EINVAL;
+  const int w = 8 * key_bytes;
+  BitLayout lay;
+  uint64_t seen = 0;
+  for (int j = 0; j < w; ++j) {
+    if (bit_order[j] >= w) return BSORT_EINVAL;
+    seen |= 1ull << bit_order[j];
+    lay.src[j] = bit_order[j];
+  }
+  if (seen != (w == 64 ? ~0ull : ((1ull << w) - 1))) return BSORT_EINVAL;  // not a permutation
+  if (reinterpret_cast<uintptr_t>(keys) & (uintptr_t)(key_bytes - 1)) return BSORT_EINVAL;
+  // the sort's own checks, before anything is enqueued
+  int rc = dispatch(keys, key_type, key_bytes, n, nullptr, 1, false, flags, indices, scratch,
+                    scratch_bytes, stream, CONFIG_DRY_RUN);
+  if (rc != BSORT_OK) return rc;
+  int cus = 0;
+  rc = device_check(&cus);
+  if (rc != BSORT_OK) return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const uint32_t g = clamp_grid((n + 255) / 256, (uint64_t)cus * 8);
+  auto transform = [&](int inverse) {
+    switch (key_bytes) {
+      case 1: hipLaunchKernelGGL(layout_kernel<uint8_t>, dim3(g), dim3(256), 0, st,
+                                 static_cast<uint8_t *>(keys), n, w, lay, inverse); break;
+      case 2: hipLaunchKernelGGL(layout_kernel<uint16_t>, dim3(g), dim3(256), 0, st,
+                                 static_cast<uint16_t *>(keys), n, w, lay, inverse); break;
+      case 4: hipLaunchKernelGGL(layout_kernel<uint32_t>, dim3(g), dim3(256), 0, st,
+                                 static_cast<uint32_t *>(keys), n, w, lay, inverse); break;
+      default: hipLaunchKernelGGL(layout_kernel<uint64_t>, dim3(g), dim3(256), 0, st,
+                                  static_cast<uint64_t *>(keys), n, w, lay, inverse); break;
+    }
+    return hipGetLastError();
+  };
+  hipError_t e = transform(0);
+  if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  rc = dispatch(keys, key_type, key_bytes, n, nullptr, 1, false, flags, indices, scratch,
+                scratch_bytes, stream);
+  if (rc != BSORT_OK) return rc;
+  e = transform(1);
+  if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  return BSORT_OK;
+}
+
 int bsort_config_count(void) { return N_CONFIGS; }
 
 const char *bsort_config_name(int config) {

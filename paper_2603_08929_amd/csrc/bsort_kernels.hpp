@@ -1521,6 +1521,31 @@ __global__ __launch_bounds__(256) void gather_kernel(const VT *values, const voi
   }
 }
 
+// ------------------------------------------------------------- bit layouts
+//
+// Keys whose order bits are not stored most significant first (a sign in
+// the lowest bit, fields in another order): a layout lists, from the most
+// significant order bit down, the stored bit that holds it.  The bits are
+// gathered into that order, the keys sorted, and the bits put back.
+struct BitLayout {
+  uint8_t src[64];  // src[i]: stored bit of order bit w - 1 - i
+};
+
+template <typename KT>
+__global__ void layout_kernel(KT *keys, uint64_t n, int w, BitLayout lay, int inverse) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t k = (uint64_t)keys[i];
+    uint64_t out = 0;
+    for (int j = 0; j < w; ++j) {
+      const int ob = w - 1 - j, sb = lay.src[j];
+      if (!inverse) out |= ((k >> sb) & 1ull) << ob;  // stored -> order
+      else out |= ((k >> ob) & 1ull) << sb;            // order -> stored
+    }
+    keys[i] = (KT)out;
+  }
+}
+
 // ------------------------------------------------------------ 128-bit keys
 //
 // A 128-bit key (low word first) is sorted most significant word first, as

@@ -195,3 +195,20 @@ def test_sort128_validation():
     assert f(fake, 0, 1000, 0, fake, fake, sb(1000, 1, 0) - 1, None) == _lib.ESCRATCH
     assert f(fake, 0, 1 << 32, 0, fake, fake, 1 << 62, None) == _lib.ETOOBIG
 
+
+def test_layout_validation():
+    import ctypes
+    fake = 1 << 40
+    f = _lib.bsort_sort_layout
+    order = (ctypes.c_uint8 * 32)(*range(31, -1, -1))
+    bad = (ctypes.c_uint8 * 32)(*([0] * 32))          # not a permutation
+    big = (ctypes.c_uint8 * 32)(*([40] + list(range(30, -1, -1))))
+    need = _lib.bsort_scratch_bytes(4, 100, 1, 1, 0)
+    assert f(None, 0, 4, 0, 0, None, None, None, 0, None) == _lib.OK        # n = 0
+    assert f(fake, 0, 4, 100, 0, None, fake, fake, need, None) == _lib.EINVAL
+    assert f(fake, 0, 4, 100, 0, bad, fake, fake, need, None) == _lib.EINVAL
+    assert f(fake, 0, 4, 100, 0, big, fake, fake, need, None) == _lib.EINVAL
+    assert f(fake, 0, 3, 100, 0, order, fake, fake, need, None) == _lib.EINVAL
+    assert f(fake + 2, 0, 4, 100, 0, order, fake, fake, need, None) == _lib.EINVAL
+    assert f(fake, 0, 4, 100, 0, order, fake, fake, need - 1, None) == _lib.ESCRATCH
+
