@@ -53,6 +53,9 @@ CALIB_KERNEL = "bitwise_not"
 CALIB_ELEMS = 1 << 28  # int32: 1 GiB read + 1 GiB written
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "level_kernel_u32_idx_2p26_traffic.txt")
 SOURCES = [os.path.join(ROOT, "paper_2603_08929_amd", "csrc", "bsort_kernels.hpp")]  # device code
+# The level kernel and everything it is built from come first in that file;
+# the hash covers the text up to this line, which follows the kernel.
+LEVEL_END = "// Before each level: (1) the per-tile descriptor map"
 
 
 def log(msg: str) -> None:
@@ -72,7 +75,13 @@ def code_hash(texts) -> str:
 
 
 def source_hash() -> str:
-    return code_hash(open(p).read() for p in SOURCES)
+    """Hash of the level kernel's code: the device source up to the end of
+    the level kernel."""
+    text = open(SOURCES[0]).read()
+    cut = text.find(LEVEL_END)
+    if cut < 0:
+        raise RuntimeError("level kernel end marker not found in the device source")
+    return code_hash([text[:cut]])
 
 
 def workload_arrays():
