@@ -101,6 +101,20 @@ struct FinishShape {
   static constexpr uint32_t TFIN = FB * FIPT;
 };
 
+// The finish shape for segments of at most T keys: one wave.
+template <typename KT>
+struct SmallFinish {
+  static constexpr int B = 64;
+  static constexpr int IPT = sizeof(KT) == 8 ? 4 : 8;
+  static constexpr uint32_t T = B * IPT;
+};
+
+struct TinyFinish {
+  static constexpr int B = 64;
+  static constexpr int IPT = 1;
+  static constexpr uint32_t T = 64;
+};
+
 struct Config {
   int lv, fv, grid;  // level shape, finish shape, grid (0 full, 1 half)
 };
@@ -127,8 +141,8 @@ size_t up256(size_t x) { return (x + 255) & ~(size_t)255; }
 // every parent yields at most two finish entries per level; copy entries
 // hold more than T keys each.
 struct Layout {
-  size_t hdr, cnts, segs[2], recs[2], acc[2], split[2], tmap[2], fin, cpy, keys1, idx0, idx1,
-      keys0, total;
+  size_t hdr, cnts, segs[2], recs[2], acc[2], split[2], tmap[2], fin, fins, fint, cpy, keys1,
+      idx0, idx1, keys0, total;
   uint64_t smax, tmax, fmax, cmax;
 };
 
@@ -154,6 +168,8 @@ bool make_layout(int key_bytes, uint64_t n, uint64_t B, bool with_idx, uint32_t 
   for (int i = 0; i < 2; ++i) { L->split[i] = off; off = up256(off + L->smax * 8); }
   for (int i = 0; i < 2; ++i) { L->tmap[i] = off; off = up256(off + L->tmax * sizeof(Seg)); }
   L->fin = off; off = up256(off + L->fmax * sizeof(Seg));
+  L->fins = off; off = up256(off + L->fmax * sizeof(Seg));
+  L->fint = off; off = up256(off + L->fmax * sizeof(Seg));
   L->cpy = off; off = up256(off + L->cmax * sizeof(Seg));
   L->keys1 = off; off = up256(off + n * (size_t)key_bytes);
   L->idx0 = L->idx1 = 0;
@@ -208,6 +224,8 @@ int launch_all(KT *keys, uint64_t n, const int64_t *offsets, uint64_t B, int mod
   Seg *tmap[2] = {reinterpret_cast<Seg *>(scr + L.tmap[0]),
                   reinterpret_cast<Seg *>(scr + L.tmap[1])};
   Seg *fin = reinterpret_cast<Seg *>(scr + L.fin);
+  Seg *fins = reinterpret_cast<Seg *>(scr + L.fins);
+  Seg *fint = reinterpret_cast<Seg *>(scr + L.fint);
   Seg *cpy = reinterpret_cast<Seg *>(scr + L.cpy);
   KT *kbuf[2] = {keys, reinterpret_cast<KT *>(scr + L.keys1)};
   uint32_t *ibuf[2] = {nullptr, nullptr};
@@ -231,9 +249,13 @@ int launch_all(KT *keys, uint64_t n, const int64_t *offsets, uint64_t B, int mod
   ListArgs la;
   la.hdr = hdr;
   la.fin = fin;
+  la.fin_small = fins;
+  la.fin_tiny = fint;
   la.cpy = cpy;
   la.tile = LS::TILE;
   la.t_fin = FS::TFIN;
+  la.t_small = SmallFinish<KT>::T;
+  la.t_tiny = TinyFinish::T;
   la.recount = (uint32_t)(2 * L.tmax);
 
   SeedArgs sa;
@@ -354,10 +376,28 @@ int launch_all(KT *keys, uint64_t n, const int64_t *offsets, uint64_t B, int mod
   fa.desc = desc;
   fa.idx64 = idx64;
   fa.no_skip = no_skip;
+  fa.count = &hdr->n_finish;
   auto fk = finish_kernel<KT, IDX, FS::FB, FS::FIPT>;
   static const int occ_fin = occupancy(fk, FS::FB);
   const uint32_t fgrid = clamp_grid(L.fmax, (uint64_t)cus * occ_fin / gdiv);
   hipLaunchKernelGGL(fk, dim3(fgrid), dim3(FS::FB), 0, st, fa);
+  // segments of at most SmallFinish::T keys: one wave each
+  using SF = SmallFinish<KT>;
+  FinishArgs<KT> fs = fa;
+  fs.list = fins;
+  fs.count = &hdr->n_finish_small;
+  auto sk = finish_kernel<KT, IDX, SF::B, SF::IPT>;
+  static const int occ_small = occupancy(sk, SF::B);
+  const uint32_t sgrid = clamp_grid(L.fmax, (uint64_t)cus * occ_small / gdiv);
+  hipLaunchKernelGGL(sk, dim3(sgrid), dim3(SF::B), 0, st, fs);
+  // segments of at most 64 keys: one key per lane
+  FinishArgs<KT> ft = fa;
+  ft.list = fint;
+  ft.count = &hdr->n_finish_tiny;
+  auto tk = finish_kernel<KT, IDX, TinyFinish::B, TinyFinish::IPT>;
+  static const int occ_tiny = occupancy(tk, TinyFinish::B);
+  const uint32_t tgrid = clamp_grid(L.fmax, (uint64_t)cus * occ_tiny / gdiv);
+  hipLaunchKernelGGL(tk, dim3(tgrid), dim3(TinyFinish::B), 0, st, ft);
 
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "kernel launch");

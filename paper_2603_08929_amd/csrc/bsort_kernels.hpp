@@ -88,6 +88,8 @@ struct Header {
   uint32_t status;             // kept first: read by bsort_device_status
   uint32_t n_finish;
   uint32_t n_copy;
+  uint32_t n_finish_small;     // entries of the small-segment finish list
+  uint32_t n_finish_tiny;      // ... and of the tiny-segment one
   uint32_t pad_;
   uint64_t finish_keys;        // keys handed to the LDS finish (all levels)
   uint64_t copy_keys;          // keys of retired segments copied back
@@ -301,10 +303,14 @@ struct ListArgs {
   uint64_t *split_next;  // per-slot split of level (lvl+1)
   Seg *rec_next;        // level (lvl+1) segments the count pass must count
   Seg *fin;
+  Seg *fin_small;       // finish entries of at most t_small keys
+  Seg *fin_tiny;        // finish entries of at most t_tiny keys
   Seg *cpy;
   int next_level;
   uint32_t tile;        // keys per level tile
   uint32_t t_fin;       // finish threshold (keys)
+  uint32_t t_small;     // finish entries up to this size take the one-wave finish
+  uint32_t t_tiny;      // ... and up to this size, one key per lane
   uint32_t recount;     // count index base of segments counted by the count pass
 };
 
@@ -331,12 +337,17 @@ __device__ void emit_children(const ListArgs &a, Child (&ch)[2]) {
   // live: slots and tiles packed in one 64-bit counter so that slot order
   // and tile order agree
   uint64_t mine = 0, mrec = 0, klive = 0, kfin = 0, kcpy = 0;
-  uint32_t nfin = 0, ncpy = 0;
+  uint32_t nfin = 0, nfs = 0, nft = 0, ncpy = 0;
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
     if (ch[c].kind == KIND_LIVE) { mine += (1ull << 32) | ch[c].tiles; klive += ch[c].len; }
     if (ch[c].kind == KIND_LIVE && ch[c].cbase == CBASE_OWN) mrec += (1ull << 32) | ch[c].tiles;
-    if (ch[c].kind == KIND_FINISH) { nfin++; kfin += ch[c].len; }
+    if (ch[c].kind == KIND_FINISH) {
+      if (ch[c].len <= a.t_tiny) nft++;
+      else if (ch[c].len <= a.t_small) nfs++;
+      else nfin++;
+      kfin += ch[c].len;
+    }
     if (ch[c].kind == KIND_COPY) { ncpy++; kcpy += ch[c].len; }
   }
   // statistics (keys per list), one atomic per wave and list
@@ -351,26 +362,36 @@ __device__ void emit_children(const ListArgs &a, Child (&ch)[2]) {
   const uint64_t inc_live = wave_incl_scan_u64(mine);
   const uint64_t inc_rec = wave_incl_scan_u64(mrec);
   const uint32_t inc_fin = wave_incl_scan_u32(nfin);
+  const uint32_t inc_fs = wave_incl_scan_u32(nfs);
+  const uint32_t inc_ft = wave_incl_scan_u32(nft);
   const uint32_t inc_cpy = wave_incl_scan_u32(ncpy);
   const uint64_t tot_live = __shfl(inc_live, 63);
   const uint64_t tot_rec = __shfl(inc_rec, 63);
   const uint32_t tot_fin = __shfl(inc_fin, 63);
+  const uint32_t tot_fs = __shfl(inc_fs, 63);
+  const uint32_t tot_ft = __shfl(inc_ft, 63);
   const uint32_t tot_cpy = __shfl(inc_cpy, 63);
   uint64_t b_live = 0, b_rec = 0;
-  uint32_t b_fin = 0, b_cpy = 0;
+  uint32_t b_fin = 0, b_fs = 0, b_ft = 0, b_cpy = 0;
   if (lane == 0) {
     if (tot_live) b_live = atomic_add_u64(&a.hdr->packed[a.next_level], tot_live);
     if (tot_rec) b_rec = atomic_add_u64(&a.hdr->rec_packed[a.next_level], tot_rec);
     if (tot_fin) b_fin = atomic_add_u32(&a.hdr->n_finish, tot_fin);
+    if (tot_fs) b_fs = atomic_add_u32(&a.hdr->n_finish_small, tot_fs);
+    if (tot_ft) b_ft = atomic_add_u32(&a.hdr->n_finish_tiny, tot_ft);
     if (tot_cpy) b_cpy = atomic_add_u32(&a.hdr->n_copy, tot_cpy);
   }
   b_live = __shfl(b_live, 0);
   b_rec = __shfl(b_rec, 0);
   b_fin = __shfl(b_fin, 0);
+  b_fs = __shfl(b_fs, 0);
+  b_ft = __shfl(b_ft, 0);
   b_cpy = __shfl(b_cpy, 0);
   uint64_t pos = b_live + (inc_live - mine);
   uint64_t rpos = b_rec + (inc_rec - mrec);
   uint32_t fpos = b_fin + (inc_fin - nfin);
+  uint32_t fspos = b_fs + (inc_fs - nfs);
+  uint32_t ftpos = b_ft + (inc_ft - nft);
   uint32_t cpos = b_cpy + (inc_cpy - ncpy);
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
@@ -406,7 +427,9 @@ __device__ void emit_children(const ListArgs &a, Child (&ch)[2]) {
         rpos += (1ull << 32) | ch[c].tiles;
       }
     } else if (ch[c].kind == KIND_FINISH) {
-      a.fin[fpos++] = s;
+      if (ch[c].len <= a.t_tiny) a.fin_tiny[ftpos++] = s;
+      else if (ch[c].len <= a.t_small) a.fin_small[fspos++] = s;
+      else a.fin[fpos++] = s;
     } else if (ch[c].kind == KIND_COPY) {
       a.cpy[cpos++] = s;
     }
@@ -1099,6 +1122,7 @@ struct FinishArgs {
   KT *keys_final;
   void *idx_final;
   const Seg *list;
+  const uint32_t *count;  // entries in list (a header counter)
   Header *hdr;
   int w, mode, desc, idx64, no_skip;
 };
@@ -1172,7 +1196,7 @@ void finish_kernel(FinishArgs<KT> a) {
       NARROW ? reinterpret_cast<uint32_t *>(s_code) : s_cnt + CNTW + SEGW + 4 * WAVES;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const uint32_t nf = a.hdr->n_finish;
+  const uint32_t nf = *a.count;
 
   for (uint32_t e = blockIdx.x; e < nf; e += gridDim.x) {
     if (tid == 0) s_seg = a.list[e];

@@ -140,3 +140,23 @@ def test_bad_offsets_reported_and_nothing_sorted():
         assert _lib.bsort_device_status(scratch.data_ptr(), stream()) & 2
         np.testing.assert_array_equal(keys.cpu().numpy().view(np.uint32), bits)
         assert (ind.cpu().numpy() == -7).all()
+
+
+@pytest.mark.parametrize("name", ["f32", "u8", "i16", "f64"])
+def test_many_small_segments(name):
+    """20 000 segments of 0..600 keys: most take the one-wave finish (at most
+    512 keys, 256 for 8-byte keys), the rest the full one."""
+    rng = np.random.default_rng(160)
+    lengths = rng.integers(0, 601, size=20000)
+    lengths[rng.random(lengths.size) < 0.6] %= 40
+    n = int(lengths.sum())
+    bits = W.mixed_bits(name, n, 161)
+    for asc in (True, False):
+        keys, idx, offs = gpu_segmented(name, bits, lengths, asc=asc)
+        for s in range(lengths.size):
+            a, b = offs[s], offs[s + 1]
+            if b - a == 0:
+                continue
+            rk, ri = oracle_sort(name, bits[a:b], asc=asc)
+            np.testing.assert_array_equal(keys[a:b], rk, err_msg=f"segment {s} len {b - a}")
+            np.testing.assert_array_equal(idx[a:b], ri, err_msg=f"segment {s} len {b - a}")
