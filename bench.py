@@ -507,6 +507,37 @@ def extras_wide(lib, torch, np, dev, stream):
     return out
 
 
+def extras_small_segments(lib, torch, np, dev, stream):
+    """Segmented sorts of many equal small segments (f32 N(0,1), u32
+    indices), checked against torch's stable sort of the rows."""
+    log("many small segments")
+    out = []
+    for segs, seglen in ((1 << 20, 32), (1 << 18, 128), (1 << 16, 512), (1 << 13, 8192)):
+        n = segs * seglen
+        g = torch.Generator(device=dev).manual_seed(0)
+        src = torch.randn(n, generator=g, device=dev)
+        offs = torch.arange(0, n + 1, seglen, dtype=torch.int64, device=dev)
+        k = torch.empty_like(src)
+        idx = torch.empty(n, dtype=torch.int32, device=dev)
+        need = lib.bsort_scratch_bytes(4, n, segs, 1, 0)
+        scr = torch.empty(need, dtype=torch.uint8, device=dev)
+        ts = []
+        for _ in range(4):
+            k.copy_(src)
+            torch.cuda.synchronize()
+            ts.append(timed(lambda: lib.check(lib.bsort_segmented(
+                k.data_ptr(), lib.KEY_F, 4, offs.data_ptr(), segs, n, 0, idx.data_ptr(),
+                scr.data_ptr(), need, stream), "segmented"), 1, torch))
+        t = sorted(ts[1:])[1]
+        ref = torch.sort(src.view(segs, seglen), dim=1, stable=True)
+        ok = bool(torch.equal(ref.values.view(-1), k)
+                  and torch.equal(ref.indices.view(-1).to(torch.int32), idx))
+        out.append({"segments": segs, "keys_per_segment": seglen, "ms": round(t, 3),
+                    "gkeys_s": round(n / t / 1e6, 2), "equal_torch_stable_sort": ok})
+        del src, offs, k, idx, scr, ref
+    return out
+
+
 def extras_backward(lib, torch, np, dev, stream):
     from paper_2603_08929_amd.autograd import sort_along
     out = []
@@ -673,7 +704,8 @@ def main() -> int:
                   "small_u32_64k": extras_small(_lib, torch, np, dev, stream),
                   "differentiable_sort": extras_backward(_lib, torch, np, dev, stream),
                   "argsort_and_pairs": extras_pairs(_lib, torch, np, dev, stream),
-                  "keys_128_bit": extras_wide(_lib, torch, np, dev, stream)}
+                  "keys_128_bit": extras_wide(_lib, torch, np, dev, stream),
+                  "small_segments": extras_small_segments(_lib, torch, np, dev, stream)}
 
     cpu = None
     if not args.no_cpu_baseline:
