@@ -141,8 +141,8 @@ size_t up256(size_t x) { return (x + 255) & ~(size_t)255; }
 // every parent yields at most two finish entries per level; copy entries
 // hold more than T keys each.
 struct Layout {
-  size_t hdr, cnts, segs[2], recs[2], acc[2], split[2], tmap[2], fin, fins, fint, cpy, keys1,
-      idx0, idx1, keys0, total;
+  size_t hdr, cnts, segs[2], recs[2], acc[2], split[2], tmap[2], fin, fins, fint, finm, cpy,
+      keys1, idx0, idx1, keys0, total;
   uint64_t smax, tmax, fmax, cmax;
 };
 
@@ -170,6 +170,7 @@ bool make_layout(int key_bytes, uint64_t n, uint64_t B, bool with_idx, uint32_t 
   L->fin = off; off = up256(off + L->fmax * sizeof(Seg));
   L->fins = off; off = up256(off + L->fmax * sizeof(Seg));
   L->fint = off; off = up256(off + L->fmax * sizeof(Seg));
+  L->finm = off; off = up256(off + L->fmax * sizeof(Seg));
   L->cpy = off; off = up256(off + L->cmax * sizeof(Seg));
   L->keys1 = off; off = up256(off + n * (size_t)key_bytes);
   L->idx0 = L->idx1 = 0;
@@ -226,6 +227,7 @@ int launch_all(KT *keys, uint64_t n, const int64_t *offsets, uint64_t B, int mod
   Seg *fin = reinterpret_cast<Seg *>(scr + L.fin);
   Seg *fins = reinterpret_cast<Seg *>(scr + L.fins);
   Seg *fint = reinterpret_cast<Seg *>(scr + L.fint);
+  Seg *finm = reinterpret_cast<Seg *>(scr + L.finm);
   Seg *cpy = reinterpret_cast<Seg *>(scr + L.cpy);
   KT *kbuf[2] = {keys, reinterpret_cast<KT *>(scr + L.keys1)};
   uint32_t *ibuf[2] = {nullptr, nullptr};
@@ -251,11 +253,13 @@ int launch_all(KT *keys, uint64_t n, const int64_t *offsets, uint64_t B, int mod
   la.fin = fin;
   la.fin_small = fins;
   la.fin_tiny = fint;
+  la.fin_med = finm;
   la.cpy = cpy;
   la.tile = LS::TILE;
   la.t_fin = FS::TFIN;
   la.t_small = SmallFinish<KT>::T;
   la.t_tiny = TinyFinish::T;
+  la.t_med = FS::TFIN / 2;
   la.recount = (uint32_t)(2 * L.tmax);
 
   SeedArgs sa;
@@ -390,6 +394,14 @@ int launch_all(KT *keys, uint64_t n, const int64_t *offsets, uint64_t B, int mod
   static const int occ_small = occupancy(sk, SF::B);
   const uint32_t sgrid = clamp_grid(L.fmax, (uint64_t)cus * occ_small / gdiv);
   hipLaunchKernelGGL(sk, dim3(sgrid), dim3(SF::B), 0, st, fs);
+  // segments of at most half the full shape: half the keys per lane
+  FinishArgs<KT> fm = fa;
+  fm.list = finm;
+  fm.count = &hdr->n_finish_med;
+  auto mk = finish_kernel<KT, IDX, FS::FB, FS::FIPT / 2>;
+  static const int occ_med = occupancy(mk, FS::FB);
+  const uint32_t mgrid = clamp_grid(L.fmax, (uint64_t)cus * occ_med / gdiv);
+  hipLaunchKernelGGL(mk, dim3(mgrid), dim3(FS::FB), 0, st, fm);
   // segments of at most 64 keys: one key per lane
   FinishArgs<KT> ft = fa;
   ft.list = fint;

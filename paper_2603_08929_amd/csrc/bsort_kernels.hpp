@@ -90,7 +90,7 @@ struct Header {
   uint32_t n_copy;
   uint32_t n_finish_small;     // entries of the small-segment finish list
   uint32_t n_finish_tiny;      // ... and of the tiny-segment one
-  uint32_t pad_;
+  uint32_t n_finish_med;       // ... and of the medium-segment one
   uint64_t finish_keys;        // keys handed to the LDS finish (all levels)
   uint64_t copy_keys;          // keys of retired segments copied back
   uint64_t packed[MAX_LEVELS]; // per level: (live segments << 32) | tiles
@@ -305,12 +305,14 @@ struct ListArgs {
   Seg *fin;
   Seg *fin_small;       // finish entries of at most t_small keys
   Seg *fin_tiny;        // finish entries of at most t_tiny keys
+  Seg *fin_med;         // finish entries of at most t_med keys
   Seg *cpy;
   int next_level;
   uint32_t tile;        // keys per level tile
   uint32_t t_fin;       // finish threshold (keys)
   uint32_t t_small;     // finish entries up to this size take the one-wave finish
   uint32_t t_tiny;      // ... and up to this size, one key per lane
+  uint32_t t_med;       // ... and up to this size, half the full finish shape
   uint32_t recount;     // count index base of segments counted by the count pass
 };
 
@@ -337,7 +339,7 @@ __device__ void emit_children(const ListArgs &a, Child (&ch)[2]) {
   // live: slots and tiles packed in one 64-bit counter so that slot order
   // and tile order agree
   uint64_t mine = 0, mrec = 0, klive = 0, kfin = 0, kcpy = 0;
-  uint32_t nfin = 0, nfs = 0, nft = 0, ncpy = 0;
+  uint32_t nfin = 0, nfs = 0, nft = 0, nfm = 0, ncpy = 0;
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
     if (ch[c].kind == KIND_LIVE) { mine += (1ull << 32) | ch[c].tiles; klive += ch[c].len; }
@@ -345,6 +347,7 @@ __device__ void emit_children(const ListArgs &a, Child (&ch)[2]) {
     if (ch[c].kind == KIND_FINISH) {
       if (ch[c].len <= a.t_tiny) nft++;
       else if (ch[c].len <= a.t_small) nfs++;
+      else if (ch[c].len <= a.t_med) nfm++;
       else nfin++;
       kfin += ch[c].len;
     }
@@ -364,21 +367,24 @@ __device__ void emit_children(const ListArgs &a, Child (&ch)[2]) {
   const uint32_t inc_fin = wave_incl_scan_u32(nfin);
   const uint32_t inc_fs = wave_incl_scan_u32(nfs);
   const uint32_t inc_ft = wave_incl_scan_u32(nft);
+  const uint32_t inc_fm = wave_incl_scan_u32(nfm);
   const uint32_t inc_cpy = wave_incl_scan_u32(ncpy);
   const uint64_t tot_live = __shfl(inc_live, 63);
   const uint64_t tot_rec = __shfl(inc_rec, 63);
   const uint32_t tot_fin = __shfl(inc_fin, 63);
   const uint32_t tot_fs = __shfl(inc_fs, 63);
   const uint32_t tot_ft = __shfl(inc_ft, 63);
+  const uint32_t tot_fm = __shfl(inc_fm, 63);
   const uint32_t tot_cpy = __shfl(inc_cpy, 63);
   uint64_t b_live = 0, b_rec = 0;
-  uint32_t b_fin = 0, b_fs = 0, b_ft = 0, b_cpy = 0;
+  uint32_t b_fin = 0, b_fs = 0, b_ft = 0, b_fm = 0, b_cpy = 0;
   if (lane == 0) {
     if (tot_live) b_live = atomic_add_u64(&a.hdr->packed[a.next_level], tot_live);
     if (tot_rec) b_rec = atomic_add_u64(&a.hdr->rec_packed[a.next_level], tot_rec);
     if (tot_fin) b_fin = atomic_add_u32(&a.hdr->n_finish, tot_fin);
     if (tot_fs) b_fs = atomic_add_u32(&a.hdr->n_finish_small, tot_fs);
     if (tot_ft) b_ft = atomic_add_u32(&a.hdr->n_finish_tiny, tot_ft);
+    if (tot_fm) b_fm = atomic_add_u32(&a.hdr->n_finish_med, tot_fm);
     if (tot_cpy) b_cpy = atomic_add_u32(&a.hdr->n_copy, tot_cpy);
   }
   b_live = __shfl(b_live, 0);
@@ -386,12 +392,14 @@ __device__ void emit_children(const ListArgs &a, Child (&ch)[2]) {
   b_fin = __shfl(b_fin, 0);
   b_fs = __shfl(b_fs, 0);
   b_ft = __shfl(b_ft, 0);
+  b_fm = __shfl(b_fm, 0);
   b_cpy = __shfl(b_cpy, 0);
   uint64_t pos = b_live + (inc_live - mine);
   uint64_t rpos = b_rec + (inc_rec - mrec);
   uint32_t fpos = b_fin + (inc_fin - nfin);
   uint32_t fspos = b_fs + (inc_fs - nfs);
   uint32_t ftpos = b_ft + (inc_ft - nft);
+  uint32_t fmpos = b_fm + (inc_fm - nfm);
   uint32_t cpos = b_cpy + (inc_cpy - ncpy);
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
@@ -429,6 +437,7 @@ __device__ void emit_children(const ListArgs &a, Child (&ch)[2]) {
     } else if (ch[c].kind == KIND_FINISH) {
       if (ch[c].len <= a.t_tiny) a.fin_tiny[ftpos++] = s;
       else if (ch[c].len <= a.t_small) a.fin_small[fspos++] = s;
+      else if (ch[c].len <= a.t_med) a.fin_med[fmpos++] = s;
       else a.fin[fpos++] = s;
     } else if (ch[c].kind == KIND_COPY) {
       a.cpy[cpos++] = s;
