@@ -208,13 +208,14 @@ def timed(fn, reps, torch):
 def extras_word_size(lib, torch, np, dev, stream):
     from paper_2603_08929_amd import workloads as W
     entry = {"u8": lib.bsort_u8, "i8": lib.bsort_i8, "i16": lib.bsort_i16, "f16": lib.bsort_f16,
-             "bf16": lib.bsort_f16, "u64": lib.bsort_u64, "i64": lib.bsort_i64,
-             "f64": lib.bsort_f64}
-    sint = {1: np.int8, 2: np.int16, 8: np.int64}
+             "bf16": lib.bsort_f16, "i32": lib.bsort_i32, "f32": lib.bsort_f32,
+             "u64": lib.bsort_u64, "i64": lib.bsort_i64, "f64": lib.bsort_f64}
+    sint = {1: np.int8, 2: np.int16, 4: np.int32, 8: np.int64}
     N28, N27 = 1 << 28, 1 << 27
     cases = [("u8", N28, "uniform"), ("i8", N28, "uniform"), ("i16", N28, "uniform"),
-             ("f16", N28, "normal"), ("bf16", N28, "normal"), ("u64", N27, "uniform"),
-             ("i64", N27, "uniform"), ("f64", N27, "normal")]
+             ("f16", N28, "normal"), ("bf16", N28, "normal"), ("i32", N27, "uniform"),
+             ("f32", N27, "normal"), ("u64", N27, "uniform"), ("i64", N27, "uniform"),
+             ("f64", N27, "normal")]
     out = []
     for name, n, dist in cases:
         log(f"word-size sweep {name} n={n}")
