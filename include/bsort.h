@@ -148,7 +148,10 @@ int bsort_sort(void *keys, int key_type, int key_bytes, uint64_t n, uint32_t fla
  * elem_bytes 2 (fp16 / bf16, moved bit for bit), 4 (f32) or 8 (f64);
  * indices uint32, or int64 with BSORT_IDX64 in flags.  idx must hold a
  * permutation of 0..cols-1 in every row (as a sort returns it); entries
- * outside [0, cols) are skipped.  No arithmetic is done on the values.
+ * outside [0, cols) are skipped: their output positions keep the caller's
+ * bits.  No arithmetic is done on the values.  Rows of up to 8 x 128 KB are
+ * staged in LDS (coalesced writes); wider rows are scattered directly.
+ * Allocates nothing and does not synchronise.
  */
 int bsort_backward_scatter(const void *grad_sorted, const void *indices, uint64_t rows,
                            uint64_t cols, int elem_bytes, void *grad_in, uint32_t flags,

@@ -721,6 +721,53 @@ int sort128(void *keys, int key_type, uint64_t n, uint32_t flags, void *indices,
   return BSORT_OK;
 }
 
+constexpr uint64_t BWD_MAX_SLICES = 8;
+constexpr uint32_t BWD_BLOCK = 1024;
+
+int launch_status() {
+  const hipError_t e = hipGetLastError();
+  return e != hipSuccess ? hip_fail(e, "kernel launch") : BSORT_OK;
+}
+
+template <typename ET, uint32_t SB>
+void launch_staged(const void *g, const void *idx, uint64_t rows, uint64_t cols, uint64_t m,
+                   uint64_t slices, uint64_t units, uint64_t grid, void *out, bool i64,
+                   hipStream_t st) {
+  const float rcp = 1.0f / (float)cols;
+  if (i64)
+    hipLaunchKernelGGL((backward_staged_kernel<ET, true, SB, BWD_BLOCK>), dim3((uint32_t)grid),
+                       dim3(BWD_BLOCK), 0, st, static_cast<const ET *>(g), idx, rows, cols, m,
+                       slices, units, rcp, static_cast<ET *>(out));
+  else
+    hipLaunchKernelGGL((backward_staged_kernel<ET, false, SB, BWD_BLOCK>), dim3((uint32_t)grid),
+                       dim3(BWD_BLOCK), 0, st, static_cast<const ET *>(g), idx, rows, cols, m,
+                       slices, units, rcp, static_cast<ET *>(out));
+}
+
+// Launches the LDS-staged scatter when the shape suits it; false otherwise.
+template <typename ET>
+bool backward_staged(const void *g, const void *idx, uint64_t rows, uint64_t cols, void *out,
+                     bool i64, hipStream_t st) {
+  constexpr uint64_t S64 = 65536 / sizeof(ET), S128 = 131072 / sizeof(ET);
+  constexpr uint64_t MAX_GRID = 0xFFFFFFFFull / BWD_BLOCK;
+  if (cols <= S64) {
+    const uint64_t m = S64 / cols, units = (rows + m - 1) / m;
+    if (units > MAX_GRID) return false;
+    launch_staged<ET, 65536>(g, idx, rows, cols, m, 0, units, units, out, i64, st);
+    return true;
+  }
+  const uint64_t slices = (cols + S128 - 1) / S128;
+  if (slices > BWD_MAX_SLICES || rows > MAX_GRID / slices) return false;
+  const uint64_t units = rows * slices;
+  const uint64_t grid = slices > 1 ? 8 * ((units + 7) / 8) : units;
+  if (grid > MAX_GRID) return false;
+  if (slices == 1)  // one whole row per block
+    launch_staged<ET, 131072>(g, idx, rows, cols, 1, 0, units, grid, out, i64, st);
+  else
+    launch_staged<ET, 131072>(g, idx, rows, cols, 1, slices, units, grid, out, i64, st);
+  return true;
+}
+
 }  // namespace
 
 extern "C" {
@@ -796,6 +843,18 @@ int bsort_backward_scatter(const void *grad_sorted, const void *indices, uint64_
   if (rc != BSORT_OK) return rc;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const bool i64 = (flags & BSORT_IDX64) != 0;
+  // Rows of at most 64 KB: runs of whole rows staged in 64 KB of LDS (two
+  // blocks per CU).  Up to BWD_MAX_SLICES slices of 128 KB: one slice per
+  // block.  Wider rows: the direct kernel (each extra slice re-reads the row).
+  if (elem_bytes == 2) {
+    if (backward_staged<uint16_t>(grad_sorted, indices, rows, cols, grad_in, i64, st))
+      return launch_status();
+  } else if (elem_bytes == 4) {
+    if (backward_staged<uint32_t>(grad_sorted, indices, rows, cols, grad_in, i64, st))
+      return launch_status();
+  } else if (backward_staged<uint64_t>(grad_sorted, indices, rows, cols, grad_in, i64, st)) {
+    return launch_status();
+  }
   const uint64_t bx = (cols + 255) / 256;
   dim3 grid(clamp_grid(bx, 4096), clamp_grid(rows, 65535));
 #define BS_LAUNCH(ET)                                                                       \

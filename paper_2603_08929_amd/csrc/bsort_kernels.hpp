@@ -1498,6 +1498,98 @@ __global__ void backward_scatter_kernel(const ET *g, const void *idx, uint64_t r
   }
 }
 
+// The same scatter staged through LDS.  A block owns a run of output
+// positions that fits in LDS (S = SB / sizeof(ET) elements): m whole rows
+// when a row fits (m = S / cols, "packed"), else one slice [s0, s0 + S) of
+// one row.  It reads the indices and gradients that can land there in order
+// (coalesced loads: its own m rows, or the slice's whole row), drops each
+// value whose destination falls in its run into LDS and sets the
+// destination's bit in an LDS bitmap, then writes the run out in order, only
+// at marked positions: entries outside [0, cols) leave their output
+// untouched, as in the direct kernel.  The random writes thus go to LDS and
+// HBM sees whole lines.  A row of P > 1 slices is read P times; the blocks
+// of one row's slices are then given consecutive dispatch slots of one XCD
+// (blocks are dealt to the 8 XCDs round-robin; the grid is 8 ceil(units/8)),
+// so they run together and the re-reads hit that XCD's L2.
+//
+// Work item w (0 <= w < units): packed (slices == 0), rows [w m, w m + m)
+// clipped to rows; sliced, row w / slices, slice w % slices.  rcp_cols =
+// 1 / cols in fp32, used to find the row of a packed position (exact after
+// one correction, positions being below 2^17).
+template <typename ET, bool I64, uint32_t SB, uint32_t BLOCK>
+__global__ __launch_bounds__(BLOCK) void backward_staged_kernel(const ET *g, const void *idx,
+                                                                uint64_t rows, uint64_t cols,
+                                                                uint64_t m, uint64_t slices,
+                                                                uint64_t units, float rcp_cols,
+                                                                ET *out) {
+  constexpr uint32_t S = SB / sizeof(ET);
+  constexpr uint32_t U = 4;
+  static_assert(S <= (1u << 17), "packed positions must stay below 2^17");
+  __shared__ ET s_val[S];
+  __shared__ uint32_t s_mark[S / 32];
+  const uint32_t t = threadIdx.x;
+  const uint64_t w = slices > 1 ? (blockIdx.x & 7) * ((units + 7) / 8) + (blockIdx.x >> 3)
+                                 : (uint64_t)blockIdx.x;
+  if (w >= units) return;
+  const bool packed = slices == 0;
+  uint64_t q0, in0, nin, s0 = 0;
+  uint32_t len;
+  if (packed) {
+    const uint64_t r0 = w * m;
+    const uint64_t mr = rows - r0 < m ? rows - r0 : m;
+    q0 = in0 = r0 * cols;
+    nin = mr * cols;
+    len = (uint32_t)nin;
+  } else {
+    const uint64_t r = w / slices;
+    s0 = (w - r * slices) * S;
+    in0 = r * cols;
+    q0 = in0 + s0;
+    nin = cols;
+    len = (uint32_t)(cols - s0 < S ? cols - s0 : S);
+  }
+  const uint32_t c32 = (uint32_t)cols;
+  for (uint32_t i = t; i < (len + 31) / 32; i += BLOCK) s_mark[i] = 0;
+  __syncthreads();
+  const ET *gr = g + in0;
+  auto dest = [&](uint64_t l) -> uint64_t {
+    return I64 ? (uint64_t) static_cast<const int64_t *>(idx)[in0 + l]
+               : (uint64_t) static_cast<const uint32_t *>(idx)[in0 + l];
+  };
+  // LDS position of input l with row-local destination d (>= len: none)
+  auto target = [&](uint64_t l, uint64_t d) -> uint64_t {
+    if (!packed) return d - s0;  // wraps above len when d < s0
+    const uint32_t l32 = (uint32_t)l;
+    uint32_t rr = (uint32_t)((float)l32 * rcp_cols);
+    if (rr * c32 > l32) --rr;
+    else if ((rr + 1) * c32 <= l32) ++rr;
+    return d < cols ? (uint64_t)rr * cols + d : ~(uint64_t)0;
+  };
+  auto place = [&](uint64_t o, ET v) {
+    if (o < len) {
+      s_val[o] = v;
+      atomicOr(&s_mark[o >> 5], 1u << (o & 31));
+    }
+  };
+  uint64_t l = t;
+  for (; l + (U - 1) * BLOCK < nin; l += U * BLOCK) {
+    uint64_t d[U];
+    ET v[U];
+#pragma unroll
+    for (uint32_t k = 0; k < U; ++k) {
+      d[k] = dest(l + k * BLOCK);
+      v[k] = gr[l + k * BLOCK];
+    }
+#pragma unroll
+    for (uint32_t k = 0; k < U; ++k) place(target(l + k * BLOCK, d[k]), v[k]);
+  }
+  for (; l < nin; l += BLOCK) place(target(l, dest(l)), gr[l]);
+  __syncthreads();
+  ET *o = out + q0;
+  for (uint32_t i = t; i < len; i += BLOCK)
+    if ((s_mark[i >> 5] >> (i & 31)) & 1u) o[i] = s_val[i];
+}
+
 // ---------------------------------------------------------- payload gather
 
 // Segment of position x: the last s < B with offsets[s] <= x, searched in

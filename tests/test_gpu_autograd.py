@@ -5,8 +5,9 @@ import numpy as np
 import pytest
 import torch
 
-from paper_2603_08929_amd import api
+from paper_2603_08929_amd import _lib, api
 from paper_2603_08929_amd.autograd import BSortFunction, sort_along
+from gpu_util import stream
 
 pytestmark = pytest.mark.gpu
 
@@ -92,6 +93,45 @@ def test_backward_scatter_kernel_direct(dtype):
     out32 = api.backward_scatter(gs.cuda(), idx.to(torch.int32).cuda())
     assert torch.equal(out64.cpu(), ref)
     assert torch.equal(out32.cpu(), ref)
+
+
+# (rows, cols, element bytes): whole rows packed into one LDS run (tiny,
+# odd and just-fitting rows), one row per 128 KB run, rows cut into 2..8
+# slices with ragged last slices, and rows too wide for the staged kernel
+# (the direct kernel).
+SCATTER_SHAPES = [(5000, 64, 4), (333, 7, 2), (9, 1, 8), (3, 16384, 4), (5, 32768, 2),
+                  (4, 65536, 4), (3, 16385, 8), (2, 98309, 4), (3, 131072 * 2 - 1, 4),
+                  (2, 524288, 2), (2, 600001, 2), (1, 1 << 17, 8), (6, 20000, 4), (3, 65536, 2)]
+
+
+@pytest.mark.parametrize("rows,cols,eb", SCATTER_SHAPES)
+def test_backward_scatter_shapes_and_skips(rows, cols, eb):
+    """Every staging shape against numpy's scatter: random permutations per
+    row with some entries replaced by indices outside [0, cols) (negative
+    ones for int64), whose output positions must keep the caller's bits."""
+    rng = np.random.default_rng(rows * 7 + cols + eb)
+    idx = np.stack([rng.permutation(cols) for _ in range(rows)]).astype(np.int64)
+    bad = rng.random(idx.shape) < 0.01
+    bad.flat[0] = True
+    vdt = {2: np.uint16, 4: np.uint32, 8: np.uint64}[eb]
+    sdt = {2: np.int16, 4: np.int32, 8: np.int64}[eb]  # same bits, a torch dtype
+    g = rng.integers(0, 1 << (8 * eb - 1), size=idx.shape, dtype=np.uint64).astype(vdt)
+    fill = vdt(0x5A5A5A5A5A5A5A5A & ((1 << (8 * eb)) - 1))
+    gd = torch.from_numpy(g.view(sdt)).cuda()
+    for i64 in (False, True):
+        ix = idx.copy()
+        ix[bad] = np.where(rng.random(int(bad.sum())) < 0.5, cols, -1 if i64 else cols + 9)
+        ok = (ix >= 0) & (ix < cols)
+        want = np.full(idx.shape, fill, dtype=vdt)
+        want[np.nonzero(ok)[0], ix[ok]] = g[ok]
+        out = torch.from_numpy(np.full(idx.shape, fill, dtype=vdt).view(sdt)).cuda()
+        ind = torch.from_numpy(ix if i64 else ix.astype(np.uint32).view(np.int32)).cuda()
+        rc = _lib.bsort_backward_scatter(gd.data_ptr(), ind.data_ptr(), rows, cols, eb,
+                                         out.data_ptr(), _lib.IDX64 if i64 else 0, stream())
+        _lib.check(rc, "bsort_backward_scatter")
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(out.cpu().numpy().view(vdt), want,
+                                      err_msg=f"{rows}x{cols} eb={eb} i64={i64}")
 
 
 def test_edge_shapes():
