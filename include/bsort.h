@@ -157,6 +157,29 @@ int bsort_backward_scatter(const void *grad_sorted, const void *indices, uint64_
                            uint64_t cols, int elem_bytes, void *grad_in, uint32_t flags,
                            void *stream);
 
+/* ---- in-place sort with small scratch ----
+ *
+ * Keys only.  Every level partitions each live segment in place by
+ * exchanging misplaced keys in pairs, as Algorithm 1's swap loop does
+ * (Section II; Theorem 5 bounds that loop's auxiliary space), instead of
+ * scattering stably into a second buffer.  The scratch then holds only
+ * per-level lists and per-tile counts: bsort_inplace_scratch_bytes(...)
+ * is O(n / 2048 + num_segments) words, a few percent of the keys.  Equal
+ * keys are indistinguishable, so the sorted keys equal those of
+ * bsort_sort; no permutation is produced (the exchange is not stable).
+ * Each level reads the live keys about three times, so this is slower than
+ * bsort_sort.  key_type, key_bytes, offsets and validation as for
+ * bsort_sort / bsort_segmented; flags: BSORT_DESCENDING, BSORT_NO_SKIP,
+ * BSORT_NO_FINISH (others give BSORT_EINVAL).  Scratch 256-byte aligned.
+ */
+size_t bsort_inplace_scratch_bytes(int key_bytes, uint64_t n, uint64_t num_segments,
+                                   uint32_t flags);
+int bsort_sort_inplace(void *keys, int key_type, int key_bytes, uint64_t n, uint32_t flags,
+                       void *scratch, size_t scratch_bytes, void *stream);
+int bsort_segmented_inplace(void *keys, int key_type, int key_bytes, const int64_t *offsets,
+                            uint64_t num_segments, uint64_t n, uint32_t flags, void *scratch,
+                            size_t scratch_bytes, void *stream);
+
 /* ---- values that travel with the keys ----
  *
  * A key-value sort permutes a payload exactly as the keys: after the sort,

@@ -38,7 +38,8 @@ SYMBOLS = ["bsort_scratch_bytes", "bsort_sort", "bsort_segmented", "bsort_segmen
            "bsort_autotune", "bsort_autotune_reset", "bsort_graph_create",
            "bsort_graph_launch", "bsort_graph_destroy", "bsort_pairs_scratch_bytes",
            "bsort_sort_pairs", "bsort_segmented_pairs", "bsort_gather",
-           "bsort_scratch_bytes128", "bsort_sort128", "bsort_sort_layout"] + \
+           "bsort_scratch_bytes128", "bsort_sort128", "bsort_sort_layout",
+           "bsort_inplace_scratch_bytes", "bsort_sort_inplace", "bsort_segmented_inplace"] + \
     [f"bsort_{t}" for t in TYPED]
 
 lib.bsort_scratch_bytes.argtypes = [_i, _u64, _u64, _i, _u32]
@@ -73,6 +74,12 @@ lib.bsort_sort128.restype = _i
 lib.bsort_sort_layout.argtypes = [_vp, _i, _i, _u64, _u32, ctypes.POINTER(ctypes.c_uint8), _vp,
                                   _vp, _sz, _vp]
 lib.bsort_sort_layout.restype = _i
+lib.bsort_inplace_scratch_bytes.argtypes = [_i, _u64, _u64, _u32]
+lib.bsort_inplace_scratch_bytes.restype = _sz
+lib.bsort_sort_inplace.argtypes = [_vp, _i, _i, _u64, _u32, _vp, _sz, _vp]
+lib.bsort_sort_inplace.restype = _i
+lib.bsort_segmented_inplace.argtypes = [_vp, _i, _i, _vp, _u64, _u64, _u32, _vp, _sz, _vp]
+lib.bsort_segmented_inplace.restype = _i
 lib.bsort_strerror.argtypes = [_i]
 lib.bsort_strerror.restype = ctypes.c_char_p
 lib.bsort_device_status.argtypes = [_vp, _vp]
@@ -144,5 +151,8 @@ bsort_gather = lib.bsort_gather
 bsort_scratch_bytes128 = lib.bsort_scratch_bytes128
 bsort_sort128 = lib.bsort_sort128
 bsort_sort_layout = lib.bsort_sort_layout
+bsort_inplace_scratch_bytes = lib.bsort_inplace_scratch_bytes
+bsort_sort_inplace = lib.bsort_sort_inplace
+bsort_segmented_inplace = lib.bsort_segmented_inplace
 for _t in TYPED:
     globals()[f"bsort_{_t}"] = getattr(lib, f"bsort_{_t}")

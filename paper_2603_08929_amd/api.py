@@ -263,6 +263,27 @@ def sort_layout_(keys: torch.Tensor, bit_order, family: Optional[str] = None,
     return idx
 
 
+def sort_inplace_(keys: torch.Tensor, offsets: Optional[torch.Tensor] = None,
+                  descending: bool = False, flags: int = 0) -> None:
+    """Sorts a contiguous 1-D GPU tensor (or each segment of it) in place
+    with the small-scratch in-place variant: keys only, the same sorted keys
+    as sort_, no permutation."""
+    kt, kb = key_type(keys.dtype)
+    B, offp = _segment_args(keys, offsets)
+    n = keys.numel()
+    fl = _flags(descending, flags, False)
+    need = _lib.bsort_inplace_scratch_bytes(kb, n, B, fl)
+    scratch = torch.empty(max(need, 256), dtype=torch.uint8, device=keys.device)
+    if offsets is None:
+        rc = _lib.bsort_sort_inplace(keys.data_ptr(), kt, kb, n, fl, scratch.data_ptr(),
+                                     scratch.numel(), _stream(keys.device))
+    else:
+        rc = _lib.bsort_segmented_inplace(keys.data_ptr(), kt, kb, offp, B, n, fl,
+                                          scratch.data_ptr(), scratch.numel(),
+                                          _stream(keys.device))
+    _lib.check(rc, "bsort_sort_inplace")
+
+
 def device_status(scratch: torch.Tensor) -> int:
     return int(_lib.bsort_device_status(scratch.data_ptr(), _stream(scratch.device)))
 

@@ -349,6 +349,7 @@ int launch_all(KT *keys, uint64_t n, const int64_t *offsets, uint64_t B, int mod
     pa.idx64 = idx64;
     pa.no_skip = no_skip;
     pa.no_finish = no_finish;
+    pa.inplace = 0;
     hipLaunchKernelGGL(plan_kernel, dim3(pgrid), dim3(256), 0, st, pa);
   }
 
@@ -721,6 +722,257 @@ int sort128(void *keys, int key_type, uint64_t n, uint32_t flags, void *indices,
   return BSORT_OK;
 }
 
+// ---- in-place (keys-only, low-scratch) sort
+//
+// Scratch: the header, per-level lists and per-tile arrays only, O(n / tile
+// + segments).  Bounds as for the main layout, except that the finish lists
+// are consumed after every step that fills them (the seed and each plan),
+// so they hold one step's entries: the seed's (at most B) or two per parent.
+constexpr uint32_t IP_FLAGS = BSORT_DESCENDING | BSORT_NO_SKIP | BSORT_NO_FINISH;
+
+struct InplaceLayout {
+  size_t hdr, cnts, segs[2], recs[2], acc[2], split[2], tmap, pre, loc, fin, fins, fint, finm,
+      cpy, total;
+  uint64_t smax, tmax, fmax;
+};
+
+bool inplace_layout(int key_bytes, uint64_t n, uint64_t B, uint32_t flags, InplaceLayout *L) {
+  if (key_bytes != 1 && key_bytes != 2 && key_bytes != 4 && key_bytes != 8) return false;
+  const uint64_t tile = tile_of(key_bytes, 0), tfin = tfin_of(key_bytes, 0);
+  const bool no_finish = (flags & BSORT_NO_FINISH) != 0;
+  L->smax = (no_finish ? n / 2 : n / (tfin + 1)) + 1;
+  L->tmax = n / tile + L->smax + 1;
+  const uint64_t fb = B + 2 * L->smax + 1;
+  L->fmax = fb < n + 1 ? fb : n + 1;
+  size_t off = 0;
+  L->hdr = off; off = up256(off + sizeof(Header));
+  L->cnts = off; off = up256(off + 4 * (3 * L->tmax) * 4);
+  for (int i = 0; i < 2; ++i) { L->segs[i] = off; off = up256(off + L->smax * sizeof(Seg)); }
+  for (int i = 0; i < 2; ++i) { L->recs[i] = off; off = up256(off + L->smax * sizeof(Seg)); }
+  for (int i = 0; i < 2; ++i) { L->acc[i] = off; off = up256(off + L->tmax * sizeof(AccRep)); }
+  for (int i = 0; i < 2; ++i) { L->split[i] = off; off = up256(off + L->smax * 8); }
+  L->tmap = off; off = up256(off + L->tmax * sizeof(Seg));
+  L->pre = off; off = up256(off + L->tmax * 4);
+  L->loc = off; off = up256(off + L->tmax * 8);
+  L->fin = off; off = up256(off + L->fmax * sizeof(Seg));
+  L->fins = off; off = up256(off + L->fmax * sizeof(Seg));
+  L->fint = off; off = up256(off + L->fmax * sizeof(Seg));
+  L->finm = off; off = up256(off + L->fmax * sizeof(Seg));
+  L->cpy = off; off = up256(off + sizeof(Seg));  // never filled: nothing sits in a second buffer
+  L->total = off;
+  return true;
+}
+
+template <typename KT>
+void launch_finishes(FinishArgs<KT> fa, Header *hdr, Seg *fin, Seg *fins, Seg *fint, Seg *finm,
+                     uint64_t fmax, int cus, hipStream_t st) {
+  using FS = FinishShape<KT, 0>;
+  using SF = SmallFinish<KT>;
+  auto fk = finish_kernel<KT, false, FS::FB, FS::FIPT>;
+  auto mk = finish_kernel<KT, false, FS::FB, FS::FIPT / 2>;
+  auto sk = finish_kernel<KT, false, SF::B, SF::IPT>;
+  auto tk = finish_kernel<KT, false, TinyFinish::B, TinyFinish::IPT>;
+  static const int occ_f = occupancy(fk, FS::FB), occ_m = occupancy(mk, FS::FB);
+  static const int occ_s = occupancy(sk, SF::B), occ_t = occupancy(tk, TinyFinish::B);
+  fa.list = fin;
+  fa.count = &hdr->n_finish;
+  hipLaunchKernelGGL(fk, dim3(clamp_grid(fmax, (uint64_t)cus * occ_f)), dim3(FS::FB), 0, st, fa);
+  fa.list = finm;
+  fa.count = &hdr->n_finish_med;
+  hipLaunchKernelGGL(mk, dim3(clamp_grid(fmax, (uint64_t)cus * occ_m)), dim3(FS::FB), 0, st, fa);
+  fa.list = fins;
+  fa.count = &hdr->n_finish_small;
+  hipLaunchKernelGGL(sk, dim3(clamp_grid(fmax, (uint64_t)cus * occ_s)), dim3(SF::B), 0, st, fa);
+  fa.list = fint;
+  fa.count = &hdr->n_finish_tiny;
+  hipLaunchKernelGGL(tk, dim3(clamp_grid(fmax, (uint64_t)cus * occ_t)), dim3(TinyFinish::B), 0,
+                     st, fa);
+}
+
+template <typename KT>
+int launch_inplace(KT *keys, uint64_t n, const int64_t *offsets, uint64_t B, int mode,
+                   uint32_t flags, char *scr, const InplaceLayout &L, int cus, hipStream_t st) {
+  using LS = LevelShape<KT, 0>;
+  using FS = FinishShape<KT, 0>;
+  const int w = 8 * (int)sizeof(KT);
+  const int desc = (flags & BSORT_DESCENDING) ? 1 : 0;
+  const int no_skip = (flags & BSORT_NO_SKIP) ? 1 : 0;
+  const int no_finish = (flags & BSORT_NO_FINISH) ? 1 : 0;
+  Header *hdr = reinterpret_cast<Header *>(scr + L.hdr);
+  Seg *segs[2] = {reinterpret_cast<Seg *>(scr + L.segs[0]),
+                  reinterpret_cast<Seg *>(scr + L.segs[1])};
+  Seg *recs[2] = {reinterpret_cast<Seg *>(scr + L.recs[0]),
+                  reinterpret_cast<Seg *>(scr + L.recs[1])};
+  AccRep *acc[2] = {reinterpret_cast<AccRep *>(scr + L.acc[0]),
+                    reinterpret_cast<AccRep *>(scr + L.acc[1])};
+  uint64_t *split[2] = {reinterpret_cast<uint64_t *>(scr + L.split[0]),
+                        reinterpret_cast<uint64_t *>(scr + L.split[1])};
+  Seg *fin = reinterpret_cast<Seg *>(scr + L.fin);
+  Seg *fins = reinterpret_cast<Seg *>(scr + L.fins);
+  Seg *fint = reinterpret_cast<Seg *>(scr + L.fint);
+  Seg *finm = reinterpret_cast<Seg *>(scr + L.finm);
+  const uint64_t cap = (uint64_t)cus * 16;
+  uint32_t *cnt_base = reinterpret_cast<uint32_t *>(scr + L.cnts);
+  const uint64_t cn = 3 * L.tmax;
+  uint32_t *tcnt[2] = {cnt_base, cnt_base + 2 * cn};
+  uint32_t *scnt[2] = {cnt_base + cn, cnt_base + 3 * cn};
+  hipLaunchKernelGGL(init_kernel, dim3(clamp_grid((4 * cn + 255) / 256, 2048)), dim3(256), 0,
+                     st, hdr, cnt_base, 4 * cn);
+  if (offsets)
+    hipLaunchKernelGGL(validate_kernel, dim3(clamp_grid((B + 256) / 256, 1024)), dim3(256), 0,
+                       st, offsets, B, n, hdr);
+
+  ListArgs la;
+  la.hdr = hdr;
+  la.fin = fin;
+  la.fin_small = fins;
+  la.fin_tiny = fint;
+  la.fin_med = finm;
+  la.cpy = reinterpret_cast<Seg *>(scr + L.cpy);
+  la.tile = LS::TILE;
+  la.t_fin = FS::TFIN;
+  la.t_small = SmallFinish<KT>::T;
+  la.t_tiny = TinyFinish::T;
+  la.t_med = FS::TFIN / 2;
+  la.recount = (uint32_t)(2 * L.tmax);
+
+  SeedArgs sa;
+  sa.l = la;
+  sa.l.live_next = segs[0];
+  sa.l.acc_next = acc[0];
+  sa.l.split_next = split[0];
+  sa.l.rec_next = recs[0];
+  sa.l.next_level = 0;
+  sa.offsets = offsets;
+  sa.B = B;
+  sa.n = n;
+  sa.w = w;
+  sa.with_idx = 0;
+  sa.no_finish = no_finish;
+  sa.idx_final = nullptr;
+  sa.idx64 = 0;
+  hipLaunchKernelGGL(seed_kernel, dim3(clamp_grid((B + 255) / 256, cap)), dim3(256), 0, st, sa);
+
+  FinishArgs<KT> fa;
+  fa.keys_buf[0] = keys;
+  fa.keys_buf[1] = keys;
+  fa.idx_buf[0] = nullptr;
+  fa.idx_buf[1] = nullptr;
+  fa.keys_final = keys;
+  fa.idx_final = nullptr;
+  fa.hdr = hdr;
+  fa.w = w;
+  fa.mode = mode;
+  fa.desc = desc;
+  fa.idx64 = 0;
+  fa.no_skip = no_skip;
+  launch_finishes<KT>(fa, hdr, fin, fins, fint, finm, L.fmax, cus, st);
+
+  auto ck = ip_count_kernel<KT, LS::LB, LS::LIPT>;
+  auto lk = ip_locate_kernel<KT, LS::LB, LS::LIPT>;
+  auto sk = ip_swap_kernel<KT, LS::LB, LS::LIPT>;
+  static const int occ_c = occupancy(ck, LS::LB), occ_l = occupancy(lk, LS::LB),
+                   occ_s = occupancy(sk, LS::LB);
+  const uint32_t cgrid = clamp_grid(L.tmax, (uint64_t)cus * occ_c);
+  const uint32_t lgrid = clamp_grid(L.tmax, (uint64_t)cus * occ_l);
+  const uint32_t sgrid = clamp_grid(L.tmax, (uint64_t)cus * occ_s);
+  const uint32_t xgrid = clamp_grid((L.tmax + 3) / 4, cap);
+  const uint32_t pgrid = clamp_grid((L.smax + 255) / 256, cap);
+  const int levels = (!offsets && !no_finish && n <= FS::TFIN) ? 0 : w;
+  for (int lvl = 0; lvl < levels; ++lvl) {
+    InplaceArgs<KT> a;
+    a.keys = keys;
+    a.live = segs[lvl & 1];
+    a.tiles = reinterpret_cast<Seg *>(scr + L.tmap);
+    a.hdr = hdr;
+    a.tcnt = tcnt[lvl & 1];
+    a.scnt = scnt[lvl & 1];
+    a.pre = reinterpret_cast<uint32_t *>(scr + L.pre);
+    a.loc = reinterpret_cast<uint64_t *>(scr + L.loc);
+    a.acc = acc[lvl & 1];
+    a.split = split[lvl & 1];
+    a.w = w;
+    a.mode = mode;
+    a.desc = desc;
+    a.level = lvl;
+    hipLaunchKernelGGL(ck, dim3(cgrid), dim3(LS::LB), 0, st, a);
+    hipLaunchKernelGGL((ip_prefix_kernel<KT>), dim3(xgrid), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(lk, dim3(lgrid), dim3(LS::LB), 0, st, a);
+    hipLaunchKernelGGL(sk, dim3(sgrid), dim3(LS::LB), 0, st, a);
+
+    PlanArgs pa;
+    pa.l = la;
+    pa.l.live_next = segs[(lvl + 1) & 1];
+    pa.l.acc_next = acc[(lvl + 1) & 1];
+    pa.l.split_next = split[(lvl + 1) & 1];
+    pa.l.rec_next = recs[(lvl + 1) & 1];
+    pa.l.next_level = lvl + 1;
+    pa.live = segs[lvl & 1];
+    pa.acc = acc[lvl & 1];
+    pa.split = split[lvl & 1];
+    pa.zero_a = tcnt[lvl & 1];  // counted again two levels on
+    pa.zero_b = scnt[lvl & 1];
+    pa.zero_n = cn;
+    pa.level = lvl;
+    pa.w = w;
+    pa.with_idx = 0;
+    pa.idx64 = 0;
+    pa.no_skip = no_skip;
+    pa.no_finish = no_finish;
+    pa.inplace = 1;
+    hipLaunchKernelGGL(plan_kernel, dim3(pgrid), dim3(256), 0, st, pa);
+    launch_finishes<KT>(fa, hdr, fin, fins, fint, finm, L.fmax, cus, st);
+  }
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  return BSORT_OK;
+}
+
+template <typename KT>
+int run_inplace(void *keys, uint64_t n, const int64_t *offsets, uint64_t B, bool segmented,
+                int mode, uint32_t flags, void *scratch, size_t scratch_bytes, void *stream) {
+  if (flags & ~IP_FLAGS) return BSORT_EINVAL;
+  if (segmented && B > 0 && !offsets) return BSORT_EINVAL;
+  if (segmented && B == 0 && n != 0) return BSORT_EINVAL;
+  if (n == 0) return BSORT_OK;
+  if (!keys || !scratch) return BSORT_EINVAL;
+  if (n >= (1ull << 32)) return BSORT_ETOOBIG;
+  const uint64_t b = segmented ? B : 1;
+  InplaceLayout L;
+  if (!inplace_layout((int)sizeof(KT), n, b, flags, &L)) return BSORT_EINVAL;
+  if (scratch_bytes < L.total) return BSORT_ESCRATCH;
+  if (reinterpret_cast<uintptr_t>(scratch) & 255) return BSORT_EINVAL;
+  int cus = 0;
+  const int rc = device_check(&cus);
+  if (rc != BSORT_OK) return rc;
+  return launch_inplace<KT>(static_cast<KT *>(keys), n, segmented ? offsets : nullptr, b, mode,
+                            flags, static_cast<char *>(scratch), L, cus,
+                            static_cast<hipStream_t>(stream));
+}
+
+int dispatch_inplace(void *keys, int key_type, int key_bytes, uint64_t n, const int64_t *offsets,
+                     uint64_t B, bool segmented, uint32_t flags, void *scratch,
+                     size_t scratch_bytes, void *stream) {
+  if (key_type != BSORT_KEY_U && key_type != BSORT_KEY_I && key_type != BSORT_KEY_F)
+    return BSORT_EINVAL;
+  switch (key_bytes) {
+    case 1:
+      return run_inplace<uint8_t>(keys, n, offsets, B, segmented, key_type, flags, scratch,
+                                  scratch_bytes, stream);
+    case 2:
+      return run_inplace<uint16_t>(keys, n, offsets, B, segmented, key_type, flags, scratch,
+                                   scratch_bytes, stream);
+    case 4:
+      return run_inplace<uint32_t>(keys, n, offsets, B, segmented, key_type, flags, scratch,
+                                   scratch_bytes, stream);
+    case 8:
+      return run_inplace<uint64_t>(keys, n, offsets, B, segmented, key_type, flags, scratch,
+                                   scratch_bytes, stream);
+    default:
+      return BSORT_EINVAL;
+  }
+}
+
 constexpr uint64_t BWD_MAX_SLICES = 8;
 constexpr uint32_t BWD_BLOCK = 1024;
 
@@ -916,6 +1168,27 @@ int bsort_gather(const void *values, int value_bytes, const void *indices,
   if (rc != BSORT_OK) return rc;
   return launch_gather(values, value_bytes, indices, (flags & BSORT_IDX64) != 0, offsets,
                        offsets ? num_segments : 1, n, out, cus, static_cast<hipStream_t>(stream));
+}
+
+size_t bsort_inplace_scratch_bytes(int key_bytes, uint64_t n, uint64_t num_segments,
+                                   uint32_t flags) {
+  if (flags & ~IP_FLAGS) return 0;
+  InplaceLayout L;
+  if (!inplace_layout(key_bytes, n, num_segments ? num_segments : 1, flags, &L)) return 0;
+  return L.total;
+}
+
+int bsort_sort_inplace(void *keys, int key_type, int key_bytes, uint64_t n, uint32_t flags,
+                       void *scratch, size_t scratch_bytes, void *stream) {
+  return dispatch_inplace(keys, key_type, key_bytes, n, nullptr, 1, false, flags, scratch,
+                          scratch_bytes, stream);
+}
+
+int bsort_segmented_inplace(void *keys, int key_type, int key_bytes, const int64_t *offsets,
+                            uint64_t num_segments, uint64_t n, uint32_t flags, void *scratch,
+                            size_t scratch_bytes, void *stream) {
+  return dispatch_inplace(keys, key_type, key_bytes, n, offsets, num_segments, true, flags,
+                          scratch, scratch_bytes, stream);
 }
 
 size_t bsort_scratch_bytes128(uint64_t n, int with_indices, uint32_t flags) {

@@ -518,11 +518,12 @@ struct PlanArgs {
   int idx64;
   int no_skip;
   int no_finish;
+  int inplace;  // the level partitioned in place: no buffers, no reversal, no counts
 };
 
 __global__ void plan_kernel(PlanArgs a) {
   const uint32_t S = (uint32_t)(a.l.hdr->packed[a.level] >> 32);
-  const uint32_t buf_out = (uint32_t)((a.level + 1) & 1) ? META_BUF : 0u;
+  const uint32_t buf_out = (!a.inplace && ((a.level + 1) & 1)) ? META_BUF : 0u;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.zero_n; i += stride) {
     a.zero_a[i] = 0;
@@ -567,7 +568,7 @@ __global__ void plan_kernel(PlanArgs a) {
         const uint64_t len = c ? p.len - F : F;
         const uint64_t andv = c ? and_hi : and_lo;
         const uint64_t orv = c ? or_hi : or_lo;
-        const uint32_t rev = c ? META_REV : 0u;
+        const uint32_t rev = (c && !a.inplace) ? META_REV : 0u;
         ch[c].start = c ? p.start + F : p.start;
         ch[c].len = len;
         if (len == 0) continue;
@@ -595,7 +596,7 @@ __global__ void plan_kernel(PlanArgs a) {
         } else {
           // the level counted this child's front keys on bit - 1 per tile;
           // a child that skipped to a lower bit is counted by the count pass
-          const bool pre = nb == bit - 1;
+          const bool pre = nb == bit - 1 && !a.inplace;
           ch[c].meta = meta | (pre ? META_PRE : 0u) | (uint32_t)nb;
           ch[c].kind = KIND_LIVE;
           ch[c].tiles = (uint32_t)((len + a.l.tile - 1) / a.l.tile);
@@ -1478,6 +1479,323 @@ __global__ void copy_kernel(CopyArgs<KT> a) {
         else static_cast<uint32_t *>(a.idx_final)[s.start + i] = v;
       }
     }
+  }
+}
+
+// ------------------------------------------------------- in-place levels
+//
+// A keys-only variant whose scratch is O(n / tile): each level partitions
+// every live segment in place, exchanging misplaced keys as Algorithm 1's
+// swap loop does, instead of scattering into a second buffer.  Equal keys
+// are indistinguishable, so the sorted keys equal the stable path's; the
+// exchange is not stable, so no permutation is produced.  Per level:
+//  count:  per tile, the front keys on the segment's bit (tcnt, sums per
+//          64-tile group in scnt, the segment total F in split) and the
+//          AND/OR of the front and of the back keys.  Those are properties
+//          of the two key sets, not of their positions, so they are taken
+//          before any key moves.
+//  prefix: per tile, the front keys in the segment's earlier tiles.
+//  locate: the split point is k = start + F.  The c back keys left of k and
+//          the c front keys right of k are exchanged in pairs: the a-th back
+//          key left of k, counted from the left, with the a-th front key
+//          right of k, counted from the segment's right end.  A tile whose
+//          back keys left of k have ranks a_j .. a_j + c_j - 1 owns those
+//          pairs; locate finds its first partner, the front key with
+//          F - 1 - a_j front keys to its left, before any key moves.
+//  swap:   the owner lists its back keys left of k, walks leftwards from its
+//          first partner collecting c_j front keys, and exchanges the pairs.
+//          Between its partners lie only back keys right of k, which no
+//          block writes; keys past its last partner may be changing, but
+//          they rank at or past c_j and are ignored.  Left of k, a tile's
+//          keys are written only by the tile's own block.
+
+constexpr uint64_t LOC_NONE = ~0ull;
+
+template <typename KT>
+struct InplaceArgs {
+  KT *keys;
+  const Seg *live;   // this level's live segments, in tile order
+  Seg *tiles;        // per tile: its segment (written by the count pass)
+  Header *hdr;
+  uint32_t *tcnt;    // per tile, at the segment's cbase + j
+  uint32_t *scnt;    // per 64-tile group, at cbase + j / 64
+  uint32_t *pre;     // per tile: front keys in the segment's earlier tiles
+  uint64_t *loc;     // per tile: position of its first partner
+  AccRep *acc;       // AND/OR replicas of the front (lo) and back (hi) keys
+  uint64_t *split;   // per segment slot: front keys F
+  int w, mode, desc, level;
+};
+
+// Exclusive prefix over the block; `total` gets the block's sum.  Uses
+// s_w[WAVES] and leaves it free for the next call.
+template <int WAVES>
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *s_w, uint32_t &total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint32_t inc = wave_incl_scan_dpp(v);
+  if (lane == 63) s_w[wave] = inc;
+  __syncthreads();
+  uint32_t before = 0, tot = 0;
+#pragma unroll
+  for (int q = 0; q < WAVES; ++q) {
+    const uint32_t x = s_w[q];
+    before += q < wave ? x : 0u;
+    tot += x;
+  }
+  __syncthreads();
+  total = tot;
+  return before + inc - v;
+}
+
+template <typename KT, int BLOCK, int IPT>
+__global__ __launch_bounds__(BLOCK) void ip_count_kernel(InplaceArgs<KT> a) {
+  constexpr int WAVES = BLOCK / 64;
+  constexpr uint32_t TILE = BLOCK * IPT;
+  __shared__ Seg s_seg;
+  __shared__ uint32_t s_c[WAVES];
+  __shared__ uint64_t s_acc[WAVES][4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (blockIdx.x == 0 && tid == 0) {
+    // the previous step's finish lists have been consumed
+    a.hdr->n_finish = 0;
+    a.hdr->n_finish_small = 0;
+    a.hdr->n_finish_tiny = 0;
+    a.hdr->n_finish_med = 0;
+  }
+  const uint64_t pk = a.hdr->packed[a.level];
+  const uint32_t S = (uint32_t)(pk >> 32), ntiles = (uint32_t)pk;
+  for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    if (tid == 0) {
+      uint32_t lo = 0, hi = S - 1;
+      while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (a.live[mid].tile0 <= t) lo = mid;
+        else hi = mid - 1;
+      }
+      s_seg = a.live[lo];
+      a.tiles[t] = s_seg;
+    }
+    __syncthreads();
+    const uint64_t start = uni(s_seg.start), len = uni(s_seg.len);
+    const uint32_t meta = uni(s_seg.meta), tile0 = uni(s_seg.tile0);
+    const uint32_t cbase = uni(s_seg.cbase), slot = uni(s_seg.slot);
+    const uint32_t j = t - tile0;
+    const int bit = (int)(meta & BIT_MASK);
+    const uint64_t f = (uint64_t)flip_of(bit, a.w, a.mode, a.desc, (meta & META_SIGN) ? 1 : 0);
+    const uint64_t lo = (uint64_t)j * TILE;
+    const uint32_t cnt = (uint32_t)(len - lo < (uint64_t)TILE ? len - lo : (uint64_t)TILE);
+    const rsrc_t kr = make_rsrc(a.keys + start + lo, cnt * (uint32_t)sizeof(KT));
+    uint32_t c = 0;
+    uint64_t and_f = ~0ull, or_f = 0, and_b = ~0ull, or_b = 0;
+#pragma unroll
+    for (int i = 0; i < IPT; ++i) {
+      const uint32_t q = (uint32_t)(i * BLOCK + tid);
+      const uint64_t k = (uint64_t)buf_load<KT>(kr, q * (uint32_t)sizeof(KT));
+      if (q < cnt) {
+        if (((k >> bit) & 1ull) == f) {
+          ++c;
+          and_f &= k;
+          or_f |= k;
+        } else {
+          and_b &= k;
+          or_b |= k;
+        }
+      }
+    }
+    c = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan_dpp(c), 63);
+    and_f = wave_and_dpp(and_f);
+    or_f = wave_or_dpp(or_f);
+    and_b = wave_and_dpp(and_b);
+    or_b = wave_or_dpp(or_b);
+    if (lane == 0) {
+      s_c[wave] = c;
+      s_acc[wave][0] = and_f;
+      s_acc[wave][1] = or_f;
+      s_acc[wave][2] = and_b;
+      s_acc[wave][3] = or_b;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      uint32_t sum = 0;
+      uint64_t af = ~0ull, of = 0, ab = ~0ull, ob = 0;
+#pragma unroll
+      for (int q = 0; q < WAVES; ++q) {
+        sum += s_c[q];
+        af &= s_acc[q][0];
+        of |= s_acc[q][1];
+        ab &= s_acc[q][2];
+        ob |= s_acc[q][3];
+      }
+      a.tcnt[cbase + j] = sum;
+      AccRep *z = &a.acc[tile0 + ACC_STRIDE * (j % acc_repl(len, TILE))];
+      if (sum) {
+        atomic_add_u32(&a.scnt[cbase + (j >> 6)], sum);
+        atomic_add_u64(&a.split[slot], sum);
+        atomic_and_u64(&z->and_lo, af);
+        atomic_or_u64(&z->or_lo, of);
+      }
+      if (sum < cnt) {
+        atomic_and_u64(&z->and_hi, ab);
+        atomic_or_u64(&z->or_hi, ob);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// One wave per tile: the sum of the group sums before the tile's group and
+// of the tile counts before it within the group.
+template <typename KT>
+__global__ __launch_bounds__(256) void ip_prefix_kernel(InplaceArgs<KT> a) {
+  const int lane = threadIdx.x & 63;
+  const uint32_t ntiles = (uint32_t)a.hdr->packed[a.level];
+  const uint32_t wpb = blockDim.x / 64;
+  for (uint32_t t = blockIdx.x * wpb + (threadIdx.x >> 6); t < ntiles; t += gridDim.x * wpb) {
+    const Seg s = a.tiles[t];
+    const uint32_t j = t - s.tile0;
+    uint32_t p = 0;
+    for (uint32_t g = (uint32_t)lane; g < (j >> 6); g += 64) p += a.scnt[s.cbase + g];
+    if ((uint32_t)lane < (j & 63u)) p += a.tcnt[s.cbase + (j & ~63u) + lane];
+    p = (uint32_t)wave_sum_u64(p);
+    if (lane == 0) a.pre[t] = p;
+  }
+}
+
+template <typename KT, int BLOCK, int IPT>
+__global__ __launch_bounds__(BLOCK) void ip_locate_kernel(InplaceArgs<KT> a) {
+  constexpr int WAVES = BLOCK / 64;
+  constexpr uint32_t TILE = BLOCK * IPT;
+  __shared__ uint32_t s_w[WAVES];
+  __shared__ uint32_t s_i;
+  __shared__ uint64_t s_pos;
+  const int tid = threadIdx.x;
+  const uint32_t ntiles = (uint32_t)a.hdr->packed[a.level];
+  for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const Seg sg = a.tiles[t];
+    const uint64_t start = uni(sg.start), len = uni(sg.len);
+    const uint32_t tile0 = uni(sg.tile0), j = t - tile0;
+    const uint64_t F = uni(a.split[uni(sg.slot)]);
+    const uint64_t aj = (uint64_t)j * TILE - a.pre[t];  // back keys before the tile
+    if ((uint64_t)j * TILE >= F || aj >= F) {
+      // the tile starts right of k, or owns no pair
+      if (tid == 0) a.loc[t] = LOC_NONE;
+      continue;
+    }
+    const uint32_t g = (uint32_t)(F - 1 - aj);  // front keys left of the first partner
+    if (tid == 0) {
+      const uint32_t nt = (uint32_t)((len + TILE - 1) / TILE);
+      uint32_t lo = 0, hi = nt - 1;
+      while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (a.pre[tile0 + mid] <= g) lo = mid;
+        else hi = mid - 1;
+      }
+      s_i = lo;
+      s_pos = LOC_NONE;
+    }
+    __syncthreads();
+    const uint32_t i = uni(s_i);
+    const uint32_t r = g - a.pre[tile0 + i];  // rank of the partner among tile i's fronts
+    const uint64_t lo = (uint64_t)i * TILE;
+    const uint32_t cnt = (uint32_t)(len - lo < (uint64_t)TILE ? len - lo : (uint64_t)TILE);
+    const int bit = (int)(uni(sg.meta) & BIT_MASK);
+    const uint64_t f =
+        (uint64_t)flip_of(bit, a.w, a.mode, a.desc, (uni(sg.meta) & META_SIGN) ? 1 : 0);
+    const rsrc_t kr = make_rsrc(a.keys + start + lo, cnt * (uint32_t)sizeof(KT));
+    uint32_t fr = 0;  // fronts among this thread's IPT consecutive keys, as bits
+#pragma unroll
+    for (int q = 0; q < IPT; ++q) {
+      const uint32_t p = (uint32_t)(tid * IPT + q);
+      const uint64_t k = (uint64_t)buf_load<KT>(kr, p * (uint32_t)sizeof(KT));
+      if (p < cnt && ((k >> bit) & 1ull) == f) fr |= 1u << q;
+    }
+    uint32_t total;
+    const uint32_t ex = block_excl_scan<WAVES>((uint32_t)__builtin_popcount(fr), s_w, total);
+    if (r >= ex && r < ex + (uint32_t)__builtin_popcount(fr)) {
+      uint32_t m = fr, skip = r - ex;
+      while (skip--) m &= m - 1;
+      s_pos = start + lo + (uint64_t)(tid * IPT) + (uint64_t)__builtin_ctz(m);
+    }
+    __syncthreads();
+    if (tid == 0) a.loc[t] = s_pos;
+    __syncthreads();
+  }
+}
+
+template <typename KT, int BLOCK, int IPT>
+__global__ __launch_bounds__(BLOCK) void ip_swap_kernel(InplaceArgs<KT> a) {
+  constexpr int WAVES = BLOCK / 64;
+  constexpr uint32_t TILE = BLOCK * IPT;
+  __shared__ uint32_t s_a[TILE];  // this tile's back keys left of k: offsets in the tile
+  __shared__ uint32_t s_b[TILE];  // their partners: absolute positions
+  __shared__ uint32_t s_w[WAVES];
+  const int tid = threadIdx.x;
+  const uint32_t ntiles = (uint32_t)a.hdr->packed[a.level];
+  for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const Seg sg = a.tiles[t];
+    const uint64_t start = uni(sg.start);
+    const uint32_t j = t - uni(sg.tile0);
+    const uint64_t F = uni(a.split[uni(sg.slot)]);
+    const uint64_t lo = (uint64_t)j * TILE;
+    if (lo >= F) continue;  // the tile starts right of k
+    const uint64_t k = start + F;
+    const uint64_t ts = start + lo;
+    const uint32_t lcnt = (uint32_t)(F - lo < (uint64_t)TILE ? F - lo : (uint64_t)TILE);
+    const int bit = (int)(uni(sg.meta) & BIT_MASK);
+    const uint64_t f =
+        (uint64_t)flip_of(bit, a.w, a.mode, a.desc, (uni(sg.meta) & META_SIGN) ? 1 : 0);
+    // back keys in [ts, ts + lcnt), in position order
+    const rsrc_t kl = make_rsrc(a.keys + ts, lcnt * (uint32_t)sizeof(KT));
+    uint32_t bk = 0;
+#pragma unroll
+    for (int q = 0; q < IPT; ++q) {
+      const uint32_t p = (uint32_t)(tid * IPT + q);
+      const uint64_t key = (uint64_t)buf_load<KT>(kl, p * (uint32_t)sizeof(KT));
+      if (p < lcnt && ((key >> bit) & 1ull) != f) bk |= 1u << q;
+    }
+    uint32_t cj;
+    uint32_t ex = block_excl_scan<WAVES>((uint32_t)__builtin_popcount(bk), s_w, cj);
+    for (uint32_t m = bk; m; m &= m - 1) s_a[ex++] = (uint32_t)(tid * IPT) + (uint32_t)__builtin_ctz(m);
+    cj = uni(cj);
+    if (cj == 0) {
+      __syncthreads();
+      continue;
+    }
+    const uint64_t first = uni(a.loc[t]);
+    uint32_t found = 0;
+    if (first != LOC_NONE && first >= k) {
+      // walk leftwards from the first partner, never below k
+      uint64_t hi = first;
+      while (found < cj) {
+        const uint64_t clo = hi + 1 >= k + TILE ? hi + 1 - TILE : k;
+        const uint32_t span = (uint32_t)(hi + 1 - clo);
+        uint32_t fr = 0;  // bit q: key hi - (tid * IPT + q) is a front key
+#pragma unroll
+        for (int q = 0; q < IPT; ++q) {
+          const uint32_t d = (uint32_t)(tid * IPT + q);
+          if (d < span) {
+            const uint64_t key = (uint64_t)a.keys[hi - d];
+            if (((key >> bit) & 1ull) == f) fr |= 1u << q;
+          }
+        }
+        uint32_t tot;
+        uint32_t rk = found + block_excl_scan<WAVES>((uint32_t)__builtin_popcount(fr), s_w, tot);
+        for (uint32_t m = fr; m && rk < cj; m &= m - 1, ++rk)
+          s_b[rk] = (uint32_t)(hi - (uint64_t)(tid * IPT + __builtin_ctz(m)));
+        found += uni(tot);
+        if (clo == k) break;
+        hi = clo - 1;
+      }
+    }
+    if (found < cj && tid == 0) atomic_or_u32(&a.hdr->status, STATUS_BAD_COUNTS);
+    const uint32_t pairs = found < cj ? found : cj;
+    __syncthreads();
+    for (uint32_t i = tid; i < pairs; i += BLOCK) {
+      const uint64_t pa = ts + s_a[i], pb = s_b[i];
+      const KT ka = a.keys[pa], kb = a.keys[pb];
+      a.keys[pa] = kb;
+      a.keys[pb] = ka;
+    }
+    __syncthreads();
   }
 }
 

@@ -212,3 +212,37 @@ def test_layout_validation():
     assert f(fake + 2, 0, 4, 100, 0, order, fake, fake, need, None) == _lib.EINVAL
     assert f(fake, 0, 4, 100, 0, order, fake, fake, need - 1, None) == _lib.ESCRATCH
 
+
+
+def test_inplace_validation_and_scratch():
+    """The in-place variant's scratch is a small fraction of the keys, and
+    bad arguments are refused before any device work."""
+    fake = 1 << 40
+    sb = _lib.bsort_inplace_scratch_bytes
+    for kb in (1, 2, 4, 8):
+        n = 1 << 26
+        need = sb(kb, n, 1, 0)
+        assert 0 < need < n * kb // 8, (kb, need)
+        # far below what the stable path asks for
+        assert need * 8 < _lib.bsort_scratch_bytes(kb, n, 1, 0, 0)
+    assert sb(3, 100, 1, 0) == 0                                  # width
+    assert sb(4, 100, 1, _lib.IDX64) == 0                         # no permutation output
+    assert sb(4, 100, 1, _lib.KEYS_UNCHANGED) == 0
+    assert sb(4, 1 << 20, 1, _lib.NO_FINISH) > sb(4, 1 << 20, 1, 0)
+    assert sb(4, 1 << 20, 5000, 0) > sb(4, 1 << 20, 1, 0)        # per-segment entries
+    f = _lib.bsort_sort_inplace
+    need = sb(4, 1000, 1, 0)
+    assert f(None, 0, 4, 0, 0, None, 0, None) == _lib.OK                       # n = 0
+    assert f(fake, 7, 4, 1000, 0, fake, need, None) == _lib.EINVAL             # family
+    assert f(fake, 0, 3, 1000, 0, fake, need, None) == _lib.EINVAL             # width
+    assert f(fake, 0, 4, 1000, _lib.IDX64, fake, need, None) == _lib.EINVAL    # flag
+    assert f(fake, 0, 4, 1000, 1 << 7, fake, need, None) == _lib.EINVAL
+    assert f(None, 0, 4, 1000, 0, fake, need, None) == _lib.EINVAL             # null keys
+    assert f(fake, 0, 4, 1000, 0, None, need, None) == _lib.EINVAL             # null scratch
+    assert f(fake, 0, 4, 1000, 0, fake, need - 1, None) == _lib.ESCRATCH
+    assert f(fake, 0, 4, 1000, 0, fake + 4, need, None) == _lib.EINVAL         # alignment
+    assert f(fake, 0, 4, 1 << 32, 0, fake, 1 << 62, None) == _lib.ETOOBIG
+    seg = _lib.bsort_segmented_inplace
+    assert seg(fake, 0, 4, None, 3, 10, 0, fake, 1 << 30, None) == _lib.EINVAL
+    assert seg(fake, 0, 4, fake, 0, 10, 0, fake, 1 << 30, None) == _lib.EINVAL
+    assert seg(fake, 0, 4, fake, 0, 0, 0, fake, 1 << 30, None) == _lib.OK
