@@ -539,6 +539,57 @@ def extras_small_segments(lib, torch, np, dev, stream):
     return out
 
 
+def extras_inplace(lib, torch, np, dev, stream):
+    """The in-place keys-only variant beside the stable keys-only sort on the
+    same arrays: time (keys restored outside the timed region), scratch each
+    asks for, and the sorted keys compared bit for bit."""
+    from paper_2603_08929_amd import workloads as W
+    out = []
+    fam = {"f32": lib.KEY_F, "u32": lib.KEY_U, "u64": lib.KEY_U, "u8": lib.KEY_U}
+    carrier = {4: torch.int32, 8: torch.int64, 1: torch.int8}
+    for name, n in (("f32", 1 << 26), ("u32", 1 << 26), ("u64", 1 << 27), ("u8", 1 << 26)):
+        log(f"in-place {name} n={n}")
+        kb = W.DTYPES[name][0] // 8
+        bits = W.normal_bits(name, n, 0) if name == "f32" else W.uniform_bits(name, n, 1)
+        npc = {1: np.int8, 4: np.int32, 8: np.int64}[kb]
+        src = torch.from_numpy(np.ascontiguousarray(bits.astype(W.DTYPES[name][2])).view(npc))
+        src = src.to(dev)
+        assert src.dtype == carrier[kb]
+        a = torch.empty_like(src)
+        b = torch.empty_like(src)
+        need_ip = lib.bsort_inplace_scratch_bytes(kb, n, 1, 0)
+        need_st = lib.bsort_scratch_bytes(kb, n, 1, 0, 0)
+        s_ip = torch.empty(need_ip, dtype=torch.uint8, device=dev)
+        s_st = torch.empty(need_st, dtype=torch.uint8, device=dev)
+
+        def run_ip():
+            lib.check(lib.bsort_sort_inplace(a.data_ptr(), fam[name], kb, n, 0, s_ip.data_ptr(),
+                                             need_ip, stream), "inplace")
+
+        def run_st():
+            lib.check(lib.bsort_sort(b.data_ptr(), fam[name], kb, n, 0, None, s_st.data_ptr(),
+                                     need_st, stream), "stable")
+
+        def med(buf, fn, reps=5):
+            ts = []
+            for _ in range(reps + 1):
+                buf.copy_(src)
+                torch.cuda.synchronize()
+                ts.append(timed(fn, 1, torch))
+            return sorted(ts[1:])[reps // 2]
+
+        t_ip = med(a, run_ip)
+        t_st = med(b, run_st)
+        ok = bool(torch.equal(a, b)) and lib.bsort_device_status(s_ip.data_ptr(), stream) == 0
+        out.append({"dtype": name, "n": n, "inplace_ms": round(t_ip, 3),
+                    "inplace_gkeys_s": round(n / t_ip / 1e6, 3), "stable_ms": round(t_st, 3),
+                    "inplace_scratch_bytes": int(need_ip), "stable_scratch_bytes": int(need_st),
+                    "scratch_ratio_of_keys": round(need_ip / (n * kb), 4), "keys_equal": ok})
+        del src, a, b, s_ip, s_st
+        torch.cuda.empty_cache()
+    return out
+
+
 def extras_backward(lib, torch, np, dev, stream):
     from paper_2603_08929_amd.autograd import sort_along
     out = []
@@ -706,7 +757,8 @@ def main() -> int:
                   "differentiable_sort": extras_backward(_lib, torch, np, dev, stream),
                   "argsort_and_pairs": extras_pairs(_lib, torch, np, dev, stream),
                   "keys_128_bit": extras_wide(_lib, torch, np, dev, stream),
-                  "small_segments": extras_small_segments(_lib, torch, np, dev, stream)}
+                  "small_segments": extras_small_segments(_lib, torch, np, dev, stream),
+                  "in_place": extras_inplace(_lib, torch, np, dev, stream)}
 
     cpu = None
     if not args.no_cpu_baseline:

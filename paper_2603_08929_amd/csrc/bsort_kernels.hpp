@@ -1488,26 +1488,34 @@ __global__ void copy_kernel(CopyArgs<KT> a) {
 // every live segment in place, exchanging misplaced keys as Algorithm 1's
 // swap loop does, instead of scattering into a second buffer.  Equal keys
 // are indistinguishable, so the sorted keys equal the stable path's; the
-// exchange is not stable, so no permutation is produced.  Per level:
+// exchange is not stable, so no permutation is produced.
+//
+// With F front keys the split point is k = start + F.  The c back keys left
+// of k and the c front keys right of k are exchanged in pairs: the r-th
+// back key left of k, counted from the left, with the r-th front key right
+// of k, counted from the segment's right end.  Tiles cut both rank
+// sequences: a tile left of k starts its back ranks at a_j (back keys
+// before it), a tile right of k starts its front ranks at b_i (front keys
+// after it).  A work item starts at every such boundary r0 and runs to the
+// next one, so it meets at most one tile on each side whatever the key
+// distribution: it takes the back keys of one tile from its left start and
+// the front keys of one tile from its right start, and exchanges as many
+// pairs as the shorter list holds.  The side whose tile ends at the next
+// boundary lists exactly the item's keys; the other side lists them first
+// and keys of later items after them.  An item reads only its own keys and
+// keys no block writes (back keys right of k, front keys left of k), apart
+// from those later keys, which it never uses.  Per level:
 //  count:  per tile, the front keys on the segment's bit (tcnt, sums per
 //          64-tile group in scnt, the segment total F in split) and the
 //          AND/OR of the front and of the back keys.  Those are properties
 //          of the two key sets, not of their positions, so they are taken
 //          before any key moves.
 //  prefix: per tile, the front keys in the segment's earlier tiles.
-//  locate: the split point is k = start + F.  The c back keys left of k and
-//          the c front keys right of k are exchanged in pairs: the a-th back
-//          key left of k, counted from the left, with the a-th front key
-//          right of k, counted from the segment's right end.  A tile whose
-//          back keys left of k have ranks a_j .. a_j + c_j - 1 owns those
-//          pairs; locate finds its first partner, the front key with
-//          F - 1 - a_j front keys to its left, before any key moves.
-//  swap:   the owner lists its back keys left of k, walks leftwards from its
-//          first partner collecting c_j front keys, and exchanges the pairs.
-//          Between its partners lie only back keys right of k, which no
-//          block writes; keys past its last partner may be changing, but
-//          they rank at or past c_j and are ignored.  Left of k, a tile's
-//          keys are written only by the tile's own block.
+//  locate: per tile, up to two items (one at its first back key left of k,
+//          one at its last front key right of k) and the partner position
+//          of each start, found before any key moves.  An item at a right
+//          tile's boundary that is also a left tile's is left to the latter.
+//  swap:   per item, list both sides in LDS and exchange.
 
 constexpr uint64_t LOC_NONE = ~0ull;
 
@@ -1520,7 +1528,7 @@ struct InplaceArgs {
   uint32_t *tcnt;    // per tile, at the segment's cbase + j
   uint32_t *scnt;    // per 64-tile group, at cbase + j / 64
   uint32_t *pre;     // per tile: front keys in the segment's earlier tiles
-  uint64_t *loc;     // per tile: position of its first partner
+  uint64_t *items;   // per tile: two items, each {left start, right start}
   AccRep *acc;       // AND/OR replicas of the front (lo) and back (hi) keys
   uint64_t *split;   // per segment slot: front keys F
   int w, mode, desc, level;
@@ -1544,6 +1552,38 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *s_w, u
   __syncthreads();
   total = tot;
   return before + inc - v;
+}
+
+// Position of the r-th key (from 0, in position order) of the given side
+// (front or back) among keys[base, base + lim); LOC_NONE if there are not
+// that many.  Each thread looks at IPT consecutive keys.  Ends with a
+// barrier; every thread gets the answer.
+template <typename KT, int BLOCK, int IPT>
+__device__ uint64_t select_side(const KT *keys, uint64_t base, uint32_t lim, uint32_t r,
+                                bool want_front, int bit, uint64_t f, uint32_t *s_w,
+                                uint64_t *s_pos) {
+  constexpr int WAVES = BLOCK / 64;
+  const int tid = threadIdx.x;
+  const rsrc_t kr = make_rsrc(keys + base, lim * (uint32_t)sizeof(KT));
+  uint32_t m = 0;
+#pragma unroll
+  for (int q = 0; q < IPT; ++q) {
+    const uint32_t p = (uint32_t)(tid * IPT + q);
+    const uint64_t k = (uint64_t)buf_load<KT>(kr, p * (uint32_t)sizeof(KT));
+    if (p < lim && ((((k >> bit) & 1ull) == f) == want_front)) m |= 1u << q;
+  }
+  if (tid == 0) *s_pos = LOC_NONE;
+  uint32_t total;
+  const uint32_t ex = block_excl_scan<WAVES>((uint32_t)__builtin_popcount(m), s_w, total);
+  if (r >= ex && r < ex + (uint32_t)__builtin_popcount(m)) {
+    uint32_t mm = m;
+    for (uint32_t skip = r - ex; skip; --skip) mm &= mm - 1;
+    *s_pos = base + (uint64_t)(tid * IPT) + (uint64_t)__builtin_ctz(mm);
+  }
+  __syncthreads();
+  const uint64_t pos = uni(*s_pos);
+  __syncthreads();
+  return pos;
 }
 
 template <typename KT, int BLOCK, int IPT>
@@ -1665,7 +1705,8 @@ __global__ __launch_bounds__(BLOCK) void ip_locate_kernel(InplaceArgs<KT> a) {
   constexpr int WAVES = BLOCK / 64;
   constexpr uint32_t TILE = BLOCK * IPT;
   __shared__ uint32_t s_w[WAVES];
-  __shared__ uint32_t s_i;
+  __shared__ uint32_t s_first, s_last;  // first back left of k, last front right of k (+1)
+  __shared__ uint32_t s_t;
   __shared__ uint64_t s_pos;
   const int tid = threadIdx.x;
   const uint32_t ntiles = (uint32_t)a.hdr->packed[a.level];
@@ -1674,49 +1715,90 @@ __global__ __launch_bounds__(BLOCK) void ip_locate_kernel(InplaceArgs<KT> a) {
     const uint64_t start = uni(sg.start), len = uni(sg.len);
     const uint32_t tile0 = uni(sg.tile0), j = t - tile0;
     const uint64_t F = uni(a.split[uni(sg.slot)]);
-    const uint64_t aj = (uint64_t)j * TILE - a.pre[t];  // back keys before the tile
-    if ((uint64_t)j * TILE >= F || aj >= F) {
-      // the tile starts right of k, or owns no pair
-      if (tid == 0) a.loc[t] = LOC_NONE;
-      continue;
-    }
-    const uint32_t g = (uint32_t)(F - 1 - aj);  // front keys left of the first partner
-    if (tid == 0) {
-      const uint32_t nt = (uint32_t)((len + TILE - 1) / TILE);
-      uint32_t lo = 0, hi = nt - 1;
-      while (lo < hi) {
-        const uint32_t mid = (lo + hi + 1) >> 1;
-        if (a.pre[tile0 + mid] <= g) lo = mid;
-        else hi = mid - 1;
-      }
-      s_i = lo;
-      s_pos = LOC_NONE;
-    }
-    __syncthreads();
-    const uint32_t i = uni(s_i);
-    const uint32_t r = g - a.pre[tile0 + i];  // rank of the partner among tile i's fronts
-    const uint64_t lo = (uint64_t)i * TILE;
-    const uint32_t cnt = (uint32_t)(len - lo < (uint64_t)TILE ? len - lo : (uint64_t)TILE);
     const int bit = (int)(uni(sg.meta) & BIT_MASK);
     const uint64_t f =
         (uint64_t)flip_of(bit, a.w, a.mode, a.desc, (uni(sg.meta) & META_SIGN) ? 1 : 0);
+    const uint64_t lo = (uint64_t)j * TILE;
+    const uint32_t cnt = (uint32_t)(len - lo < (uint64_t)TILE ? len - lo : (uint64_t)TILE);
+    // local bounds of the tile's left part [0, lend) and right part [rbeg, cnt)
+    const uint32_t lend = lo < F ? (uint32_t)(F - lo < cnt ? F - lo : cnt) : 0u;
+    const uint32_t rbeg = lend;
+    if (tid == 0) {
+      s_first = ~0u;
+      s_last = 0;
+    }
+    __syncthreads();
     const rsrc_t kr = make_rsrc(a.keys + start + lo, cnt * (uint32_t)sizeof(KT));
-    uint32_t fr = 0;  // fronts among this thread's IPT consecutive keys, as bits
+    uint32_t first = ~0u, last = 0, fronts = 0;
 #pragma unroll
     for (int q = 0; q < IPT; ++q) {
       const uint32_t p = (uint32_t)(tid * IPT + q);
       const uint64_t k = (uint64_t)buf_load<KT>(kr, p * (uint32_t)sizeof(KT));
-      if (p < cnt && ((k >> bit) & 1ull) == f) fr |= 1u << q;
+      const bool fr = ((k >> bit) & 1ull) == f;
+      if (p < lend && !fr && first == ~0u) first = p;
+      if (p >= rbeg && p < cnt && fr) last = p + 1;
+      fronts += (p < cnt && fr) ? 1u : 0u;
     }
-    uint32_t total;
-    const uint32_t ex = block_excl_scan<WAVES>((uint32_t)__builtin_popcount(fr), s_w, total);
-    if (r >= ex && r < ex + (uint32_t)__builtin_popcount(fr)) {
-      uint32_t m = fr, skip = r - ex;
-      while (skip--) m &= m - 1;
-      s_pos = start + lo + (uint64_t)(tid * IPT) + (uint64_t)__builtin_ctz(m);
+    if (first != ~0u) atomicMin(&s_first, first);
+    if (last) atomicMax(&s_last, last);
+    uint32_t tc;
+    (void)block_excl_scan<WAVES>(fronts, s_w, tc);  // its barriers publish s_first, s_last
+    const uint32_t fb = uni(s_first), lf = uni(s_last);
+    const uint32_t pre_t = uni(a.pre[t]);
+    const uint32_t nt = (uint32_t)((len + TILE - 1) / TILE);
+    uint64_t item[4] = {LOC_NONE, LOC_NONE, LOC_NONE, LOC_NONE};
+    if (fb != ~0u) {
+      // item at this tile's first back key left of k: rank r0 = back keys before the tile
+      const uint64_t r0 = lo - pre_t;
+      const uint32_t g = (uint32_t)(F - 1 - r0);  // front keys left of its partner
+      if (tid == 0) {
+        uint32_t l = 0, h = nt - 1;
+        while (l < h) {
+          const uint32_t mid = (l + h + 1) >> 1;
+          if (a.pre[tile0 + mid] <= g) l = mid;
+          else h = mid - 1;
+        }
+        s_t = l;
+      }
+      __syncthreads();
+      const uint32_t i = uni(s_t);
+      const uint64_t ilo = (uint64_t)i * TILE;
+      const uint32_t icnt = (uint32_t)(len - ilo < (uint64_t)TILE ? len - ilo : (uint64_t)TILE);
+      item[0] = start + lo + fb;
+      item[1] = select_side<KT, BLOCK, IPT>(a.keys, start + ilo, icnt, g - a.pre[tile0 + i], true,
+                                            bit, f, s_w, &s_pos);
     }
-    __syncthreads();
-    if (tid == 0) a.loc[t] = s_pos;
+    if (lf) {
+      // item at this tile's last front key right of k: rank r0 = front keys after the tile
+      const uint64_t r0 = F - pre_t - tc;
+      const uint32_t nl = (uint32_t)((F + TILE - 1) / TILE);  // tiles with a left part
+      if (tid == 0) {
+        uint32_t l = 0, h = nl - 1;  // last left tile whose back rank start a <= r0
+        while (l < h) {
+          const uint32_t mid = (l + h + 1) >> 1;
+          if ((uint64_t)mid * TILE - a.pre[tile0 + mid] <= r0) l = mid;
+          else h = mid - 1;
+        }
+        s_t = l;
+      }
+      __syncthreads();
+      const uint32_t jj = uni(s_t);
+      const uint64_t jlo = (uint64_t)jj * TILE;
+      const uint64_t aj = jlo - a.pre[tile0 + jj];
+      if (aj != r0) {  // else the left tile's own item starts here
+        const uint32_t jl = (uint32_t)(F - jlo < (uint64_t)TILE ? F - jlo : (uint64_t)TILE);
+        item[2] = select_side<KT, BLOCK, IPT>(a.keys, start + jlo, jl, (uint32_t)(r0 - aj), false,
+                                              bit, f, s_w, &s_pos);
+        item[3] = start + lo + (lf - 1);
+      }
+    }
+    if (tid == 0) {
+      uint64_t *o = &a.items[4ull * t];
+      o[0] = item[0];
+      o[1] = item[1];
+      o[2] = item[2];
+      o[3] = item[3];
+    }
     __syncthreads();
   }
 }
@@ -1725,72 +1807,52 @@ template <typename KT, int BLOCK, int IPT>
 __global__ __launch_bounds__(BLOCK) void ip_swap_kernel(InplaceArgs<KT> a) {
   constexpr int WAVES = BLOCK / 64;
   constexpr uint32_t TILE = BLOCK * IPT;
-  __shared__ uint32_t s_a[TILE];  // this tile's back keys left of k: offsets in the tile
-  __shared__ uint32_t s_b[TILE];  // their partners: absolute positions
+  __shared__ uint32_t s_a[TILE];  // back keys left of k, from the item's left start
+  __shared__ uint32_t s_b[TILE];  // front keys right of k, from its right start leftwards
   __shared__ uint32_t s_w[WAVES];
   const int tid = threadIdx.x;
   const uint32_t ntiles = (uint32_t)a.hdr->packed[a.level];
-  for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+  for (uint32_t u = blockIdx.x; u < 2 * ntiles; u += gridDim.x) {
+    const uint32_t t = u >> 1;
+    const uint64_t ls = uni(a.items[4ull * t + 2 * (u & 1)]);
+    const uint64_t rs = uni(a.items[4ull * t + 2 * (u & 1) + 1]);
+    if (ls == LOC_NONE || rs == LOC_NONE) continue;
     const Seg sg = a.tiles[t];
     const uint64_t start = uni(sg.start);
-    const uint32_t j = t - uni(sg.tile0);
-    const uint64_t F = uni(a.split[uni(sg.slot)]);
-    const uint64_t lo = (uint64_t)j * TILE;
-    if (lo >= F) continue;  // the tile starts right of k
-    const uint64_t k = start + F;
-    const uint64_t ts = start + lo;
-    const uint32_t lcnt = (uint32_t)(F - lo < (uint64_t)TILE ? F - lo : (uint64_t)TILE);
+    const uint64_t k = start + uni(a.split[uni(sg.slot)]);
+    if (ls >= k || rs < k) {
+      if (tid == 0) atomic_or_u32(&a.hdr->status, STATUS_BAD_COUNTS);
+      continue;
+    }
     const int bit = (int)(uni(sg.meta) & BIT_MASK);
     const uint64_t f =
         (uint64_t)flip_of(bit, a.w, a.mode, a.desc, (uni(sg.meta) & META_SIGN) ? 1 : 0);
-    // back keys in [ts, ts + lcnt), in position order
-    const rsrc_t kl = make_rsrc(a.keys + ts, lcnt * (uint32_t)sizeof(KT));
-    uint32_t bk = 0;
+    // left: [ls, end of ls's tile) below k; right: (start of rs's tile, rs] at or above k
+    const uint64_t lte = start + ((ls - start) / TILE + 1) * TILE;
+    const uint32_t ln = (uint32_t)((lte < k ? lte : k) - ls);
+    const uint64_t rtb = start + ((rs - start) / TILE) * TILE;
+    const uint32_t rn = (uint32_t)(rs + 1 - (rtb > k ? rtb : k));
+    const rsrc_t kl = make_rsrc(a.keys + ls, ln * (uint32_t)sizeof(KT));
+    uint32_t mb = 0, mf = 0;
 #pragma unroll
     for (int q = 0; q < IPT; ++q) {
-      const uint32_t p = (uint32_t)(tid * IPT + q);
-      const uint64_t key = (uint64_t)buf_load<KT>(kl, p * (uint32_t)sizeof(KT));
-      if (p < lcnt && ((key >> bit) & 1ull) != f) bk |= 1u << q;
-    }
-    uint32_t cj;
-    uint32_t ex = block_excl_scan<WAVES>((uint32_t)__builtin_popcount(bk), s_w, cj);
-    for (uint32_t m = bk; m; m &= m - 1) s_a[ex++] = (uint32_t)(tid * IPT) + (uint32_t)__builtin_ctz(m);
-    cj = uni(cj);
-    if (cj == 0) {
-      __syncthreads();
-      continue;
-    }
-    const uint64_t first = uni(a.loc[t]);
-    uint32_t found = 0;
-    if (first != LOC_NONE && first >= k) {
-      // walk leftwards from the first partner, never below k
-      uint64_t hi = first;
-      while (found < cj) {
-        const uint64_t clo = hi + 1 >= k + TILE ? hi + 1 - TILE : k;
-        const uint32_t span = (uint32_t)(hi + 1 - clo);
-        uint32_t fr = 0;  // bit q: key hi - (tid * IPT + q) is a front key
-#pragma unroll
-        for (int q = 0; q < IPT; ++q) {
-          const uint32_t d = (uint32_t)(tid * IPT + q);
-          if (d < span) {
-            const uint64_t key = (uint64_t)a.keys[hi - d];
-            if (((key >> bit) & 1ull) == f) fr |= 1u << q;
-          }
-        }
-        uint32_t tot;
-        uint32_t rk = found + block_excl_scan<WAVES>((uint32_t)__builtin_popcount(fr), s_w, tot);
-        for (uint32_t m = fr; m && rk < cj; m &= m - 1, ++rk)
-          s_b[rk] = (uint32_t)(hi - (uint64_t)(tid * IPT + __builtin_ctz(m)));
-        found += uni(tot);
-        if (clo == k) break;
-        hi = clo - 1;
+      const uint32_t d = (uint32_t)(tid * IPT + q);
+      const uint64_t key = (uint64_t)buf_load<KT>(kl, d * (uint32_t)sizeof(KT));
+      if (d < ln && ((key >> bit) & 1ull) != f) mb |= 1u << q;
+      if (d < rn) {
+        const uint64_t kr = (uint64_t)a.keys[rs - d];
+        if (((kr >> bit) & 1ull) == f) mf |= 1u << q;
       }
     }
-    if (found < cj && tid == 0) atomic_or_u32(&a.hdr->status, STATUS_BAD_COUNTS);
-    const uint32_t pairs = found < cj ? found : cj;
+    uint32_t na, nb;
+    uint32_t ea = block_excl_scan<WAVES>((uint32_t)__builtin_popcount(mb), s_w, na);
+    uint32_t eb = block_excl_scan<WAVES>((uint32_t)__builtin_popcount(mf), s_w, nb);
+    for (uint32_t m = mb; m; m &= m - 1) s_a[ea++] = (uint32_t)(ls + tid * IPT + __builtin_ctz(m));
+    for (uint32_t m = mf; m; m &= m - 1) s_b[eb++] = (uint32_t)(rs - (tid * IPT + __builtin_ctz(m)));
+    const uint32_t pairs = uni(na < nb ? na : nb);
     __syncthreads();
     for (uint32_t i = tid; i < pairs; i += BLOCK) {
-      const uint64_t pa = ts + s_a[i], pb = s_b[i];
+      const uint64_t pa = s_a[i], pb = s_b[i];
       const KT ka = a.keys[pa], kb = a.keys[pb];
       a.keys[pa] = kb;
       a.keys[pb] = ka;
