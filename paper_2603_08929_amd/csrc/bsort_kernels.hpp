@@ -1554,6 +1554,24 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *s_w, u
   return before + inc - v;
 }
 
+// Largest i in [0, n) with le(i), for a predicate that holds on a prefix of
+// [0, n) and at 0: a 64-ary search by one whole wave (every lane probes one
+// point per round), so a search over 2^14 entries takes three dependent
+// loads instead of fourteen.  All 64 lanes must call it.
+template <typename Le>
+__device__ __forceinline__ uint32_t wave_search_le(uint32_t n, Le le) {
+  const uint32_t lane = threadIdx.x & 63;
+  uint32_t lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const uint32_t step = (hi - lo + 64) / 64;
+    const uint32_t idx = lo + lane * step;
+    const uint64_t ok = __ballot(idx <= hi && le(idx));
+    lo += ((uint32_t)__popcll(ok) - 1) * step;
+    hi = lo + step - 1 < hi ? lo + step - 1 : hi;
+  }
+  return lo;
+}
+
 // Position of the r-th key (from 0, in position order) of the given side
 // (front or back) among keys[base, base + lim); LOC_NONE if there are not
 // that many.  Each thread looks at IPT consecutive keys.  Ends with a
@@ -1604,15 +1622,12 @@ __global__ __launch_bounds__(BLOCK) void ip_count_kernel(InplaceArgs<KT> a) {
   const uint64_t pk = a.hdr->packed[a.level];
   const uint32_t S = (uint32_t)(pk >> 32), ntiles = (uint32_t)pk;
   for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    if (tid == 0) {
-      uint32_t lo = 0, hi = S - 1;
-      while (lo < hi) {
-        const uint32_t mid = (lo + hi + 1) >> 1;
-        if (a.live[mid].tile0 <= t) lo = mid;
-        else hi = mid - 1;
+    if (wave == 0) {
+      const uint32_t q = wave_search_le(S, [&](uint32_t i) { return a.live[i].tile0 <= t; });
+      if (lane == 0) {
+        s_seg = a.live[q];
+        a.tiles[t] = s_seg;
       }
-      s_seg = a.live[lo];
-      a.tiles[t] = s_seg;
     }
     __syncthreads();
     const uint64_t start = uni(s_seg.start), len = uni(s_seg.len);
@@ -1751,14 +1766,9 @@ __global__ __launch_bounds__(BLOCK) void ip_locate_kernel(InplaceArgs<KT> a) {
       // item at this tile's first back key left of k: rank r0 = back keys before the tile
       const uint64_t r0 = lo - pre_t;
       const uint32_t g = (uint32_t)(F - 1 - r0);  // front keys left of its partner
-      if (tid == 0) {
-        uint32_t l = 0, h = nt - 1;
-        while (l < h) {
-          const uint32_t mid = (l + h + 1) >> 1;
-          if (a.pre[tile0 + mid] <= g) l = mid;
-          else h = mid - 1;
-        }
-        s_t = l;
+      if (tid < 64) {
+        const uint32_t l = wave_search_le(nt, [&](uint32_t i) { return a.pre[tile0 + i] <= g; });
+        if (tid == 0) s_t = l;
       }
       __syncthreads();
       const uint32_t i = uni(s_t);
@@ -1772,14 +1782,10 @@ __global__ __launch_bounds__(BLOCK) void ip_locate_kernel(InplaceArgs<KT> a) {
       // item at this tile's last front key right of k: rank r0 = front keys after the tile
       const uint64_t r0 = F - pre_t - tc;
       const uint32_t nl = (uint32_t)((F + TILE - 1) / TILE);  // tiles with a left part
-      if (tid == 0) {
-        uint32_t l = 0, h = nl - 1;  // last left tile whose back rank start a <= r0
-        while (l < h) {
-          const uint32_t mid = (l + h + 1) >> 1;
-          if ((uint64_t)mid * TILE - a.pre[tile0 + mid] <= r0) l = mid;
-          else h = mid - 1;
-        }
-        s_t = l;
+      if (tid < 64) {  // last left tile whose back rank start a <= r0
+        const uint32_t l = wave_search_le(
+            nl, [&](uint32_t i) { return (uint64_t)i * TILE - a.pre[tile0 + i] <= r0; });
+        if (tid == 0) s_t = l;
       }
       __syncthreads();
       const uint32_t jj = uni(s_t);
