@@ -731,8 +731,8 @@ int sort128(void *keys, int key_type, uint64_t n, uint32_t flags, void *indices,
 constexpr uint32_t IP_FLAGS = BSORT_DESCENDING | BSORT_NO_SKIP | BSORT_NO_FINISH;
 
 struct InplaceLayout {
-  size_t hdr, cnts, segs[2], recs[2], acc[2], split[2], tmap, pre, items, fin, fins, fint, finm,
-      cpy, total;
+  size_t hdr, cnts, segs[2], recs[2], acc[2], split[2], tmap, pre, sub, ends, items, fin, fins,
+      fint, finm, cpy, total;
   uint64_t smax, tmax, fmax;
 };
 
@@ -753,6 +753,8 @@ bool inplace_layout(int key_bytes, uint64_t n, uint64_t B, uint32_t flags, Inpla
   for (int i = 0; i < 2; ++i) { L->split[i] = off; off = up256(off + L->smax * 8); }
   L->tmap = off; off = up256(off + L->tmax * sizeof(Seg));
   L->pre = off; off = up256(off + L->tmax * 4);
+  L->sub = off; off = up256(off + L->tmax * 8 * 4);   // front keys per wave chunk (8 waves)
+  L->ends = off; off = up256(off + L->tmax * 8);
   L->items = off; off = up256(off + L->tmax * 32);  // two {left, right} starts per tile
   L->fin = off; off = up256(off + L->fmax * sizeof(Seg));
   L->fins = off; off = up256(off + L->fmax * sizeof(Seg));
@@ -871,10 +873,8 @@ int launch_inplace(KT *keys, uint64_t n, const int64_t *offsets, uint64_t B, int
   auto ck = ip_count_kernel<KT, LS::LB, LS::LIPT>;
   auto lk = ip_locate_kernel<KT, LS::LB, LS::LIPT>;
   auto sk = ip_swap_kernel<KT, LS::LB, LS::LIPT>;
-  static const int occ_c = occupancy(ck, LS::LB), occ_l = occupancy(lk, LS::LB),
-                   occ_s = occupancy(sk, LS::LB);
+  static const int occ_c = occupancy(ck, LS::LB), occ_s = occupancy(sk, LS::LB);
   const uint32_t cgrid = clamp_grid(L.tmax, (uint64_t)cus * occ_c);
-  const uint32_t lgrid = clamp_grid(L.tmax, (uint64_t)cus * occ_l);
   const uint32_t sgrid = clamp_grid(2 * L.tmax, (uint64_t)cus * occ_s);
   const uint32_t xgrid = clamp_grid((L.tmax + 3) / 4, cap);
   const uint32_t pgrid = clamp_grid((L.smax + 255) / 256, cap);
@@ -888,6 +888,8 @@ int launch_inplace(KT *keys, uint64_t n, const int64_t *offsets, uint64_t B, int
     a.tcnt = tcnt[lvl & 1];
     a.scnt = scnt[lvl & 1];
     a.pre = reinterpret_cast<uint32_t *>(scr + L.pre);
+    a.sub = reinterpret_cast<uint32_t *>(scr + L.sub);
+    a.ends = reinterpret_cast<uint32_t *>(scr + L.ends);
     a.items = reinterpret_cast<uint64_t *>(scr + L.items);
     a.acc = acc[lvl & 1];
     a.split = split[lvl & 1];
@@ -897,7 +899,7 @@ int launch_inplace(KT *keys, uint64_t n, const int64_t *offsets, uint64_t B, int
     a.level = lvl;
     hipLaunchKernelGGL(ck, dim3(cgrid), dim3(LS::LB), 0, st, a);
     hipLaunchKernelGGL((ip_prefix_kernel<KT>), dim3(xgrid), dim3(256), 0, st, a);
-    hipLaunchKernelGGL(lk, dim3(lgrid), dim3(LS::LB), 0, st, a);
+    hipLaunchKernelGGL(lk, dim3(xgrid), dim3(256), 0, st, a);
     hipLaunchKernelGGL(sk, dim3(sgrid), dim3(LS::LB), 0, st, a);
 
     PlanArgs pa;

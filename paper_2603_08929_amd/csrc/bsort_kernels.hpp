@@ -1513,8 +1513,13 @@ __global__ void copy_kernel(CopyArgs<KT> a) {
 //  prefix: per tile, the front keys in the segment's earlier tiles.
 //  locate: per tile, up to two items (one at its first back key left of k,
 //          one at its last front key right of k) and the partner position
-//          of each start, found before any key moves.  An item at a right
+//          of each start, found before any key moves: one wave per tile
+//          searches the tile prefixes, then the partner tile's per-chunk
+//          counts, and reads a single 64 * IPT-key chunk.  An item at a right
 //          tile's boundary that is also a left tile's is left to the latter.
+//  (count also records each tile's first back and last front key and the
+//  front keys of each wave's chunk: wave w of the block reads the tile's
+//  keys [w * 64 * IPT, (w + 1) * 64 * IPT).)
 //  swap:   per item, list both sides in LDS and exchange.
 
 constexpr uint64_t LOC_NONE = ~0ull;
@@ -1528,6 +1533,8 @@ struct InplaceArgs {
   uint32_t *tcnt;    // per tile, at the segment's cbase + j
   uint32_t *scnt;    // per 64-tile group, at cbase + j / 64
   uint32_t *pre;     // per tile: front keys in the segment's earlier tiles
+  uint32_t *sub;     // per tile and wave: front keys of the wave's 64 * IPT-key chunk
+  uint32_t *ends;    // per tile: first back key, last front key + 1 (tile positions)
   uint64_t *items;   // per tile: two items, each {left start, right start}
   AccRep *acc;       // AND/OR replicas of the front (lo) and back (hi) keys
   uint64_t *split;   // per segment slot: front keys F
@@ -1573,43 +1580,55 @@ __device__ __forceinline__ uint32_t wave_search_le(uint32_t n, Le le) {
 }
 
 // Position of the r-th key (from 0, in position order) of the given side
-// (front or back) among keys[base, base + lim); LOC_NONE if there are not
-// that many.  Each thread looks at IPT consecutive keys.  Ends with a
-// barrier; every thread gets the answer.
-template <typename KT, int BLOCK, int IPT>
-__device__ uint64_t select_side(const KT *keys, uint64_t base, uint32_t lim, uint32_t r,
-                                bool want_front, int bit, uint64_t f, uint32_t *s_w,
-                                uint64_t *s_pos) {
-  constexpr int WAVES = BLOCK / 64;
-  const int tid = threadIdx.x;
-  const rsrc_t kr = make_rsrc(keys + base, lim * (uint32_t)sizeof(KT));
-  uint32_t m = 0;
+// (front or back) among a tile's keys [base, base + cnt), or LOC_NONE if
+// there are not that many.  sub[0, WAVES) holds the front keys of each
+// 64 * IPT-key chunk of the tile (as the count pass reads it), so one wave
+// finds the chunk from the counts and reads that chunk only.  All 64 lanes
+// must call it; every lane gets the answer.
+template <typename KT, int WAVES, int IPT>
+__device__ uint64_t wave_select(const KT *keys, uint64_t base, uint32_t cnt, const uint32_t *sub,
+                                uint32_t r, bool want_front, int bit, uint64_t f) {
+  constexpr uint32_t SUB = 64 * IPT;
+  const uint32_t lane = threadIdx.x & 63;
+  uint32_t cw = 0;
+  if (lane < (uint32_t)WAVES) {
+    const uint32_t c0 = lane * SUB;
+    const uint32_t clen = cnt > c0 ? (cnt - c0 < SUB ? cnt - c0 : SUB) : 0u;
+    const uint32_t fr = sub[lane];
+    cw = want_front ? fr : clen - fr;
+  }
+  const uint32_t inc = wave_incl_scan_u32(cw);
+  const uint64_t past = __ballot(lane < (uint32_t)WAVES && inc > r);
+  if (!past) return LOC_NONE;
+  const int sc = __ffsll((unsigned long long)past) - 1;
+  uint32_t rr = r - (uint32_t)__shfl((int)(inc - cw), sc);
+  const uint32_t c0 = (uint32_t)sc * SUB;
 #pragma unroll
-  for (int q = 0; q < IPT; ++q) {
-    const uint32_t p = (uint32_t)(tid * IPT + q);
-    const uint64_t k = (uint64_t)buf_load<KT>(kr, p * (uint32_t)sizeof(KT));
-    if (p < lim && ((((k >> bit) & 1ull) == f) == want_front)) m |= 1u << q;
+  for (int i = 0; i < IPT; ++i) {
+    const uint32_t q = c0 + (uint32_t)(i * 64) + lane;
+    bool hit = false;
+    if (q < cnt) {
+      const uint64_t k = (uint64_t)keys[base + q];
+      hit = ((((k >> bit) & 1ull) == f) == want_front);
+    }
+    const uint64_t m = __ballot(hit);
+    const uint32_t pc = (uint32_t)__popcll(m);
+    if (rr < pc) {
+      uint64_t mm = m;
+      for (uint32_t z = 0; z < rr; ++z) mm &= mm - 1;
+      return base + c0 + (uint64_t)(i * 64) + (uint64_t)(__ffsll((unsigned long long)mm) - 1);
+    }
+    rr -= pc;
   }
-  if (tid == 0) *s_pos = LOC_NONE;
-  uint32_t total;
-  const uint32_t ex = block_excl_scan<WAVES>((uint32_t)__builtin_popcount(m), s_w, total);
-  if (r >= ex && r < ex + (uint32_t)__builtin_popcount(m)) {
-    uint32_t mm = m;
-    for (uint32_t skip = r - ex; skip; --skip) mm &= mm - 1;
-    *s_pos = base + (uint64_t)(tid * IPT) + (uint64_t)__builtin_ctz(mm);
-  }
-  __syncthreads();
-  const uint64_t pos = uni(*s_pos);
-  __syncthreads();
-  return pos;
+  return LOC_NONE;
 }
 
 template <typename KT, int BLOCK, int IPT>
 __global__ __launch_bounds__(BLOCK) void ip_count_kernel(InplaceArgs<KT> a) {
   constexpr int WAVES = BLOCK / 64;
-  constexpr uint32_t TILE = BLOCK * IPT;
+  constexpr uint32_t TILE = BLOCK * IPT, SUB = 64 * IPT;
   __shared__ Seg s_seg;
-  __shared__ uint32_t s_c[WAVES];
+  __shared__ uint32_t s_c[WAVES], s_fb[WAVES], s_lf[WAVES];
   __shared__ uint64_t s_acc[WAVES][4];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (blockIdx.x == 0 && tid == 0) {
@@ -1639,30 +1658,40 @@ __global__ __launch_bounds__(BLOCK) void ip_count_kernel(InplaceArgs<KT> a) {
     const uint64_t lo = (uint64_t)j * TILE;
     const uint32_t cnt = (uint32_t)(len - lo < (uint64_t)TILE ? len - lo : (uint64_t)TILE);
     const rsrc_t kr = make_rsrc(a.keys + start + lo, cnt * (uint32_t)sizeof(KT));
-    uint32_t c = 0;
+    uint32_t c = 0, fb = ~0u, lf = 0;
     uint64_t and_f = ~0ull, or_f = 0, and_b = ~0ull, or_b = 0;
 #pragma unroll
     for (int i = 0; i < IPT; ++i) {
-      const uint32_t q = (uint32_t)(i * BLOCK + tid);
+      const uint32_t q = (uint32_t)(wave * SUB + i * 64 + lane);
       const uint64_t k = (uint64_t)buf_load<KT>(kr, q * (uint32_t)sizeof(KT));
       if (q < cnt) {
         if (((k >> bit) & 1ull) == f) {
           ++c;
           and_f &= k;
           or_f |= k;
+          lf = q + 1;
         } else {
           and_b &= k;
           or_b |= k;
+          fb = fb < q ? fb : q;
         }
       }
     }
     c = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan_dpp(c), 63);
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+      const uint32_t ofb = (uint32_t)__shfl_xor((int)fb, d), olf = (uint32_t)__shfl_xor((int)lf, d);
+      fb = ofb < fb ? ofb : fb;
+      lf = olf > lf ? olf : lf;
+    }
     and_f = wave_and_dpp(and_f);
     or_f = wave_or_dpp(or_f);
     and_b = wave_and_dpp(and_b);
     or_b = wave_or_dpp(or_b);
     if (lane == 0) {
       s_c[wave] = c;
+      s_fb[wave] = fb;
+      s_lf[wave] = lf;
       s_acc[wave][0] = and_f;
       s_acc[wave][1] = or_f;
       s_acc[wave][2] = and_b;
@@ -1670,17 +1699,21 @@ __global__ __launch_bounds__(BLOCK) void ip_count_kernel(InplaceArgs<KT> a) {
     }
     __syncthreads();
     if (tid == 0) {
-      uint32_t sum = 0;
+      uint32_t sum = 0, tfb = ~0u, tlf = 0;
       uint64_t af = ~0ull, of = 0, ab = ~0ull, ob = 0;
 #pragma unroll
       for (int q = 0; q < WAVES; ++q) {
         sum += s_c[q];
+        tfb = tfb < s_fb[q] ? tfb : s_fb[q];
+        tlf = tlf > s_lf[q] ? tlf : s_lf[q];
         af &= s_acc[q][0];
         of |= s_acc[q][1];
         ab &= s_acc[q][2];
         ob |= s_acc[q][3];
       }
       a.tcnt[cbase + j] = sum;
+      a.ends[2ull * t] = tfb;
+      a.ends[2ull * t + 1] = tlf;
       AccRep *z = &a.acc[tile0 + ACC_STRIDE * (j % acc_repl(len, TILE))];
       if (sum) {
         atomic_add_u32(&a.scnt[cbase + (j >> 6)], sum);
@@ -1693,6 +1726,7 @@ __global__ __launch_bounds__(BLOCK) void ip_count_kernel(InplaceArgs<KT> a) {
         atomic_or_u64(&z->or_hi, ob);
       }
     }
+    if (tid < WAVES) a.sub[(uint64_t)t * WAVES + tid] = s_c[tid];
     __syncthreads();
   }
 }
@@ -1715,17 +1749,16 @@ __global__ __launch_bounds__(256) void ip_prefix_kernel(InplaceArgs<KT> a) {
   }
 }
 
+// One wave per tile.  BLOCK and IPT are the count pass's shape (the tile
+// and its chunks).
 template <typename KT, int BLOCK, int IPT>
-__global__ __launch_bounds__(BLOCK) void ip_locate_kernel(InplaceArgs<KT> a) {
+__global__ __launch_bounds__(256) void ip_locate_kernel(InplaceArgs<KT> a) {
   constexpr int WAVES = BLOCK / 64;
   constexpr uint32_t TILE = BLOCK * IPT;
-  __shared__ uint32_t s_w[WAVES];
-  __shared__ uint32_t s_first, s_last;  // first back left of k, last front right of k (+1)
-  __shared__ uint32_t s_t;
-  __shared__ uint64_t s_pos;
-  const int tid = threadIdx.x;
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t wpb = blockDim.x / 64;
   const uint32_t ntiles = (uint32_t)a.hdr->packed[a.level];
-  for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+  for (uint32_t t = blockIdx.x * wpb + (threadIdx.x >> 6); t < ntiles; t += gridDim.x * wpb) {
     const Seg sg = a.tiles[t];
     const uint64_t start = uni(sg.start), len = uni(sg.len);
     const uint32_t tile0 = uni(sg.tile0), j = t - tile0;
@@ -1735,77 +1768,47 @@ __global__ __launch_bounds__(BLOCK) void ip_locate_kernel(InplaceArgs<KT> a) {
         (uint64_t)flip_of(bit, a.w, a.mode, a.desc, (uni(sg.meta) & META_SIGN) ? 1 : 0);
     const uint64_t lo = (uint64_t)j * TILE;
     const uint32_t cnt = (uint32_t)(len - lo < (uint64_t)TILE ? len - lo : (uint64_t)TILE);
-    // local bounds of the tile's left part [0, lend) and right part [rbeg, cnt)
+    // the tile's left part is [0, lend), its right part [lend, cnt)
     const uint32_t lend = lo < F ? (uint32_t)(F - lo < cnt ? F - lo : cnt) : 0u;
-    const uint32_t rbeg = lend;
-    if (tid == 0) {
-      s_first = ~0u;
-      s_last = 0;
-    }
-    __syncthreads();
-    const rsrc_t kr = make_rsrc(a.keys + start + lo, cnt * (uint32_t)sizeof(KT));
-    uint32_t first = ~0u, last = 0, fronts = 0;
-#pragma unroll
-    for (int q = 0; q < IPT; ++q) {
-      const uint32_t p = (uint32_t)(tid * IPT + q);
-      const uint64_t k = (uint64_t)buf_load<KT>(kr, p * (uint32_t)sizeof(KT));
-      const bool fr = ((k >> bit) & 1ull) == f;
-      if (p < lend && !fr && first == ~0u) first = p;
-      if (p >= rbeg && p < cnt && fr) last = p + 1;
-      fronts += (p < cnt && fr) ? 1u : 0u;
-    }
-    if (first != ~0u) atomicMin(&s_first, first);
-    if (last) atomicMax(&s_last, last);
-    uint32_t tc;
-    (void)block_excl_scan<WAVES>(fronts, s_w, tc);  // its barriers publish s_first, s_last
-    const uint32_t fb = uni(s_first), lf = uni(s_last);
+    const uint32_t fb = uni(a.ends[2ull * t]), lf = uni(a.ends[2ull * t + 1]);
     const uint32_t pre_t = uni(a.pre[t]);
     const uint32_t nt = (uint32_t)((len + TILE - 1) / TILE);
     uint64_t item[4] = {LOC_NONE, LOC_NONE, LOC_NONE, LOC_NONE};
-    if (fb != ~0u) {
+    if (fb < lend) {
       // item at this tile's first back key left of k: rank r0 = back keys before the tile
       const uint64_t r0 = lo - pre_t;
       const uint32_t g = (uint32_t)(F - 1 - r0);  // front keys left of its partner
-      if (tid < 64) {
-        const uint32_t l = wave_search_le(nt, [&](uint32_t i) { return a.pre[tile0 + i] <= g; });
-        if (tid == 0) s_t = l;
-      }
-      __syncthreads();
-      const uint32_t i = uni(s_t);
+      const uint32_t i = wave_search_le(nt, [&](uint32_t x) { return a.pre[tile0 + x] <= g; });
       const uint64_t ilo = (uint64_t)i * TILE;
       const uint32_t icnt = (uint32_t)(len - ilo < (uint64_t)TILE ? len - ilo : (uint64_t)TILE);
       item[0] = start + lo + fb;
-      item[1] = select_side<KT, BLOCK, IPT>(a.keys, start + ilo, icnt, g - a.pre[tile0 + i], true,
-                                            bit, f, s_w, &s_pos);
+      item[1] = wave_select<KT, WAVES, IPT>(a.keys, start + ilo, icnt,
+                                            &a.sub[(uint64_t)(tile0 + i) * WAVES],
+                                            g - uni(a.pre[tile0 + i]), true, bit, f);
     }
-    if (lf) {
+    if (lf > lend) {
       // item at this tile's last front key right of k: rank r0 = front keys after the tile
-      const uint64_t r0 = F - pre_t - tc;
+      const uint64_t r0 = F - pre_t - uni(a.tcnt[uni(sg.cbase) + j]);
       const uint32_t nl = (uint32_t)((F + TILE - 1) / TILE);  // tiles with a left part
-      if (tid < 64) {  // last left tile whose back rank start a <= r0
-        const uint32_t l = wave_search_le(
-            nl, [&](uint32_t i) { return (uint64_t)i * TILE - a.pre[tile0 + i] <= r0; });
-        if (tid == 0) s_t = l;
-      }
-      __syncthreads();
-      const uint32_t jj = uni(s_t);
+      const uint32_t jj = wave_search_le(
+          nl, [&](uint32_t x) { return (uint64_t)x * TILE - a.pre[tile0 + x] <= r0; });
       const uint64_t jlo = (uint64_t)jj * TILE;
-      const uint64_t aj = jlo - a.pre[tile0 + jj];
+      const uint64_t aj = jlo - uni(a.pre[tile0 + jj]);
       if (aj != r0) {  // else the left tile's own item starts here
-        const uint32_t jl = (uint32_t)(F - jlo < (uint64_t)TILE ? F - jlo : (uint64_t)TILE);
-        item[2] = select_side<KT, BLOCK, IPT>(a.keys, start + jlo, jl, (uint32_t)(r0 - aj), false,
-                                              bit, f, s_w, &s_pos);
+        const uint32_t jcnt = (uint32_t)(len - jlo < (uint64_t)TILE ? len - jlo : (uint64_t)TILE);
+        item[2] = wave_select<KT, WAVES, IPT>(a.keys, start + jlo, jcnt,
+                                              &a.sub[(uint64_t)(tile0 + jj) * WAVES],
+                                              (uint32_t)(r0 - aj), false, bit, f);
         item[3] = start + lo + (lf - 1);
       }
     }
-    if (tid == 0) {
+    if (lane == 0) {
       uint64_t *o = &a.items[4ull * t];
       o[0] = item[0];
       o[1] = item[1];
       o[2] = item[2];
       o[3] = item[3];
     }
-    __syncthreads();
   }
 }
 

@@ -222,7 +222,8 @@ def test_inplace_validation_and_scratch():
     for kb in (1, 2, 4, 8):
         n = 1 << 26
         need = sb(kb, n, 1, 0)
-        assert 0 < need < n * kb // 8, (kb, need)
+        # per-tile words only: under a quarter of 1-byte keys, 1/16 of 4- and 8-byte keys
+        assert 0 < need < n * kb // (4 if kb == 1 else 8 if kb == 2 else 16), (kb, need)
         # far below what the stable path asks for
         assert need * 8 < _lib.bsort_scratch_bytes(kb, n, 1, 0, 0)
     assert sb(3, 100, 1, 0) == 0                                  # width
