@@ -216,6 +216,20 @@ int bsort_gather(const void *values, int value_bytes, const void *indices,
                  const int64_t *offsets, uint64_t num_segments, uint64_t n, uint32_t flags,
                  void *out, void *stream);
 
+/*
+ * The inverse: the backward of a segmented sort (its gradient flows from the
+ * sorted order back to each key's input position) or of bsort_gather:
+ *   out[base(j) + indices[j]] = values[j]     for j < n,
+ * base(j) as above.  For row-shaped sorts bsort_backward_scatter is the
+ * faster form; this one takes any segments (ragged rows, the batched sort).
+ * Arguments and validation as for bsort_gather; targets outside their
+ * segment are skipped (their output keeps the caller's bits), and indices
+ * must be a permutation within each segment for every target to be written.
+ */
+int bsort_scatter(const void *values, int value_bytes, const void *indices,
+                  const int64_t *offsets, uint64_t num_segments, uint64_t n, uint32_t flags,
+                  void *out, void *stream);
+
 /* ---- keys whose order bits are stored in another layout ----
  *
  * Section III-C notes that other bit arrangements (a sign that is not the

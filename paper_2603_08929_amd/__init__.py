@@ -11,7 +11,7 @@ as HIP kernels for gfx950 behind a C ABI (include/bsort.h).
 """
 from ._lib import (DESCENDING, IDX64, NO_FINISH, NO_SKIP, PLAIN, KEY_F, KEY_I,  # noqa: F401
                    KEY_U, lib, strerror)
-from .api import (argsort, backward_scatter, device_status, gather, scratch_bytes,  # noqa: F401
+from .api import (argsort, backward_scatter, device_status, gather, scatter, scratch_bytes,  # noqa: F401
                   segmented_sort_, sort, sort128_, sort_, sort_inplace_, sort_layout_,
                   sort_pairs_,
                   key_type)

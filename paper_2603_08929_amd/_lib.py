@@ -39,7 +39,8 @@ SYMBOLS = ["bsort_scratch_bytes", "bsort_sort", "bsort_segmented", "bsort_segmen
            "bsort_graph_launch", "bsort_graph_destroy", "bsort_pairs_scratch_bytes",
            "bsort_sort_pairs", "bsort_segmented_pairs", "bsort_gather",
            "bsort_scratch_bytes128", "bsort_sort128", "bsort_sort_layout",
-           "bsort_inplace_scratch_bytes", "bsort_sort_inplace", "bsort_segmented_inplace"] + \
+           "bsort_inplace_scratch_bytes", "bsort_sort_inplace", "bsort_segmented_inplace",
+           "bsort_scatter"] + \
     [f"bsort_{t}" for t in TYPED]
 
 lib.bsort_scratch_bytes.argtypes = [_i, _u64, _u64, _i, _u32]
@@ -67,6 +68,8 @@ lib.bsort_segmented_pairs.argtypes = [_vp, _i, _i, _vp, _u64, _u64, _u32, _vp, _
 lib.bsort_segmented_pairs.restype = _i
 lib.bsort_gather.argtypes = [_vp, _i, _vp, _vp, _u64, _u64, _u32, _vp, _vp]
 lib.bsort_gather.restype = _i
+lib.bsort_scatter.argtypes = [_vp, _i, _vp, _vp, _u64, _u64, _u32, _vp, _vp]
+lib.bsort_scatter.restype = _i
 lib.bsort_scratch_bytes128.argtypes = [_u64, _i, _u32]
 lib.bsort_scratch_bytes128.restype = _sz
 lib.bsort_sort128.argtypes = [_vp, _i, _u64, _u32, _vp, _vp, _sz, _vp]
@@ -148,6 +151,7 @@ bsort_pairs_scratch_bytes = lib.bsort_pairs_scratch_bytes
 bsort_sort_pairs = lib.bsort_sort_pairs
 bsort_segmented_pairs = lib.bsort_segmented_pairs
 bsort_gather = lib.bsort_gather
+bsort_scatter = lib.bsort_scatter
 bsort_scratch_bytes128 = lib.bsort_scratch_bytes128
 bsort_sort128 = lib.bsort_sort128
 bsort_sort_layout = lib.bsort_sort_layout

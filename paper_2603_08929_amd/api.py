@@ -211,6 +211,30 @@ def gather(values: torch.Tensor, indices: torch.Tensor,
     return out
 
 
+def scatter(values: torch.Tensor, indices: torch.Tensor,
+            offsets: Optional[torch.Tensor] = None, zero_fill: bool = True) -> torch.Tensor:
+    """out[base(j) + indices[j]] = values[j] -- the inverse of gather: the
+    backward of a (segmented) sort, ragged segments included.  zero_fill=False
+    leaves the output uninitialised, for indices that are permutations."""
+    n = indices.numel()
+    vb = _value_bytes(values, n)
+    if not indices.is_cuda or indices.dim() != 1 or not indices.is_contiguous():
+        raise ValueError("bsort.scatter: indices must be a contiguous 1-D GPU tensor")
+    if indices.dtype == torch.int64:
+        fl = IDX64
+    elif indices.dtype == torch.int32:
+        fl = 0
+    else:
+        raise TypeError("indices must be int32 (uint32 payload) or int64")
+    B, off = _segment_args(indices, offsets)
+    out = torch.zeros_like(values) if zero_fill else torch.empty_like(values)
+    rc = _lib.bsort_scatter(values.data_ptr(), vb, indices.data_ptr(), off,
+                            B if offsets is not None else 0, n, fl, out.data_ptr(),
+                            _stream(values.device))
+    _lib.check(rc, "bsort_scatter")
+    return out
+
+
 def sort128_(keys: torch.Tensor, family: str = "u", descending: bool = False,
              return_indices: bool = True, idx64: bool = False, flags: int = 0
              ) -> Optional[torch.Tensor]:

@@ -533,18 +533,18 @@ bool value_args_ok(const void *p, int value_bytes) {
 
 int launch_gather(const void *values, int value_bytes, const void *indices, bool i64,
                   const int64_t *offsets, uint64_t B, uint64_t n, void *out, int cus,
-                  hipStream_t st) {
+                  hipStream_t st, bool scatter = false) {
   const uint32_t grid = clamp_grid((n + GCH - 1) / GCH, (uint64_t)cus * 8);
+#define BG_ONE(VT, I, S)                                                                    \
+  hipLaunchKernelGGL((gather_kernel<VT, I, S>), dim3(grid), dim3(256), 0, st,               \
+                     static_cast<const VT *>(values), indices, offsets, B, n,               \
+                     static_cast<VT *>(out))
 #define BG_LAUNCH(VT)                                                                       \
   do {                                                                                      \
-    if (i64)                                                                                \
-      hipLaunchKernelGGL((gather_kernel<VT, true>), dim3(grid), dim3(256), 0, st,           \
-                         static_cast<const VT *>(values), indices, offsets, B, n,           \
-                         static_cast<VT *>(out));                                           \
-    else                                                                                    \
-      hipLaunchKernelGGL((gather_kernel<VT, false>), dim3(grid), dim3(256), 0, st,          \
-                         static_cast<const VT *>(values), indices, offsets, B, n,           \
-                         static_cast<VT *>(out));                                           \
+    if (i64 && scatter) BG_ONE(VT, true, true);                                             \
+    else if (i64) BG_ONE(VT, true, false);                                                  \
+    else if (scatter) BG_ONE(VT, false, true);                                              \
+    else BG_ONE(VT, false, false);                                                          \
   } while (0)
   switch (value_bytes) {
     case 1: BG_LAUNCH(uint8_t); break;
@@ -554,6 +554,7 @@ int launch_gather(const void *values, int value_bytes, const void *indices, bool
     default: BG_LAUNCH(uint4); break;
   }
 #undef BG_LAUNCH
+#undef BG_ONE
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
   return BSORT_OK;
@@ -1170,6 +1171,24 @@ int bsort_gather(const void *values, int value_bytes, const void *indices,
   if (rc != BSORT_OK) return rc;
   return launch_gather(values, value_bytes, indices, (flags & BSORT_IDX64) != 0, offsets,
                        offsets ? num_segments : 1, n, out, cus, static_cast<hipStream_t>(stream));
+}
+
+int bsort_scatter(const void *values, int value_bytes, const void *indices,
+                  const int64_t *offsets, uint64_t num_segments, uint64_t n, uint32_t flags,
+                  void *out, void *stream) {
+  if (flags & ~(uint32_t)BSORT_IDX64) return BSORT_EINVAL;
+  if (offsets && num_segments == 0 && n != 0) return BSORT_EINVAL;
+  if (n == 0) return BSORT_OK;
+  if (!values || !indices || !out) return BSORT_EINVAL;
+  if (!value_args_ok(values, value_bytes) || !value_args_ok(out, value_bytes))
+    return BSORT_EINVAL;
+  if (n >= (1ull << 32)) return BSORT_ETOOBIG;
+  int cus = 0;
+  const int rc = device_check(&cus);
+  if (rc != BSORT_OK) return rc;
+  return launch_gather(values, value_bytes, indices, (flags & BSORT_IDX64) != 0, offsets,
+                       offsets ? num_segments : 1, n, out, cus, static_cast<hipStream_t>(stream),
+                       true);
 }
 
 size_t bsort_inplace_scratch_bytes(int key_bytes, uint64_t n, uint64_t num_segments,

@@ -2001,8 +2001,11 @@ __device__ __forceinline__ uint64_t segment_of(const int64_t *offsets, uint64_t 
 // of GCH positions; thread 0 finds the segments of the chunk's first and
 // last position, and each position searches only between them.  A source
 // outside its segment (indices that are not a permutation) is skipped.
+// With SCATTER the same pairs move the other way, out[base + idx[j]] =
+// values[j]: the inverse permutation, which is the backward of a segmented
+// sort or of the gather (targets outside their segment are skipped).
 constexpr uint32_t GCH = 4096;
-template <typename VT, bool I64>
+template <typename VT, bool I64, bool SCATTER = false>
 __global__ __launch_bounds__(256) void gather_kernel(const VT *values, const void *indices,
                                                      const int64_t *offsets, uint64_t B,
                                                      uint64_t n, VT *out) {
@@ -2030,7 +2033,10 @@ __global__ __launch_bounds__(256) void gather_kernel(const VT *values, const voi
         len = (uint64_t)offsets[s + 1] - base;
       }
       const uint64_t src = base + ix;
-      if (ix < len && src < n) out[j] = values[src];
+      if (ix < len && src < n) {
+        if (SCATTER) out[src] = values[j];
+        else out[j] = values[src];
+      }
     }
   }
 }

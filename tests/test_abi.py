@@ -247,3 +247,15 @@ def test_inplace_validation_and_scratch():
     assert seg(fake, 0, 4, None, 3, 10, 0, fake, 1 << 30, None) == _lib.EINVAL
     assert seg(fake, 0, 4, fake, 0, 10, 0, fake, 1 << 30, None) == _lib.EINVAL
     assert seg(fake, 0, 4, fake, 0, 0, 0, fake, 1 << 30, None) == _lib.OK
+
+
+def test_scatter_validation():
+    fake = 1 << 40
+    f = _lib.bsort_scatter
+    assert f(None, 4, None, None, 0, 0, 0, None, None) == _lib.OK                 # n = 0
+    assert f(fake, 4, fake, None, 0, 10, 1 << 7, fake, None) == _lib.EINVAL       # flag
+    assert f(fake, 3, fake, None, 0, 10, 0, fake, None) == _lib.EINVAL            # width
+    assert f(fake + 2, 4, fake, None, 0, 10, 0, fake, None) == _lib.EINVAL        # alignment
+    assert f(None, 4, fake, None, 0, 10, 0, fake, None) == _lib.EINVAL            # null values
+    assert f(fake, 4, fake, fake, 0, 10, 0, fake, None) == _lib.EINVAL            # 0 segments
+    assert f(fake, 4, fake, None, 0, 1 << 32, 0, fake, None) == _lib.ETOOBIG

@@ -197,3 +197,67 @@ def test_python_sort_pairs():
     np.testing.assert_array_equal(from_device(keys, "i16"), rk)
     np.testing.assert_array_equal(idx.cpu().numpy().view(np.uint32).astype(np.int64), ri)
     np.testing.assert_array_equal(vals.cpu().numpy(), v0[ri])
+
+
+@pytest.mark.parametrize("vb", [1, 2, 4, 8, 16])
+def test_scatter_ragged_segments(vb):
+    """bsort_scatter over ragged segments against numpy's assignment
+    out[base + idx[j]] = values[j]; it undoes the gather; targets outside
+    their segment keep the caller's bits."""
+    rng = np.random.default_rng(60 + vb)
+    lengths = [0, 5, 1, 0, 3000, 7000, 2, 0, 9000, 1, 4096, 4097]
+    offs = np.concatenate([[0], np.cumsum(lengths)]).astype(np.int64)
+    n = int(offs[-1])
+    idx = np.concatenate([rng.permutation(m) for m in lengths]).astype(np.int64)
+    vals = random_values(n, vb, 61 + vb)
+    vn = vals.numpy()
+    base = np.repeat(offs[:-1], lengths)
+    want = np.zeros_like(vn)
+    want[base + idx] = vn
+    offsets = torch.from_numpy(offs).cuda()
+    for i64 in (False, True):
+        ind = torch.from_numpy(idx if i64 else idx.astype(np.int32)).cuda()
+        out = api.scatter(vals.cuda(), ind, offsets)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(out.cpu().numpy(), want)
+        # inverse of the gather
+        back = api.scatter(api.gather(vals.cuda(), ind, offsets), ind, offsets)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(back.cpu().numpy(), vn)
+    # skipped targets: index == segment length, and far outside
+    bad = idx.copy()
+    bad[offs[4] + 10] = lengths[4]
+    bad[offs[8]] = lengths[8] + 123
+    ok = np.ones(n, dtype=bool)
+    ok[[offs[4] + 10, offs[8]]] = False
+    fill = torch.full_like(vals, 7)
+    out = fill.cuda()
+    ind = torch.from_numpy(bad.astype(np.int32)).cuda()
+    vd = vals.cuda()
+    rc = _lib.bsort_scatter(vd.data_ptr(), vb, ind.data_ptr(), offsets.data_ptr(), len(lengths),
+                            n, 0, out.data_ptr(), stream())
+    _lib.check(rc, "bsort_scatter")
+    torch.cuda.synchronize()
+    exp = fill.numpy().copy()
+    exp[(base + bad)[ok]] = vn[ok]
+    np.testing.assert_array_equal(out.cpu().numpy(), exp)
+
+
+def test_scatter_is_the_segmented_sort_backward():
+    """Gradient of sum(W * sorted) through a segmented sort of ragged rows:
+    W scattered back to each key's input position (numpy's autograd-free
+    reference: grad[base + idx[j]] = W[j])."""
+    rng = np.random.default_rng(62)
+    lengths = [1, 17, 0, 5000, 8193, 3]
+    name = "f32"
+    n = int(sum(lengths))
+    bits = W.normal_bits(name, n, 63)
+    k, i, offs = gpu_segmented(name, bits, lengths, idx="i64")
+    w = rng.standard_normal(n).astype(np.float32)
+    g = api.scatter(torch.from_numpy(w).cuda(), torch.from_numpy(i).cuda(),
+                    torch.from_numpy(offs).cuda())
+    torch.cuda.synchronize()
+    base = np.repeat(offs[:-1], lengths)
+    want = np.zeros(n, dtype=np.float32)
+    want[base + i] = w
+    np.testing.assert_array_equal(g.cpu().numpy(), want)
