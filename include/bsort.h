@@ -299,6 +299,16 @@ int bsort_autotune(void *keys, int key_type, int key_bytes, const int64_t *offse
                    void *scratch, size_t scratch_bytes, void *stream, int reps);
 /* Forget every tuned choice. */
 void bsort_autotune_reset(void);
+/* A tuning cache, so that a later process need not tune again.  save writes
+ * every choice of this process to a text file, one line per device type
+ * (architecture name and CU count), key width, index mode and size class.
+ * load reads such a file and applies its entries to every visible GPU of
+ * the same type; the whole file is checked first, and a malformed one
+ * changes nothing.  Both return BSORT_OK, BSORT_EINVAL (path unreadable or
+ * unwritable, malformed file) or BSORT_EHIP; neither is thread-safe with
+ * bsort_autotune. */
+int bsort_autotune_save(const char *path);
+int bsort_autotune_load(const char *path);
 
 /* ---- HIP graphs ----
  * For callers that sort buffers of the same shape again and again (batched

@@ -40,7 +40,7 @@ SYMBOLS = ["bsort_scratch_bytes", "bsort_sort", "bsort_segmented", "bsort_segmen
            "bsort_sort_pairs", "bsort_segmented_pairs", "bsort_gather",
            "bsort_scratch_bytes128", "bsort_sort128", "bsort_sort_layout",
            "bsort_inplace_scratch_bytes", "bsort_sort_inplace", "bsort_segmented_inplace",
-           "bsort_scatter"] + \
+           "bsort_scatter", "bsort_autotune_save", "bsort_autotune_load"] + \
     [f"bsort_{t}" for t in TYPED]
 
 lib.bsort_scratch_bytes.argtypes = [_i, _u64, _u64, _i, _u32]
@@ -70,6 +70,10 @@ lib.bsort_gather.argtypes = [_vp, _i, _vp, _vp, _u64, _u64, _u32, _vp, _vp]
 lib.bsort_gather.restype = _i
 lib.bsort_scatter.argtypes = [_vp, _i, _vp, _vp, _u64, _u64, _u32, _vp, _vp]
 lib.bsort_scatter.restype = _i
+lib.bsort_autotune_save.argtypes = [ctypes.c_char_p]
+lib.bsort_autotune_save.restype = _i
+lib.bsort_autotune_load.argtypes = [ctypes.c_char_p]
+lib.bsort_autotune_load.restype = _i
 lib.bsort_scratch_bytes128.argtypes = [_u64, _i, _u32]
 lib.bsort_scratch_bytes128.restype = _sz
 lib.bsort_sort128.argtypes = [_vp, _i, _u64, _u32, _vp, _vp, _sz, _vp]
@@ -152,6 +156,8 @@ bsort_sort_pairs = lib.bsort_sort_pairs
 bsort_segmented_pairs = lib.bsort_segmented_pairs
 bsort_gather = lib.bsort_gather
 bsort_scatter = lib.bsort_scatter
+bsort_autotune_save = lib.bsort_autotune_save
+bsort_autotune_load = lib.bsort_autotune_load
 bsort_scratch_bytes128 = lib.bsort_scratch_bytes128
 bsort_sort128 = lib.bsort_sort128
 bsort_sort_layout = lib.bsort_sort_layout

@@ -1303,6 +1303,90 @@ int bsort_tuned_config(int key_bytes, int with_indices, uint64_t n, uint64_t num
 
 void bsort_autotune_reset(void) { memset(g_tuned, 0, sizeof g_tuned); }
 
+// Tuning cache: a text file, "bsort-autotune 1" and then one line per
+// choice, "<arch> <CUs> <key bytes> <with indices> <size class> <config>".
+// Entries name the device type rather than its index, so a file made on
+// one machine applies to every GPU of the same type.
+int bsort_autotune_save(const char *path) {
+  if (!path) return BSORT_EINVAL;
+  FILE *fp = fopen(path, "w");
+  if (!fp) return BSORT_EINVAL;
+  int rc = fprintf(fp, "bsort-autotune 1\n") > 0 ? BSORT_OK : BSORT_EINVAL;
+  static const int kbs[4] = {1, 2, 4, 8};
+  for (int dev = 0; dev < 64 && rc == BSORT_OK; ++dev) {
+    bool any = false;
+    for (int k = 0; k < 4 && !any; ++k)
+      for (int x = 0; x < 2 && !any; ++x)
+        for (int c = 0; c < 48 && !any; ++c) any = g_tuned[dev][k][x][c] > 0;
+    if (!any) continue;
+    hipDeviceProp_t p;
+    const hipError_t e = hipGetDeviceProperties(&p, dev);
+    if (e != hipSuccess) {
+      rc = hip_fail(e, "hipGetDeviceProperties");
+      break;
+    }
+    char arch[64];
+    snprintf(arch, sizeof arch, "%s", p.gcnArchName);
+    for (char *q = arch; *q; ++q)
+      if (*q == ' ') *q = '_';
+    for (int k = 0; k < 4 && rc == BSORT_OK; ++k)
+      for (int x = 0; x < 2 && rc == BSORT_OK; ++x)
+        for (int c = 0; c < 48 && rc == BSORT_OK; ++c)
+          if (g_tuned[dev][k][x][c] > 0 &&
+              fprintf(fp, "%s %d %d %d %d %d\n", arch, p.multiProcessorCount, kbs[k], x, c,
+                      g_tuned[dev][k][x][c] - 1) <= 0)
+            rc = BSORT_EINVAL;
+  }
+  if (fclose(fp) != 0 && rc == BSORT_OK) rc = BSORT_EINVAL;
+  return rc;
+}
+
+int bsort_autotune_load(const char *path) {
+  if (!path) return BSORT_EINVAL;
+  FILE *fp = fopen(path, "r");
+  if (!fp) return BSORT_EINVAL;
+  struct Entry {
+    char arch[64];
+    int cus, kb, idx, cls, cfg;
+  };
+  static Entry entries[64 * 4 * 2 * 48];
+  int ne = 0, rc = BSORT_OK;
+  char line[256];
+  if (!fgets(line, sizeof line, fp) || strcmp(line, "bsort-autotune 1\n") != 0) rc = BSORT_EINVAL;
+  while (rc == BSORT_OK && fgets(line, sizeof line, fp)) {
+    Entry en;
+    char tail;
+    if (ne >= (int)(sizeof entries / sizeof entries[0]) ||
+        sscanf(line, "%63s %d %d %d %d %d %c", en.arch, &en.cus, &en.kb, &en.idx, &en.cls,
+               &en.cfg, &tail) != 6 ||
+        (en.kb != 1 && en.kb != 2 && en.kb != 4 && en.kb != 8) || en.idx < 0 || en.idx > 1 ||
+        en.cls < 0 || en.cls >= 48 || en.cfg < 0 || en.cfg >= N_CONFIGS || en.cus <= 0) {
+      rc = BSORT_EINVAL;
+      break;
+    }
+    entries[ne++] = en;
+  }
+  fclose(fp);
+  if (rc != BSORT_OK || ne == 0) return rc;  // a malformed file changes nothing
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
+  for (int dev = 0; dev < ndev && dev < 64; ++dev) {
+    hipDeviceProp_t p;
+    e = hipGetDeviceProperties(&p, dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+    char arch[64];
+    snprintf(arch, sizeof arch, "%s", p.gcnArchName);
+    for (char *q = arch; *q; ++q)
+      if (*q == ' ') *q = '_';
+    for (int i = 0; i < ne; ++i)
+      if (strcmp(entries[i].arch, arch) == 0 && entries[i].cus == p.multiProcessorCount)
+        g_tuned[dev][kb_slot(entries[i].kb)][entries[i].idx][entries[i].cls] =
+            (signed char)(entries[i].cfg + 1);
+  }
+  return BSORT_OK;
+}
+
 int bsort_autotune(void *keys, int key_type, int key_bytes, const int64_t *offsets,
                    uint64_t num_segments, uint64_t n, uint32_t flags, void *indices,
                    void *scratch, size_t scratch_bytes, void *stream, int reps) {

@@ -259,3 +259,26 @@ def test_scatter_validation():
     assert f(None, 4, fake, None, 0, 10, 0, fake, None) == _lib.EINVAL            # null values
     assert f(fake, 4, fake, fake, 0, 10, 0, fake, None) == _lib.EINVAL            # 0 segments
     assert f(fake, 4, fake, None, 0, 1 << 32, 0, fake, None) == _lib.ETOOBIG
+
+
+def test_autotune_cache_files(tmp_path):
+    """Without tuned choices the cache is just its header, and loads back
+    without touching a device; unreadable or malformed files are refused
+    and change nothing."""
+    _lib.bsort_autotune_reset()
+    path = tmp_path / "t.txt"
+    assert _lib.bsort_autotune_save(str(path).encode()) == _lib.OK
+    assert path.read_text() == "bsort-autotune 1\n"
+    assert _lib.bsort_autotune_load(str(path).encode()) == _lib.OK
+    assert _lib.bsort_autotune_load(str(tmp_path / "missing.txt").encode()) == _lib.EINVAL
+    assert _lib.bsort_autotune_save(str(tmp_path / "no" / "dir.txt").encode()) == _lib.EINVAL
+    assert _lib.bsort_autotune_load(None) == _lib.EINVAL
+    for text in ("bsort-autotune 2\n", "bsort-autotune 1\ngfx950 256 3 0 10 1\n",
+                 "bsort-autotune 1\ngfx950 256 4 2 10 1\n",
+                 "bsort-autotune 1\ngfx950 256 4 0 48 1\n",
+                 "bsort-autotune 1\ngfx950 256 4 0 10 99\n",
+                 "bsort-autotune 1\ngfx950 256 4 0 10 1 extra\n",
+                 "bsort-autotune 1\ngfx950 256 4 0\n"):
+        bad = tmp_path / "bad.txt"
+        bad.write_text(text)
+        assert _lib.bsort_autotune_load(str(bad).encode()) == _lib.EINVAL, text

@@ -106,6 +106,43 @@ def test_autotune_segmented():
         _lib.bsort_autotune_reset()
 
 
+def test_autotune_cache_round_trip(tmp_path):
+    """A tuned choice survives save, reset and load; a hand-written file for
+    this device type sets a choice; a file for another type changes
+    nothing."""
+    _lib.bsort_autotune_reset()
+    try:
+        name, n = "u32", 1 << 18
+        bits = W.uniform_bits(name, n, 26)
+        keys = to_device(bits, name)
+        ind = torch.empty(n, dtype=torch.int32, device="cuda")
+        best = api.autotune(keys, indices=ind, reps=1)
+        path = str(tmp_path / "tune.txt")
+        assert _lib.bsort_autotune_save(path.encode()) == _lib.OK
+        _lib.bsort_autotune_reset()
+        assert _lib.bsort_tuned_config(4, 1, n, 1) == 0
+        assert _lib.bsort_autotune_load(path.encode()) == _lib.OK
+        assert _lib.bsort_tuned_config(4, 1, n, 1) == best
+        # hand-written entries: this device type, and another one
+        props = torch.cuda.get_device_properties(0)
+        arch = props.gcnArchName.replace(" ", "_")
+        cls = n.bit_length() - 1
+        other = tmp_path / "other.txt"
+        other.write_text(f"bsort-autotune 1\ngfx000 7 4 0 {cls} 9\n")
+        _lib.bsort_autotune_reset()
+        assert _lib.bsort_autotune_load(str(other).encode()) == _lib.OK
+        assert _lib.bsort_tuned_config(4, 0, n, 1) == 0
+        mine = tmp_path / "mine.txt"
+        mine.write_text(f"bsort-autotune 1\n{arch} {props.multi_processor_count} 4 0 {cls} 9\n")
+        assert _lib.bsort_autotune_load(str(mine).encode()) == _lib.OK
+        assert _lib.bsort_tuned_config(4, 0, n, 1) == 9
+        # and a sort with the loaded configuration still agrees with the oracle
+        k, i = gpu_sort(name, bits, idx=None)
+        np.testing.assert_array_equal(k, oracle_sort(name, bits)[0])
+    finally:
+        _lib.bsort_autotune_reset()
+
+
 def _graph_replays(make_eager, graph, keys, pristine, reps=3):
     """Replays the graph several times, with eager work and synchronisation
     between the replays, and compares every replay with the eager result."""
