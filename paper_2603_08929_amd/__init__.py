@@ -2,7 +2,7 @@
 as HIP kernels for gfx950 behind a C ABI (include/bsort.h).
 
     import paper_2603_08929_amd as bsort
-    values, indices = bsort.sort(x)               # 1-D, stable
+    values, indices = bsort.sort(x, dim=-1)       # like torch.sort(..., stable=True)
     idx = bsort.sort_(x, descending=True)         # in place
     idx = bsort.segmented_sort_(x, offsets)       # many arrays, one pass
     idx = bsort.argsort(x)                        # keys left unchanged

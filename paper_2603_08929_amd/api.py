@@ -68,12 +68,27 @@ def sort_(keys: torch.Tensor, descending: bool = False, return_indices: bool = T
     return idx
 
 
-def sort(x: torch.Tensor, descending: bool = False, idx64: bool = True, flags: int = 0
-         ) -> Tuple[torch.Tensor, torch.Tensor]:
-    """torch.sort-like on a 1-D tensor: (values, indices), stable."""
-    v = x.contiguous().clone()
-    idx = sort_(v, descending=descending, return_indices=True, idx64=idx64, flags=flags)
-    return v, idx
+def sort(x: torch.Tensor, dim: int = -1, descending: bool = False, idx64: bool = True,
+         flags: int = 0) -> Tuple[torch.Tensor, torch.Tensor]:
+    """Like torch.sort(x, dim, descending, stable=True): (values, indices),
+    x left unchanged.  Every slice along dim is one segment of a single
+    segmented call.  Indices are int64 (torch's dtype), or uint32 in int32
+    storage with idx64=False.  For gradients use sort_along."""
+    if x.dim() == 0:
+        raise ValueError("bsort.sort: need at least one dimension")
+    if x.dim() == 1:
+        v = x.contiguous().clone()
+        idx = sort_(v, descending=descending, return_indices=True, idx64=idx64, flags=flags)
+        return v, idx
+    d = dim % x.dim()
+    xm = x.movedim(d, -1).contiguous()
+    cols = xm.shape[-1]
+    rows = xm.numel() // cols if cols else 0
+    v = xm.clone().reshape(-1)
+    offsets = torch.arange(rows + 1, device=x.device, dtype=torch.int64) * cols
+    idx = segmented_sort_(v, offsets, descending=descending, return_indices=True, idx64=idx64,
+                          flags=flags)
+    return v.reshape(xm.shape).movedim(-1, d), idx.reshape(xm.shape).movedim(-1, d)
 
 
 def segmented_sort_(keys: torch.Tensor, offsets: torch.Tensor, descending: bool = False,
