@@ -875,7 +875,7 @@ int launch_inplace(KT *keys, uint64_t n, const int64_t *offsets, uint64_t B, int
   auto lk = ip_locate_kernel<KT, LS::LB, LS::LIPT>;
   auto sk = ip_swap_kernel<KT, LS::LB, LS::LIPT>;
   static const int occ_c = occupancy(ck, LS::LB), occ_s = occupancy(sk, LS::LB);
-  const uint32_t cgrid = clamp_grid(L.tmax, (uint64_t)cus * occ_c);
+  const uint32_t cgrid = clamp_grid((L.tmax + 1) / 2, (uint64_t)cus * occ_c);  // two tiles a block
   const uint32_t sgrid = clamp_grid(2 * L.tmax, (uint64_t)cus * occ_s);
   const uint32_t xgrid = clamp_grid((L.tmax + 3) / 4, cap);
   const uint32_t pgrid = clamp_grid((L.smax + 255) / 256, cap);

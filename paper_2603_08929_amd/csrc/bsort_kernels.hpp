@@ -1623,14 +1623,20 @@ __device__ uint64_t wave_select(const KT *keys, uint64_t base, uint32_t cnt, con
   return LOC_NONE;
 }
 
+// Each half of the block takes its own tile (so two tiles' searches and
+// loads are in flight per block); a wave reads two of the tile's chunks,
+// 2 * IPT keys per lane.  The outputs are per tile and per chunk as if one
+// wave had read each chunk.
 template <typename KT, int BLOCK, int IPT>
 __global__ __launch_bounds__(BLOCK) void ip_count_kernel(InplaceArgs<KT> a) {
-  constexpr int WAVES = BLOCK / 64;
+  constexpr int WAVES = BLOCK / 64;  // chunks per tile
+  constexpr int HW = WAVES / 2;      // waves per half-block
   constexpr uint32_t TILE = BLOCK * IPT, SUB = 64 * IPT;
-  __shared__ Seg s_seg;
-  __shared__ uint32_t s_c[WAVES], s_fb[WAVES], s_lf[WAVES];
-  __shared__ uint64_t s_acc[WAVES][4];
+  __shared__ Seg s_seg[2];
+  __shared__ uint32_t s_c[2][WAVES], s_fb[2][HW], s_lf[2][HW];
+  __shared__ uint64_t s_acc[2][HW][4];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int h = wave / HW, hw = wave % HW;
   if (blockIdx.x == 0 && tid == 0) {
     // the previous step's finish lists have been consumed
     a.hdr->n_finish = 0;
@@ -1640,33 +1646,49 @@ __global__ __launch_bounds__(BLOCK) void ip_count_kernel(InplaceArgs<KT> a) {
   }
   const uint64_t pk = a.hdr->packed[a.level];
   const uint32_t S = (uint32_t)(pk >> 32), ntiles = (uint32_t)pk;
-  for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    if (wave == 0) {
+  for (uint32_t t0 = 2 * blockIdx.x; t0 < ntiles; t0 += 2 * gridDim.x) {
+    const uint32_t t = t0 + (uint32_t)h;
+    const bool valid = t < ntiles;
+    if (hw == 0 && valid) {
       const uint32_t q = wave_search_le(S, [&](uint32_t i) { return a.live[i].tile0 <= t; });
       if (lane == 0) {
-        s_seg = a.live[q];
-        a.tiles[t] = s_seg;
+        s_seg[h] = a.live[q];
+        a.tiles[t] = s_seg[h];
       }
     }
     __syncthreads();
-    const uint64_t start = uni(s_seg.start), len = uni(s_seg.len);
-    const uint32_t meta = uni(s_seg.meta), tile0 = uni(s_seg.tile0);
-    const uint32_t cbase = uni(s_seg.cbase), slot = uni(s_seg.slot);
+    uint64_t start = 0, len = 0;
+    uint32_t meta = 0, tile0 = t, cbase = 0, slot = 0;
+    if (valid) {
+      start = s_seg[h].start;
+      len = s_seg[h].len;
+      meta = s_seg[h].meta;
+      tile0 = s_seg[h].tile0;
+      cbase = s_seg[h].cbase;
+      slot = s_seg[h].slot;
+    }
     const uint32_t j = t - tile0;
     const int bit = (int)(meta & BIT_MASK);
     const uint64_t f = (uint64_t)flip_of(bit, a.w, a.mode, a.desc, (meta & META_SIGN) ? 1 : 0);
     const uint64_t lo = (uint64_t)j * TILE;
-    const uint32_t cnt = (uint32_t)(len - lo < (uint64_t)TILE ? len - lo : (uint64_t)TILE);
+    const uint32_t cnt =
+        valid ? (uint32_t)(len - lo < (uint64_t)TILE ? len - lo : (uint64_t)TILE) : 0u;
     const rsrc_t kr = make_rsrc(a.keys + start + lo, cnt * (uint32_t)sizeof(KT));
-    uint32_t c = 0, fb = ~0u, lf = 0;
+    KT key[2 * IPT];
+#pragma unroll
+    for (int i = 0; i < 2 * IPT; ++i) {
+      const uint32_t q = (uint32_t)((2 * hw + i / IPT) * SUB + (i % IPT) * 64 + lane);
+      key[i] = buf_load<KT>(kr, q * (uint32_t)sizeof(KT));
+    }
+    uint32_t c[2] = {0, 0}, fb = ~0u, lf = 0;
     uint64_t and_f = ~0ull, or_f = 0, and_b = ~0ull, or_b = 0;
 #pragma unroll
-    for (int i = 0; i < IPT; ++i) {
-      const uint32_t q = (uint32_t)(wave * SUB + i * 64 + lane);
-      const uint64_t k = (uint64_t)buf_load<KT>(kr, q * (uint32_t)sizeof(KT));
+    for (int i = 0; i < 2 * IPT; ++i) {
+      const uint32_t q = (uint32_t)((2 * hw + i / IPT) * SUB + (i % IPT) * 64 + lane);
+      const uint64_t k = (uint64_t)key[i];
       if (q < cnt) {
         if (((k >> bit) & 1ull) == f) {
-          ++c;
+          ++c[i / IPT];
           and_f &= k;
           or_f |= k;
           lf = q + 1;
@@ -1677,7 +1699,8 @@ __global__ __launch_bounds__(BLOCK) void ip_count_kernel(InplaceArgs<KT> a) {
         }
       }
     }
-    c = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan_dpp(c), 63);
+    c[0] = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan_dpp(c[0]), 63);
+    c[1] = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan_dpp(c[1]), 63);
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) {
       const uint32_t ofb = (uint32_t)__shfl_xor((int)fb, d), olf = (uint32_t)__shfl_xor((int)lf, d);
@@ -1689,27 +1712,30 @@ __global__ __launch_bounds__(BLOCK) void ip_count_kernel(InplaceArgs<KT> a) {
     and_b = wave_and_dpp(and_b);
     or_b = wave_or_dpp(or_b);
     if (lane == 0) {
-      s_c[wave] = c;
-      s_fb[wave] = fb;
-      s_lf[wave] = lf;
-      s_acc[wave][0] = and_f;
-      s_acc[wave][1] = or_f;
-      s_acc[wave][2] = and_b;
-      s_acc[wave][3] = or_b;
+      s_c[h][2 * hw] = c[0];
+      s_c[h][2 * hw + 1] = c[1];
+      s_fb[h][hw] = fb;
+      s_lf[h][hw] = lf;
+      s_acc[h][hw][0] = and_f;
+      s_acc[h][hw][1] = or_f;
+      s_acc[h][hw][2] = and_b;
+      s_acc[h][hw][3] = or_b;
     }
     __syncthreads();
-    if (tid == 0) {
+    const int ht = tid - h * (BLOCK / 2);  // thread index within the half
+    if (valid && ht == 0) {
       uint32_t sum = 0, tfb = ~0u, tlf = 0;
       uint64_t af = ~0ull, of = 0, ab = ~0ull, ob = 0;
 #pragma unroll
-      for (int q = 0; q < WAVES; ++q) {
-        sum += s_c[q];
-        tfb = tfb < s_fb[q] ? tfb : s_fb[q];
-        tlf = tlf > s_lf[q] ? tlf : s_lf[q];
-        af &= s_acc[q][0];
-        of |= s_acc[q][1];
-        ab &= s_acc[q][2];
-        ob |= s_acc[q][3];
+      for (int q = 0; q < WAVES; ++q) sum += s_c[h][q];
+#pragma unroll
+      for (int q = 0; q < HW; ++q) {
+        tfb = tfb < s_fb[h][q] ? tfb : s_fb[h][q];
+        tlf = tlf > s_lf[h][q] ? tlf : s_lf[h][q];
+        af &= s_acc[h][q][0];
+        of |= s_acc[h][q][1];
+        ab &= s_acc[h][q][2];
+        ob |= s_acc[h][q][3];
       }
       a.tcnt[cbase + j] = sum;
       a.ends[2ull * t] = tfb;
@@ -1726,7 +1752,7 @@ __global__ __launch_bounds__(BLOCK) void ip_count_kernel(InplaceArgs<KT> a) {
         atomic_or_u64(&z->or_hi, ob);
       }
     }
-    if (tid < WAVES) a.sub[(uint64_t)t * WAVES + tid] = s_c[tid];
+    if (valid && ht < WAVES) a.sub[(uint64_t)t * WAVES + ht] = s_c[h][ht];
     __syncthreads();
   }
 }
