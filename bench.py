@@ -637,6 +637,11 @@ def extras_backward(lib, torch, np, dev, stream):
 
 # --------------------------------------------------------------------- main
 
+EXTRAS_GROUPS = ("word_size_sweep", "batched_vs_per_array", "small_u32_64k",
+                 "differentiable_sort", "argsort_and_pairs", "keys_128_bit", "small_segments",
+                 "in_place")
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -644,6 +649,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--extras", default="all",
+                    help="comma-separated extras groups to run (default: all of them)")
     ap.add_argument("--cpu-sample", type=int, default=1 << 25,
                     help="keys per array in the oracle's timed sample")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
@@ -655,6 +662,12 @@ def main() -> int:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the sort of one "
                           "array is a single-GPU workload here (--gpus 1)"}))
         return 2
+    if args.extras != "all":
+        unknown = [g for g in args.extras.split(",") if g not in EXTRAS_GROUPS]
+        if unknown:
+            print(f"unknown extras group(s) {unknown}; known: {list(EXTRAS_GROUPS)}",
+                  file=sys.stderr)
+            return 2
 
     import numpy as np
     import torch
@@ -751,14 +764,17 @@ def main() -> int:
     if not args.no_extras:
         del pristine, idx, scratch
         torch.cuda.empty_cache()
-        extras = {"word_size_sweep": extras_word_size(_lib, torch, np, dev, stream),
-                  "batched_vs_per_array": extras_batched(_lib, torch, np, dev, stream),
-                  "small_u32_64k": extras_small(_lib, torch, np, dev, stream),
-                  "differentiable_sort": extras_backward(_lib, torch, np, dev, stream),
-                  "argsort_and_pairs": extras_pairs(_lib, torch, np, dev, stream),
-                  "keys_128_bit": extras_wide(_lib, torch, np, dev, stream),
-                  "small_segments": extras_small_segments(_lib, torch, np, dev, stream),
-                  "in_place": extras_inplace(_lib, torch, np, dev, stream)}
+        groups = {"word_size_sweep": extras_word_size,
+                  "batched_vs_per_array": extras_batched,
+                  "small_u32_64k": extras_small,
+                  "differentiable_sort": extras_backward,
+                  "argsort_and_pairs": extras_pairs,
+                  "keys_128_bit": extras_wide,
+                  "small_segments": extras_small_segments,
+                  "in_place": extras_inplace}
+        assert tuple(groups) == EXTRAS_GROUPS
+        want = list(groups) if args.extras == "all" else args.extras.split(",")
+        extras = {g: groups[g](_lib, torch, np, dev, stream) for g in want}
 
     cpu = None
     if not args.no_cpu_baseline:
