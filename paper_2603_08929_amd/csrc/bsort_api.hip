@@ -873,7 +873,10 @@ int launch_inplace(KT *keys, uint64_t n, const int64_t *offsets, uint64_t B, int
 
   auto ck = ip_count_kernel<KT, LS::LB, LS::LIPT>;
   auto lk = ip_locate_kernel<KT, LS::LB, LS::LIPT>;
-  auto sk = ip_swap_kernel<KT, LS::LB, LS::LIPT>;
+  // the coalesced swap for 2- and 4-byte keys, the blocked one for 1- and 8-byte keys
+  // (the faster of the two for each width)
+  auto sk = (sizeof(KT) == 2 || sizeof(KT) == 4) ? ip_swap_kernel<KT, LS::LB, LS::LIPT>
+                                                 : ip_swap_blocked_kernel<KT, LS::LB, LS::LIPT>;
   static const int occ_c = occupancy(ck, LS::LB), occ_s = occupancy(sk, LS::LB);
   const uint32_t cgrid = clamp_grid((L.tmax + 1) / 2, (uint64_t)cus * occ_c);  // two tiles a block
   const uint32_t sgrid = clamp_grid(2 * L.tmax, (uint64_t)cus * occ_s);

@@ -1838,8 +1838,99 @@ __global__ __launch_bounds__(256) void ip_locate_kernel(InplaceArgs<KT> a) {
   }
 }
 
+// Lists are built with coalesced loads: item position d = i * BLOCK + tid
+// (row i of IPT), so position order is (row, wave, lane).  A key's rank in
+// its list is the keys flagged in earlier (row, wave) slots -- one wave scan
+// over the IPT * WAVES slot counts -- plus the flagged lanes below it.
 template <typename KT, int BLOCK, int IPT>
 __global__ __launch_bounds__(BLOCK) void ip_swap_kernel(InplaceArgs<KT> a) {
+  constexpr int WAVES = BLOCK / 64;
+  constexpr int NS = IPT * WAVES;  // (row, wave) slots
+  static_assert(NS <= 64, "one wave scans the slot counts");
+  constexpr uint32_t TILE = BLOCK * IPT;
+  static_assert(TILE <= 65536, "list offsets are 16-bit");
+  __shared__ uint16_t s_a[TILE];  // back keys left of k: offsets from the item's left start
+  __shared__ uint16_t s_b[TILE];  // front keys right of k: offsets left of its right start
+  __shared__ uint32_t s_ca[NS], s_cb[NS];  // slot counts, then their exclusive prefixes
+  __shared__ uint32_t s_n[2];              // list lengths
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const uint32_t ntiles = (uint32_t)a.hdr->packed[a.level];
+  for (uint32_t u = blockIdx.x; u < 2 * ntiles; u += gridDim.x) {
+    const uint32_t t = u >> 1;
+    const uint64_t ls = uni(a.items[4ull * t + 2 * (u & 1)]);
+    const uint64_t rs = uni(a.items[4ull * t + 2 * (u & 1) + 1]);
+    if (ls == LOC_NONE || rs == LOC_NONE) continue;
+    const Seg sg = a.tiles[t];
+    const uint64_t start = uni(sg.start);
+    const uint64_t k = start + uni(a.split[uni(sg.slot)]);
+    if (ls >= k || rs < k) {
+      if (tid == 0) atomic_or_u32(&a.hdr->status, STATUS_BAD_COUNTS);
+      continue;
+    }
+    const int bit = (int)(uni(sg.meta) & BIT_MASK);
+    const uint64_t f =
+        (uint64_t)flip_of(bit, a.w, a.mode, a.desc, (uni(sg.meta) & META_SIGN) ? 1 : 0);
+    // left: [ls, end of ls's tile) below k; right: (start of rs's tile, rs] at or above k
+    const uint64_t lte = start + ((ls - start) / TILE + 1) * TILE;
+    const uint32_t ln = (uint32_t)((lte < k ? lte : k) - ls);
+    const uint64_t rtb = start + ((rs - start) / TILE) * TILE;
+    const uint32_t rn = (uint32_t)(rs + 1 - (rtb > k ? rtb : k));
+    const rsrc_t kl = make_rsrc(a.keys + ls, ln * (uint32_t)sizeof(KT));
+    // the right list runs leftwards from rs: offset d is at rs - d, so its
+    // range starts rn - 1 keys left of rs and is read back to front
+    const rsrc_t kr = make_rsrc(a.keys + (rs + 1 - rn), rn * (uint32_t)sizeof(KT));
+    uint32_t ba = 0, bb = 0, ra[IPT], rb[IPT];
+#pragma unroll
+    for (int i = 0; i < IPT; ++i) {
+      const uint32_t d = (uint32_t)(i * BLOCK + tid);
+      const uint64_t kA = (uint64_t)buf_load<KT>(kl, d * (uint32_t)sizeof(KT));
+      const uint64_t kB = (uint64_t)buf_load<KT>(kr, (rn - 1 - d) * (uint32_t)sizeof(KT));
+      const bool fa = d < ln && ((kA >> bit) & 1ull) != f;
+      const bool fb = d < rn && ((kB >> bit) & 1ull) == f;
+      const uint64_t ma = __ballot(fa), mb = __ballot(fb);
+      ra[i] = lanes_below(ma);
+      rb[i] = lanes_below(mb);
+      ba |= (uint32_t)fa << i;
+      bb |= (uint32_t)fb << i;
+      if (lane == 0) {
+        s_ca[i * WAVES + wave] = (uint32_t)__popcll(ma);
+        s_cb[i * WAVES + wave] = (uint32_t)__popcll(mb);
+      }
+    }
+    __syncthreads();
+    if (wave < 2) {
+      uint32_t *sc = wave ? s_cb : s_ca;
+      const uint32_t v = lane < NS ? sc[lane] : 0u;
+      const uint32_t inc = wave_incl_scan_dpp(v);
+      if (lane < NS) sc[lane] = inc - v;
+      if (lane == 63) s_n[wave] = inc;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < IPT; ++i) {
+      const uint16_t d = (uint16_t)(i * BLOCK + tid);
+      if ((ba >> i) & 1u) s_a[s_ca[i * WAVES + wave] + ra[i]] = d;
+      if ((bb >> i) & 1u) s_b[s_cb[i * WAVES + wave] + rb[i]] = d;
+    }
+    const uint32_t na = s_n[0], nb = s_n[1];
+    const uint32_t pairs = uni(na < nb ? na : nb);
+    __syncthreads();
+    for (uint32_t i = tid; i < pairs; i += BLOCK) {
+      const uint64_t pa = ls + s_a[i], pb = rs - s_b[i];
+      const KT ka = a.keys[pa], kb = a.keys[pb];
+      a.keys[pa] = kb;
+      a.keys[pb] = ka;
+    }
+    __syncthreads();
+  }
+}
+
+// The same exchange with each lane taking IPT consecutive positions and
+// block-wide scans for the ranks; faster than the coalesced form for 1- and
+// 8-byte keys on MI355X.
+template <typename KT, int BLOCK, int IPT>
+__global__ __launch_bounds__(BLOCK) void ip_swap_blocked_kernel(InplaceArgs<KT> a) {
   constexpr int WAVES = BLOCK / 64;
   constexpr uint32_t TILE = BLOCK * IPT;
   __shared__ uint32_t s_a[TILE];  // back keys left of k, from the item's left start
