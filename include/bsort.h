@@ -167,8 +167,9 @@ int bsort_backward_scatter(const void *grad_sorted, const void *indices, uint64_
  * is O(n / 2048 + num_segments) words, a few percent of the keys.  Equal
  * keys are indistinguishable, so the sorted keys equal those of
  * bsort_sort; no permutation is produced (the exchange is not stable).
- * Each level reads the live keys about three times, so this is slower than
- * bsort_sort.  key_type, key_bytes, offsets and validation as for
+ * Each level reads the live keys about twice (a count pass, then the
+ * exchange) and writes the exchanged pairs, so this takes about twice as
+ * long as bsort_sort without indices.  key_type, key_bytes, offsets and validation as for
  * bsort_sort / bsort_segmented; flags: BSORT_DESCENDING, BSORT_NO_SKIP,
  * BSORT_NO_FINISH (others give BSORT_EINVAL).  Scratch 256-byte aligned.
  */

@@ -136,3 +136,26 @@ def test_python_api_and_empty():
     got = t.view(torch.int16).cpu().numpy().view(np.uint16)
     for a, b in ((0, 50000), (50000, 50001), (50001, 100003)):
         np.testing.assert_array_equal(got[a:b], oracle_sort("f16", bits[a:b], asc=False)[0])
+
+
+def test_inplace_many_segments_and_no_finish():
+    """2^14 segments of ragged small lengths (all finished straight from the
+    seed, one list entry each), and a segmented NO_FINISH call in which every
+    segment runs its global levels down to bit 0."""
+    rng = np.random.default_rng(560)
+    lengths = rng.integers(0, 200, size=1 << 14)
+    n = int(lengths.sum())
+    offs = np.concatenate([[0], np.cumsum(lengths)])
+    for name in ("f32", "u8"):
+        bits = W.mixed_bits(name, n, 561)
+        k = gpu_inplace(name, bits, asc=False, lengths=list(lengths))
+        for s in range(0, lengths.size, 97):
+            a, b = offs[s], offs[s + 1]
+            np.testing.assert_array_equal(k[a:b], oracle_sort(name, bits[a:b], asc=False)[0])
+    lengths = [3000, 1, 0, 12000, 257]
+    offs = np.concatenate([[0], np.cumsum(lengths)])
+    bits = W.mixed_bits("i32", int(sum(lengths)), 562)
+    k = gpu_inplace("i32", bits, flags=_lib.NO_FINISH, lengths=lengths)
+    for s in range(len(lengths)):
+        a, b = offs[s], offs[s + 1]
+        np.testing.assert_array_equal(k[a:b], oracle_sort("i32", bits[a:b])[0])
