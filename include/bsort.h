@@ -54,6 +54,7 @@ extern "C" {
 #define BSORT_ETOOBIG (-3)  /* n of 2^32 keys or more (any call)                         */
 #define BSORT_EHIP (-4)     /* the HIP runtime refused a launch (see bsort_strerror)     */
 #define BSORT_ENODEV (-5)   /* the current device is not a gfx950 GPU                    */
+#define BSORT_ENOSPACE (-6) /* more scratch than bsort_segmented_noalloc's buffer holds   */
 
 /* ---- flags ---- */
 #define BSORT_DESCENDING 1u /* non-increasing order                                       */
@@ -136,6 +137,29 @@ int bsort_segmented_f32(float *keys, const int64_t *offsets, uint64_t num_segmen
 int bsort_segmented_i32(int32_t *keys, const int64_t *offsets, uint64_t num_segments,
                         uint64_t n, uint32_t flags, void *indices, void *scratch,
                         size_t scratch_bytes, void *stream);
+
+/*
+ * Allocation-free form of bsort_segmented, for callers that cannot allocate
+ * device memory or pass a workspace: code recorded under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc.  Same arguments,
+ * result and errors as bsort_segmented, without scratch and scratch_bytes:
+ * the scratch is a fixed array of BSORT_NOALLOC_SCRATCH_BYTES bytes in device
+ * memory that the library holds on every GPU it runs on, from the first
+ * call on that GPU until the process ends.  The call itself allocates
+ * nothing (no hipMalloc, hipFree or allocating library routine).
+ * A call that would need more scratch than that -- i.e. whenever
+ * bsort_scratch_bytes(key_bytes, n, num_segments, indices != NULL, flags)
+ * exceeds BSORT_NOALLOC_SCRATCH_BYTES -- returns BSORT_ENOSPACE before
+ * anything is enqueued.  All calls on one GPU share its array, which keeps
+ * the last call's contents (each call clears what it needs with a kernel):
+ * calls that overlap on one GPU (two streams, two threads) race and must be
+ * ordered by the caller.  The device status word of bsort_device_status is
+ * not available to these calls.
+ */
+#define BSORT_NOALLOC_SCRATCH_BYTES (64ull << 20)
+int bsort_segmented_noalloc(void *keys, int key_type, int key_bytes, const int64_t *offsets,
+                            uint64_t num_segments, uint64_t n, uint32_t flags, void *indices,
+                            void *stream);
 
 /* Generic single-array form of the typed entry points above. */
 int bsort_sort(void *keys, int key_type, int key_bytes, uint64_t n, uint32_t flags,

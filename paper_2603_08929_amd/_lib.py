@@ -22,7 +22,8 @@ if not os.path.exists(LIB):
 lib = ctypes.CDLL(LIB)
 
 # status codes and flags (include/bsort.h)
-OK, EINVAL, ESCRATCH, ETOOBIG, EHIP, ENODEV = 0, -1, -2, -3, -4, -5
+OK, EINVAL, ESCRATCH, ETOOBIG, EHIP, ENODEV, ENOSPACE = 0, -1, -2, -3, -4, -5, -6
+NOALLOC_SCRATCH_BYTES = 64 << 20
 DESCENDING, NO_SKIP, NO_FINISH, IDX64, KEYS_UNCHANGED = 1, 2, 4, 8, 16
 PLAIN = NO_SKIP | NO_FINISH
 KEY_U, KEY_I, KEY_F = 0, 1, 2
@@ -40,7 +41,8 @@ SYMBOLS = ["bsort_scratch_bytes", "bsort_sort", "bsort_segmented", "bsort_segmen
            "bsort_sort_pairs", "bsort_segmented_pairs", "bsort_gather",
            "bsort_scratch_bytes128", "bsort_sort128", "bsort_sort_layout",
            "bsort_inplace_scratch_bytes", "bsort_sort_inplace", "bsort_segmented_inplace",
-           "bsort_scatter", "bsort_autotune_save", "bsort_autotune_load"] + \
+           "bsort_scatter", "bsort_autotune_save", "bsort_autotune_load",
+           "bsort_segmented_noalloc"] + \
     [f"bsort_{t}" for t in TYPED]
 
 lib.bsort_scratch_bytes.argtypes = [_i, _u64, _u64, _i, _u32]
@@ -53,6 +55,8 @@ lib.bsort_sort.argtypes = [_vp, _i, _i, _u64, _u32, _vp, _vp, _sz, _vp]
 lib.bsort_sort.restype = _i
 lib.bsort_segmented.argtypes = [_vp, _i, _i, _vp, _u64, _u64, _u32, _vp, _vp, _sz, _vp]
 lib.bsort_segmented.restype = _i
+lib.bsort_segmented_noalloc.argtypes = [_vp, _i, _i, _vp, _u64, _u64, _u32, _vp, _vp]
+lib.bsort_segmented_noalloc.restype = _i
 for t in ("f32", "i32"):
     fn = getattr(lib, f"bsort_segmented_{t}")
     fn.argtypes = [_vp, _vp, _u64, _u64, _u32, _vp, _vp, _sz, _vp]
@@ -133,6 +137,7 @@ def check(rc: int, what: str) -> None:
 bsort_scratch_bytes = lib.bsort_scratch_bytes
 bsort_sort = lib.bsort_sort
 bsort_segmented = lib.bsort_segmented
+bsort_segmented_noalloc = lib.bsort_segmented_noalloc
 bsort_segmented_f32 = lib.bsort_segmented_f32
 bsort_segmented_i32 = lib.bsort_segmented_i32
 bsort_backward_scatter = lib.bsort_backward_scatter

@@ -15,8 +15,10 @@
 // device memory and loop until it is exhausted.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 
 #include "bsort.h"
 #include "bsort_kernels.hpp"
@@ -1026,6 +1028,35 @@ bool backward_staged(const void *g, const void *idx, uint64_t rows, uint64_t col
   return true;
 }
 
+// ---- allocation-free calls
+//
+// bsort_segmented_noalloc takes its scratch from this fixed array instead of
+// from the caller.  Every GPU the library runs on holds its own copy, at its
+// own address, from the first such call until the process ends.  On the host
+// the array's name is only a stand-in: its device address is fetched once
+// per device with hipGetSymbolAddress (with that device current) and kept,
+// and only that address is ever handed to kernels.
+static __device__ __align__(256) char noalloc_scratch[BSORT_NOALLOC_SCRATCH_BYTES];
+void *g_noalloc_ptr[64];
+std::atomic<int> g_noalloc_ready[64];
+std::mutex g_noalloc_mu;
+
+int noalloc_scratch_of(int dev, void **out) {
+  if (!g_noalloc_ready[dev].load(std::memory_order_acquire)) {
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (!g_noalloc_ready[dev].load(std::memory_order_relaxed)) {
+      void *p = nullptr;
+      const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(noalloc_scratch));
+      if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress");
+      if (!p || (reinterpret_cast<uintptr_t>(p) & 255)) return BSORT_EHIP;
+      g_noalloc_ptr[dev] = p;
+      g_noalloc_ready[dev].store(1, std::memory_order_release);
+    }
+  }
+  *out = g_noalloc_ptr[dev];
+  return BSORT_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1518,6 +1549,26 @@ int bsort_graph_destroy(bsort_graph *graph) {
   return BSORT_OK;
 }
 
+int bsort_segmented_noalloc(void *keys, int key_type, int key_bytes, const int64_t *offsets,
+                            uint64_t num_segments, uint64_t n, uint32_t flags, void *indices,
+                            void *stream) {
+  if (n == 0)  // validated and done without any scratch, as bsort_segmented does
+    return dispatch(keys, key_type, key_bytes, n, offsets, num_segments, true, flags, indices,
+                    nullptr, 0, stream);
+  // the same bound as bsort_segmented's check of a caller's scratch
+  const size_t need = bsort_scratch_bytes(key_bytes, n, num_segments, indices != nullptr, flags);
+  if (need == 0) return BSORT_EINVAL;
+  if (n < (1ull << 32) && need > (size_t)BSORT_NOALLOC_SCRATCH_BYTES) return BSORT_ENOSPACE;
+  int cus = 0, dev = 0;
+  int rc = device_check(&cus, &dev);
+  if (rc != BSORT_OK) return rc;
+  void *scr = nullptr;
+  rc = noalloc_scratch_of(dev, &scr);
+  if (rc != BSORT_OK) return rc;
+  return dispatch(keys, key_type, key_bytes, n, offsets, num_segments, true, flags, indices, scr,
+                  (size_t)BSORT_NOALLOC_SCRATCH_BYTES, stream);
+}
+
 const char *bsort_strerror(int status) {
   switch (status) {
     case BSORT_OK: return "ok";
@@ -1526,6 +1577,9 @@ const char *bsort_strerror(int status) {
     case BSORT_ETOOBIG: return "too many keys (2^32 or more)";
     case BSORT_EHIP: return g_hip_err[0] ? g_hip_err : "HIP runtime error";
     case BSORT_ENODEV: return "current device is not a gfx950 GPU";
+    case BSORT_ENOSPACE:
+      return "the call needs more scratch than the allocation-free entry point's built-in "
+             "buffer (BSORT_NOALLOC_SCRATCH_BYTES) holds";
     default: return "unknown status";
   }
 }

@@ -282,3 +282,19 @@ def test_autotune_cache_files(tmp_path):
         bad = tmp_path / "bad.txt"
         bad.write_text(text)
         assert _lib.bsort_autotune_load(str(bad).encode()) == _lib.EINVAL, text
+
+
+def test_noalloc_validation_before_any_device_work():
+    """The allocation-free entry point: n = 0 succeeds with null pointers,
+    bad arguments are refused, and a call needing more scratch than the
+    built-in buffer holds returns ENOSPACE -- all before a device is queried."""
+    f = _lib.bsort_segmented_noalloc
+    fake = 1 << 40
+    assert f(None, _lib.KEY_U, 4, None, 0, 0, 0, None, None) == _lib.OK
+    assert f(fake, _lib.KEY_U, 3, fake, 1, 10, 0, None, None) == _lib.EINVAL   # key width
+    assert f(fake, _lib.KEY_U, 4, fake, 1, 10, 1 << 7, None, None) == _lib.EINVAL  # flag
+    cap = _lib.NOALLOC_SCRATCH_BYTES
+    n = 1 << 24  # u32 keys with indices: 64 MiB of ping-pong buffers alone
+    assert _lib.bsort_scratch_bytes(4, n, 1, 1, 0) > cap
+    assert f(fake, _lib.KEY_U, 4, fake, 1, n, 0, fake, None) == _lib.ENOSPACE
+    assert "allocation-free" in _lib.strerror(_lib.ENOSPACE)
