@@ -55,7 +55,7 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "level_kernel_u32_idx_2p26_traffic
 SOURCES = [os.path.join(ROOT, "paper_2603_08929_amd", "csrc", "bsort_kernels.hpp")]  # device code
 # The level kernel and everything it is built from come first in that file;
 # the hash covers the text up to this line, which follows the kernel.
-LEVEL_END = "// Before each level: (1) the per-tile descriptor map"
+LEVEL_END = "// ------------------------------------------------------------- LDS finish"
 
 
 def log(msg: str) -> None:

@@ -81,9 +81,9 @@ int device_check(int *cus, int *device = nullptr) {
   return BSORT_OK;
 }
 
-// Launch configurations.  A configuration fixes the level kernel's block
-// and tile (TILE = LB * LIPT keys), the finish kernel's block and threshold
-// (T = FB * FIPT keys) and the grids (every resident workgroup, or half).
+// Launch configurations.  A configuration fixes the level tile (one wave
+// of 64 lanes x LIPT keys), the finish kernel's block and threshold (T =
+// FB * FIPT keys) and the grids (every resident workgroup, or half).
 // Configuration 0 is the default; bsort_autotune times all of them on the
 // caller's data and remembers the fastest per key width, index mode and
 // size class.
@@ -92,7 +92,13 @@ constexpr int N_CONFIGS = N_LEVEL_SHAPES * N_FINISH_SHAPES * N_GRIDS;
 
 template <typename KT, int V>
 struct LevelShape {
-  static constexpr int LB = V == 0 ? 512 : 256;
+  static constexpr int LIPT = V == 0 ? 8 : 4;
+  static constexpr uint32_t TILE = 64 * LIPT;
+};
+// The in-place path's tile: a 512-thread workgroup.
+template <typename KT>
+struct InplaceShape {
+  static constexpr int LB = 512;
   static constexpr int LIPT = sizeof(KT) == 8 ? 4 : 8;
   static constexpr uint32_t TILE = LB * LIPT;
 };
@@ -123,10 +129,12 @@ struct Config {
 Config config_of(int id) { return Config{id / 6, (id / 2) % 3, id % 2}; }
 constexpr int CONFIG_DRY_RUN = -2;  // validate the arguments and the device, launch nothing
 
+// Level tile of a configuration's level shape (the smaller one is lv = 1).
 uint32_t tile_of(int key_bytes, int lv) {
-  const uint32_t lb = lv == 0 ? 512 : 256;
-  return lb * (key_bytes == 8 ? 4 : 8);
+  (void)key_bytes;
+  return 64u * (lv == 0 ? 8u : 4u);
 }
+uint32_t inplace_tile_of(int key_bytes) { return 512u * (key_bytes == 8 ? 4u : 8u); }
 uint32_t tfin_of(int key_bytes, int fv) {
   const uint32_t fb = fv == 1 ? 256 : 512;
   return fb * ((fv == 2 ? 8 : 16) / (key_bytes == 8 ? 2 : 1));
@@ -141,11 +149,13 @@ size_t up256(size_t x) { return (x + 255) & ~(size_t)255; }
 // it there).  Bounds: a live segment holds more than T keys (at least 2
 // with BSORT_NO_FINISH); a level's tiles are at most n/TILE + segments;
 // every parent yields at most two finish entries per level; copy entries
-// hold more than T keys each.
+// hold more than T keys each.  The small per-level arrays come first: the
+// level kernel reads them through one buffer descriptor with 32-bit
+// offsets (`meta` bytes from the start).
 struct Layout {
-  size_t hdr, cnts, segs[2], recs[2], acc[2], split[2], tmap[2], fin, fins, fint, finm, cpy,
-      keys1, idx0, idx1, keys0, total;
-  uint64_t smax, tmax, fmax, cmax;
+  size_t hdr, cnts, segs[2], acc[2], split[2], tmap, pc, agg, carry, fin, fins, fint, finm, cpy,
+      meta, keys1, idx0, idx1, keys0, total;
+  uint64_t smax, tmax, fmax, cmax, cn, nchunks;
 };
 
 bool make_layout(int key_bytes, uint64_t n, uint64_t B, bool with_idx, uint32_t flags,
@@ -158,17 +168,21 @@ bool make_layout(int key_bytes, uint64_t n, uint64_t B, bool with_idx, uint32_t 
   const uint64_t fb = B + 2 * w * L->smax + 1;
   L->fmax = (fb < n + 1 ? fb : n + 1);
   L->cmax = n / (tfin + 1ull) + 1;
+  // next-level front counts per tile, two level parities: child c of a
+  // parent with tiles [tile0, tile0 + nt) counts at 2 tile0 + c nt + j
+  L->cn = 2 * L->tmax + 1;
+  L->nchunks = L->tmax / PREP_TILES + 1;
   size_t off = 0;
   L->hdr = off; off = up256(off + sizeof(Header));
-  // per-tile front counts: [tiles, 64-tile groups] x two level parities,
-  // each indexed up to 3 * tmax: two children per parent tile range, then
-  // the segments counted by the count pass at recount + tile0
-  L->cnts = off; off = up256(off + 4 * (3 * L->tmax) * 4);
+  L->cnts = off; off = up256(off + 2 * L->cn * 4);
   for (int i = 0; i < 2; ++i) { L->segs[i] = off; off = up256(off + L->smax * sizeof(Seg)); }
-  for (int i = 0; i < 2; ++i) { L->recs[i] = off; off = up256(off + L->smax * sizeof(Seg)); }
   for (int i = 0; i < 2; ++i) { L->acc[i] = off; off = up256(off + L->tmax * sizeof(AccRep)); }
   for (int i = 0; i < 2; ++i) { L->split[i] = off; off = up256(off + L->smax * 8); }
-  for (int i = 0; i < 2; ++i) { L->tmap[i] = off; off = up256(off + L->tmax * sizeof(Seg)); }
+  L->tmap = off; off = up256(off + L->tmax * sizeof(Seg));
+  L->pc = off; off = up256(off + L->tmax * 8);
+  L->agg = off; off = up256(off + L->nchunks * 8);
+  L->carry = off; off = up256(off + L->nchunks * 8);
+  L->meta = off;
   L->fin = off; off = up256(off + L->fmax * sizeof(Seg));
   L->fins = off; off = up256(off + L->fmax * sizeof(Seg));
   L->fint = off; off = up256(off + L->fmax * sizeof(Seg));
@@ -184,7 +198,7 @@ bool make_layout(int key_bytes, uint64_t n, uint64_t B, bool with_idx, uint32_t 
   L->keys0 = 0;
   if (flags & BSORT_KEYS_UNCHANGED) { L->keys0 = off; off = up256(off + n * (size_t)key_bytes); }
   L->total = off;
-  return true;
+  return L->meta < (1ull << 32);
 }
 
 template <typename K>
@@ -218,14 +232,14 @@ int launch_all(KT *keys, uint64_t n, const int64_t *offsets, uint64_t B, int mod
   Header *hdr = reinterpret_cast<Header *>(scr + L.hdr);
   Seg *segs[2] = {reinterpret_cast<Seg *>(scr + L.segs[0]),
                   reinterpret_cast<Seg *>(scr + L.segs[1])};
-  Seg *recs[2] = {reinterpret_cast<Seg *>(scr + L.recs[0]),
-                  reinterpret_cast<Seg *>(scr + L.recs[1])};
   AccRep *acc[2] = {reinterpret_cast<AccRep *>(scr + L.acc[0]),
                     reinterpret_cast<AccRep *>(scr + L.acc[1])};
   uint64_t *split[2] = {reinterpret_cast<uint64_t *>(scr + L.split[0]),
                         reinterpret_cast<uint64_t *>(scr + L.split[1])};
-  Seg *tmap[2] = {reinterpret_cast<Seg *>(scr + L.tmap[0]),
-                  reinterpret_cast<Seg *>(scr + L.tmap[1])};
+  Seg *tmap = reinterpret_cast<Seg *>(scr + L.tmap);
+  uint2 *pc = reinterpret_cast<uint2 *>(scr + L.pc);
+  uint64_t *agg = reinterpret_cast<uint64_t *>(scr + L.agg);
+  uint64_t *carry = reinterpret_cast<uint64_t *>(scr + L.carry);
   Seg *fin = reinterpret_cast<Seg *>(scr + L.fin);
   Seg *fins = reinterpret_cast<Seg *>(scr + L.fins);
   Seg *fint = reinterpret_cast<Seg *>(scr + L.fint);
@@ -241,11 +255,10 @@ int launch_all(KT *keys, uint64_t n, const int64_t *offsets, uint64_t B, int mod
 
   const uint64_t cap = (uint64_t)cus * 16;
   uint32_t *cnt_base = reinterpret_cast<uint32_t *>(scr + L.cnts);
-  const uint64_t cn = 3 * L.tmax;  // entries per count array
-  uint32_t *tcnt[2] = {cnt_base, cnt_base + 2 * cn};
-  uint32_t *scnt[2] = {cnt_base + cn, cnt_base + 3 * cn};
-  hipLaunchKernelGGL(init_kernel, dim3(clamp_grid((4 * cn + 255) / 256, 2048)), dim3(256), 0,
-                     st, hdr, cnt_base, 4 * cn);
+  const uint64_t cn = L.cn;  // entries per count array
+  uint32_t *cnt[2] = {cnt_base, cnt_base + cn};
+  hipLaunchKernelGGL(init_kernel, dim3(clamp_grid((2 * cn + 255) / 256, 2048)), dim3(256), 0,
+                     st, hdr, cnt_base, 2 * cn);
   if (offsets)
     hipLaunchKernelGGL(validate_kernel, dim3(clamp_grid((B + 256) / 256, 1024)), dim3(256), 0,
                        st, offsets, B, n, hdr);
@@ -262,14 +275,13 @@ int launch_all(KT *keys, uint64_t n, const int64_t *offsets, uint64_t B, int mod
   la.t_small = SmallFinish<KT>::T;
   la.t_tiny = TinyFinish::T;
   la.t_med = FS::TFIN / 2;
-  la.recount = (uint32_t)(2 * L.tmax);
+  la.recount = (uint32_t)(2 * L.tmax);  // never read: the prep pass counts such segments
 
   SeedArgs sa;
   sa.l = la;
   sa.l.live_next = segs[0];
   sa.l.acc_next = acc[0];
   sa.l.split_next = split[0];
-  sa.l.rec_next = recs[0];
   sa.l.next_level = 0;
   sa.offsets = offsets;
   sa.B = B;
@@ -281,52 +293,55 @@ int launch_all(KT *keys, uint64_t n, const int64_t *offsets, uint64_t B, int mod
   sa.idx64 = idx64;
   hipLaunchKernelGGL(seed_kernel, dim3(clamp_grid((B + 255) / 256, cap)), dim3(256), 0, st, sa);
 
-  auto lk = level_kernel<KT, IDX, LS::LB, LS::LIPT>;
-  static const int occ_level = occupancy(lk, LS::LB);
-  const uint32_t lgrid = clamp_grid(L.tmax, (uint64_t)cus * occ_level / gdiv);
+  auto lk = level_kernel<KT, IDX, LS::LIPT>;
+  static const int occ_level = occupancy(lk, 256);
+  const uint32_t lgrid = clamp_grid((L.tmax + 3) / 4, (uint64_t)cus * occ_level / gdiv);
   const uint32_t pgrid = clamp_grid((L.smax + 255) / 256, cap);
-  auto ck = count_kernel<KT, LS::LB, LS::LIPT>;
-  static const int occ_count = occupancy(ck, LS::LB);
-  const uint32_t cgrid = clamp_grid(L.tmax, (uint64_t)cus * occ_count / gdiv);
+  auto pk = prep_kernel<KT, LS::LIPT>;
+  const uint32_t cgrid = clamp_grid(L.nchunks, L.nchunks);
   // A single array that fits the LDS finish never has a live segment: the
   // seed hands it straight to the finish, so the level passes and the copy
   // would all find empty lists.
   const int levels = (!offsets && !no_finish && n <= FS::TFIN) ? 0 : w;
   for (int lvl = 0; lvl < levels; ++lvl) {
-    CountArgs<KT> ca;
-    ca.keys = kbuf[lvl & 1];
+    PrepArgs<KT> ca;
+    ca.keys[0] = kbuf[0];
+    ca.keys[1] = kbuf[1];
     ca.live = segs[lvl & 1];
-    ca.rec = recs[lvl & 1];
-    ca.tiles = tmap[lvl & 1];
+    ca.tmap = tmap;
+    ca.pc = pc;
+    ca.agg = agg;
+    ca.carry = carry;
+    ca.cnt_in = cnt[lvl & 1];
     ca.hdr = hdr;
-    ca.tcnt = tcnt[lvl & 1];
-    ca.scnt = scnt[lvl & 1];
     ca.w = w;
     ca.mode = mode;
     ca.desc = desc;
     ca.level = lvl;
-    hipLaunchKernelGGL(ck, dim3(cgrid), dim3(LS::LB), 0, st, ca);
+    hipLaunchKernelGGL(pk, dim3(cgrid), dim3(256), 0, st, ca);
 
     LevelArgs<KT> a;
-    a.keys_in = kbuf[lvl & 1];
-    a.keys_out = kbuf[(lvl + 1) & 1];
-    a.idx_in = ibuf[lvl & 1];
-    a.idx_out = ibuf[(lvl + 1) & 1];
-    a.tiles = tmap[lvl & 1];
+    a.keys[0] = kbuf[0];
+    a.keys[1] = kbuf[1];
+    a.idx[0] = ibuf[0];
+    a.idx[1] = ibuf[1];
+    a.meta = scr;
+    a.off.tmap = (uint32_t)L.tmap;
+    a.off.pc = (uint32_t)L.pc;
+    a.off.carry = (uint32_t)L.carry;
+    a.off.acc = (uint32_t)L.acc[lvl & 1];
+    a.off.range = (uint32_t)L.meta;
     a.acc = acc[lvl & 1];
     a.split = split[lvl & 1];
     a.hdr = hdr;
-    a.tcnt_in = tcnt[lvl & 1];
-    a.scnt_in = scnt[lvl & 1];
-    a.tcnt_out = tcnt[(lvl + 1) & 1];
-    a.scnt_out = scnt[(lvl + 1) & 1];
+    a.cnt_out = cnt[(lvl + 1) & 1];
     a.w = w;
     a.mode = mode;
     a.desc = desc;
     a.level = lvl;
     const bool timed = g_timing.armed && !g_capturing && g_timing.count < g_timing.cap;
     if (timed) (void)hipEventRecord(g_timing.ev[2 * g_timing.count], st);
-    hipLaunchKernelGGL(lk, dim3(lgrid), dim3(LS::LB), 0, st, a);
+    hipLaunchKernelGGL(lk, dim3(lgrid), dim3(256), 0, st, a);
     if (timed) {
       (void)hipEventRecord(g_timing.ev[2 * g_timing.count + 1], st);
       g_timing.lvl[g_timing.count++] = lvl;
@@ -337,13 +352,12 @@ int launch_all(KT *keys, uint64_t n, const int64_t *offsets, uint64_t B, int mod
     pa.l.live_next = segs[(lvl + 1) & 1];
     pa.l.acc_next = acc[(lvl + 1) & 1];
     pa.l.split_next = split[(lvl + 1) & 1];
-    pa.l.rec_next = recs[(lvl + 1) & 1];
     pa.l.next_level = lvl + 1;
     pa.live = segs[lvl & 1];
     pa.acc = acc[lvl & 1];
     pa.split = split[lvl & 1];
-    pa.zero_a = tcnt[lvl & 1];  // read by this level, filled by the next one
-    pa.zero_b = scnt[lvl & 1];
+    pa.zero_a = cnt[lvl & 1];  // read by this level's prep, filled by the next level
+    pa.zero_b = nullptr;
     pa.zero_n = cn;
     pa.level = lvl;
     pa.w = w;
@@ -734,14 +748,14 @@ int sort128(void *keys, int key_type, uint64_t n, uint32_t flags, void *indices,
 constexpr uint32_t IP_FLAGS = BSORT_DESCENDING | BSORT_NO_SKIP | BSORT_NO_FINISH;
 
 struct InplaceLayout {
-  size_t hdr, cnts, segs[2], recs[2], acc[2], split[2], tmap, pre, sub, ends, items, fin, fins,
+  size_t hdr, cnts, segs[2], acc[2], split[2], tmap, pre, sub, ends, items, fin, fins,
       fint, finm, cpy, total;
   uint64_t smax, tmax, fmax;
 };
 
 bool inplace_layout(int key_bytes, uint64_t n, uint64_t B, uint32_t flags, InplaceLayout *L) {
   if (key_bytes != 1 && key_bytes != 2 && key_bytes != 4 && key_bytes != 8) return false;
-  const uint64_t tile = tile_of(key_bytes, 0), tfin = tfin_of(key_bytes, 0);
+  const uint64_t tile = inplace_tile_of(key_bytes), tfin = tfin_of(key_bytes, 0);
   const bool no_finish = (flags & BSORT_NO_FINISH) != 0;
   L->smax = (no_finish ? n / 2 : n / (tfin + 1)) + 1;
   L->tmax = n / tile + L->smax + 1;
@@ -751,7 +765,6 @@ bool inplace_layout(int key_bytes, uint64_t n, uint64_t B, uint32_t flags, Inpla
   L->hdr = off; off = up256(off + sizeof(Header));
   L->cnts = off; off = up256(off + 4 * (3 * L->tmax) * 4);
   for (int i = 0; i < 2; ++i) { L->segs[i] = off; off = up256(off + L->smax * sizeof(Seg)); }
-  for (int i = 0; i < 2; ++i) { L->recs[i] = off; off = up256(off + L->smax * sizeof(Seg)); }
   for (int i = 0; i < 2; ++i) { L->acc[i] = off; off = up256(off + L->tmax * sizeof(AccRep)); }
   for (int i = 0; i < 2; ++i) { L->split[i] = off; off = up256(off + L->smax * 8); }
   L->tmap = off; off = up256(off + L->tmax * sizeof(Seg));
@@ -797,7 +810,7 @@ void launch_finishes(FinishArgs<KT> fa, Header *hdr, Seg *fin, Seg *fins, Seg *f
 template <typename KT>
 int launch_inplace(KT *keys, uint64_t n, const int64_t *offsets, uint64_t B, int mode,
                    uint32_t flags, char *scr, const InplaceLayout &L, int cus, hipStream_t st) {
-  using LS = LevelShape<KT, 0>;
+  using LS = InplaceShape<KT>;
   using FS = FinishShape<KT, 0>;
   const int w = 8 * (int)sizeof(KT);
   const int desc = (flags & BSORT_DESCENDING) ? 1 : 0;
@@ -806,8 +819,6 @@ int launch_inplace(KT *keys, uint64_t n, const int64_t *offsets, uint64_t B, int
   Header *hdr = reinterpret_cast<Header *>(scr + L.hdr);
   Seg *segs[2] = {reinterpret_cast<Seg *>(scr + L.segs[0]),
                   reinterpret_cast<Seg *>(scr + L.segs[1])};
-  Seg *recs[2] = {reinterpret_cast<Seg *>(scr + L.recs[0]),
-                  reinterpret_cast<Seg *>(scr + L.recs[1])};
   AccRep *acc[2] = {reinterpret_cast<AccRep *>(scr + L.acc[0]),
                     reinterpret_cast<AccRep *>(scr + L.acc[1])};
   uint64_t *split[2] = {reinterpret_cast<uint64_t *>(scr + L.split[0]),
@@ -846,7 +857,6 @@ int launch_inplace(KT *keys, uint64_t n, const int64_t *offsets, uint64_t B, int
   sa.l.live_next = segs[0];
   sa.l.acc_next = acc[0];
   sa.l.split_next = split[0];
-  sa.l.rec_next = recs[0];
   sa.l.next_level = 0;
   sa.offsets = offsets;
   sa.B = B;
@@ -913,7 +923,6 @@ int launch_inplace(KT *keys, uint64_t n, const int64_t *offsets, uint64_t B, int
     pa.l.live_next = segs[(lvl + 1) & 1];
     pa.l.acc_next = acc[(lvl + 1) & 1];
     pa.l.split_next = split[(lvl + 1) & 1];
-    pa.l.rec_next = recs[(lvl + 1) & 1];
     pa.l.next_level = lvl + 1;
     pa.live = segs[lvl & 1];
     pa.acc = acc[lvl & 1];
@@ -1314,8 +1323,8 @@ const char *bsort_config_name(int config) {
   if (!names[config][0]) {
     const Config c = config_of(config);
     snprintf(names[config], sizeof names[config],
-             "level %dx%d (tile %u keys of 4 B), finish %dx%d (T %u keys of 4 B), %s grid",
-             c.lv == 0 ? 512 : 256, 8, tile_of(4, c.lv), c.fv == 1 ? 256 : 512,
+             "level one wave x %d (tile %u keys), finish %dx%d (T %u keys of 4 B), %s grid",
+             c.lv == 0 ? 8 : 4, tile_of(4, c.lv), c.fv == 1 ? 256 : 512,
              c.fv == 2 ? 8 : 16, tfin_of(4, c.fv), c.grid ? "half" : "full");
   }
   return names[config];

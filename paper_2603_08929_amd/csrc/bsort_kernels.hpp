@@ -6,27 +6,23 @@
 // recurses into both.  Here the recursion runs breadth first: one global
 // "level" processes the current bit of every live segment at once.
 //
-// A level is ONE pass over the live keys: each workgroup takes a tile of
-// one segment, ranks its keys front/back with wave ballots and an LDS scan,
-// takes how many front keys precede the tile from per-tile counts made
-// before the level (by the previous level while it wrote the keys, or by a
-// count pass for segments whose bit was reached by skipping), and scatters
-// the tile as two contiguous runs.  The split point of a segment is not
-// needed before its back part is written: back keys are placed from the
-// segment's right end leftwards, so the back child is stored in reverse
-// order and the next level reads it right to left (a per-segment "rev"
-// flag).  The same pass folds the AND and
-// OR of each child's keys into per-child accumulators, from which the next
-// level picks the child's next bit (bits on which a child is constant are
-// skipped: a split with an empty side is the identity) or retires it.
-// Segments of at most T keys finish all their remaining bits inside one
-// workgroup, in LDS (the hybrid switch to a cache-resident routine that the
-// paper proposes in Sections IV-B and V).
+// A level is ONE pass over the live keys: each wave takes a tile of one
+// segment, ranks its keys front/back with ballots and lane masks, takes
+// how many front keys precede the tile (and the segment's total) from
+// per-tile counts made before the level -- by the previous level while it
+// wrote the keys, or by the prep pass for segments whose bit was reached by
+// skipping -- and a scan of them by the prep pass, and writes the front keys
+// from the segment's start and the back keys after all its front keys.  The
+// same pass folds the AND and OR of each child's keys into per-child
+// accumulators, from which the next level picks the child's next bit (bits
+// on which a child is constant are skipped: a split with an empty side is
+// the identity) or retires it.  Segments of at most T keys finish all their
+// remaining bits inside one workgroup, in LDS (the hybrid switch to a
+// cache-resident routine that the paper proposes in Sections IV-B and V).
 //
-// Workgroups take tiles round-robin; every load of the next tile is issued
-// on every path (empty ranges where there is nothing to read), so that the
-// in-order counter of outstanding loads lets the current tile's work wait
-// only for its own data.
+// Every load of a tile is issued on every path (empty ranges where there is
+// nothing to read), so that the in-order counter of outstanding loads lets
+// the current tile's work wait only for its own data.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -43,11 +39,10 @@ enum : int { MODE_U = 0, MODE_I = 1, MODE_F = 2 };
 // Segment descriptor meta bits.
 constexpr uint32_t BIT_MASK = 0x7Fu;   // bit to split on next (0..63)
 constexpr uint32_t BIT_NONE = 0x7Fu;   // no bit left: copy only
-constexpr uint32_t META_REV = 1u << 7; // stored right to left
 constexpr uint32_t META_SIGN = 1u << 8;  // float keys of this segment are negative
 constexpr uint32_t META_BUF = 1u << 9;   // data lives in the scratch buffers
 constexpr uint32_t META_IOTA = 1u << 10; // index payload not materialized yet
-constexpr uint32_t META_PRE = 1u << 11;  // the previous level counted `bit` per tile
+constexpr uint32_t META_PRE = 1u << 11;  // the previous level counted `bit` per tile (at cbase)
 
 constexpr uint32_t STATUS_OVERSIZE = 1u;  // a finish entry larger than the workgroup's capacity
 constexpr uint32_t STATUS_BAD_OFFSETS = 2u;
@@ -94,7 +89,7 @@ struct Header {
   uint64_t finish_keys;        // keys handed to the LDS finish (all levels)
   uint64_t copy_keys;          // keys of retired segments copied back
   uint64_t packed[MAX_LEVELS]; // per level: (live segments << 32) | tiles
-  uint64_t rec_packed[MAX_LEVELS]; // per level: (segments << 32) | tiles to recount
+  uint32_t prep_ticket[MAX_LEVELS]; // per level: prep workgroups done
   uint64_t live_keys[MAX_LEVELS]; // per level: keys in live segments
 };
 
@@ -259,6 +254,24 @@ __device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t v) {
   return v;
 }
 
+// Largest i in [0, n) with le(i), for a predicate that holds on a prefix of
+// [0, n) and at 0: a 64-ary search by one whole wave (every lane probes one
+// point per round), so a search over 2^14 entries takes three dependent
+// loads instead of fourteen.  All 64 lanes must call it.
+template <typename Le>
+__device__ __forceinline__ uint32_t wave_search_le(uint32_t n, Le le) {
+  const uint32_t lane = threadIdx.x & 63;
+  uint32_t lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const uint32_t step = (hi - lo + 64) / 64;
+    const uint32_t idx = lo + lane * step;
+    const uint64_t ok = __ballot(idx <= hi && le(idx));
+    lo += ((uint32_t)__popcll(ok) - 1) * step;
+    hi = lo + step - 1 < hi ? lo + step - 1 : hi;
+  }
+  return lo;
+}
+
 // Which side a key goes to (Algorithm 1's test, with the direction rules of
 // Algorithms 3-5): 1 = back part.  Ascending puts the 0-side first; the sign
 // pass of signed and float keys runs in the inverse direction; the lower
@@ -301,7 +314,6 @@ struct ListArgs {
   Seg *live_next;       // level (lvl+1) live list, in tile order
   AccRep *acc_next;     // per-tile AND/OR replicas of level (lvl+1)
   uint64_t *split_next;  // per-slot split of level (lvl+1)
-  Seg *rec_next;        // level (lvl+1) segments the count pass must count
   Seg *fin;
   Seg *fin_small;       // finish entries of at most t_small keys
   Seg *fin_tiny;        // finish entries of at most t_tiny keys
@@ -313,14 +325,14 @@ struct ListArgs {
   uint32_t t_small;     // finish entries up to this size take the one-wave finish
   uint32_t t_tiny;      // ... and up to this size, one key per lane
   uint32_t t_med;       // ... and up to this size, half the full finish shape
-  uint32_t recount;     // count index base of segments counted by the count pass
+  uint32_t recount;     // count base of segments whose counts the level did not make
 };
 
 struct Child {
   uint64_t start, len;
   uint32_t meta;
   uint32_t tiles;
-  uint32_t cbase;     // count base, or CBASE_OWN: recounted, at recount + tile0
+  uint32_t cbase;     // count base, or CBASE_OWN: not counted by the level, at recount + tile0
   int kind;
 };
 constexpr uint32_t CBASE_OWN = 0xFFFFFFFFu;
@@ -338,12 +350,11 @@ __device__ void emit_children(const ListArgs &a, Child (&ch)[2]) {
   const int lane = threadIdx.x & 63;
   // live: slots and tiles packed in one 64-bit counter so that slot order
   // and tile order agree
-  uint64_t mine = 0, mrec = 0, klive = 0, kfin = 0, kcpy = 0;
+  uint64_t mine = 0, klive = 0, kfin = 0, kcpy = 0;
   uint32_t nfin = 0, nfs = 0, nft = 0, nfm = 0, ncpy = 0;
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
     if (ch[c].kind == KIND_LIVE) { mine += (1ull << 32) | ch[c].tiles; klive += ch[c].len; }
-    if (ch[c].kind == KIND_LIVE && ch[c].cbase == CBASE_OWN) mrec += (1ull << 32) | ch[c].tiles;
     if (ch[c].kind == KIND_FINISH) {
       if (ch[c].len <= a.t_tiny) nft++;
       else if (ch[c].len <= a.t_small) nfs++;
@@ -363,24 +374,21 @@ __device__ void emit_children(const ListArgs &a, Child (&ch)[2]) {
     if (kcpy) atomic_add_u64(&a.hdr->copy_keys, kcpy);
   }
   const uint64_t inc_live = wave_incl_scan_u64(mine);
-  const uint64_t inc_rec = wave_incl_scan_u64(mrec);
   const uint32_t inc_fin = wave_incl_scan_u32(nfin);
   const uint32_t inc_fs = wave_incl_scan_u32(nfs);
   const uint32_t inc_ft = wave_incl_scan_u32(nft);
   const uint32_t inc_fm = wave_incl_scan_u32(nfm);
   const uint32_t inc_cpy = wave_incl_scan_u32(ncpy);
   const uint64_t tot_live = __shfl(inc_live, 63);
-  const uint64_t tot_rec = __shfl(inc_rec, 63);
   const uint32_t tot_fin = __shfl(inc_fin, 63);
   const uint32_t tot_fs = __shfl(inc_fs, 63);
   const uint32_t tot_ft = __shfl(inc_ft, 63);
   const uint32_t tot_fm = __shfl(inc_fm, 63);
   const uint32_t tot_cpy = __shfl(inc_cpy, 63);
-  uint64_t b_live = 0, b_rec = 0;
+  uint64_t b_live = 0;
   uint32_t b_fin = 0, b_fs = 0, b_ft = 0, b_fm = 0, b_cpy = 0;
   if (lane == 0) {
     if (tot_live) b_live = atomic_add_u64(&a.hdr->packed[a.next_level], tot_live);
-    if (tot_rec) b_rec = atomic_add_u64(&a.hdr->rec_packed[a.next_level], tot_rec);
     if (tot_fin) b_fin = atomic_add_u32(&a.hdr->n_finish, tot_fin);
     if (tot_fs) b_fs = atomic_add_u32(&a.hdr->n_finish_small, tot_fs);
     if (tot_ft) b_ft = atomic_add_u32(&a.hdr->n_finish_tiny, tot_ft);
@@ -388,14 +396,12 @@ __device__ void emit_children(const ListArgs &a, Child (&ch)[2]) {
     if (tot_cpy) b_cpy = atomic_add_u32(&a.hdr->n_copy, tot_cpy);
   }
   b_live = __shfl(b_live, 0);
-  b_rec = __shfl(b_rec, 0);
   b_fin = __shfl(b_fin, 0);
   b_fs = __shfl(b_fs, 0);
   b_ft = __shfl(b_ft, 0);
   b_fm = __shfl(b_fm, 0);
   b_cpy = __shfl(b_cpy, 0);
   uint64_t pos = b_live + (inc_live - mine);
-  uint64_t rpos = b_rec + (inc_rec - mrec);
   uint32_t fpos = b_fin + (inc_fin - nfin);
   uint32_t fspos = b_fs + (inc_fs - nfs);
   uint32_t ftpos = b_ft + (inc_ft - nft);
@@ -426,14 +432,6 @@ __device__ void emit_children(const ListArgs &a, Child (&ch)[2]) {
       }
       a.split_next[slot] = 0;
       pos += (1ull << 32) | ch[c].tiles;
-      if (ch[c].cbase == CBASE_OWN) {
-        // to be counted on its bit before the level; .slot holds the
-        // segment's first tile in the recount tile space
-        Seg r = s;
-        r.slot = (uint32_t)rpos;
-        a.rec_next[rpos >> 32] = r;
-        rpos += (1ull << 32) | ch[c].tiles;
-      }
     } else if (ch[c].kind == KIND_FINISH) {
       if (ch[c].len <= a.t_tiny) a.fin_tiny[ftpos++] = s;
       else if (ch[c].len <= a.t_small) a.fin_small[fspos++] = s;
@@ -447,7 +445,8 @@ __device__ void emit_children(const ListArgs &a, Child (&ch)[2]) {
 
 // Level 0: every user segment becomes a live segment (split on the top bit,
 // the first pass of Algorithms 2, 3 and 4), or goes straight to the finish
-// list when it is small.
+// list when it is small.  Its front counts are not known yet, so the prep
+// pass before the level counts its tiles.
 struct SeedArgs {
   ListArgs l;
   const int64_t *offsets; // nullable: one segment [0, n)
@@ -494,7 +493,7 @@ __global__ void seed_kernel(SeedArgs a) {
         } else {
           ch[0].kind = KIND_LIVE;
           ch[0].tiles = (uint32_t)((len + a.l.tile - 1) / a.l.tile);
-          ch[0].cbase = CBASE_OWN;  // counted by the count pass
+          ch[0].cbase = CBASE_OWN;
         }
       }
     }
@@ -504,12 +503,15 @@ __global__ void seed_kernel(SeedArgs a) {
 
 // After level `level`: turn each parent's two children into next-level
 // segments, finish entries, copy entries or nothing (already in place).
+// The level wrote the children into the other buffer, front child first;
+// a split with an empty side moved nothing, so that child stays where its
+// parent was (and keeps an index payload that is still the identity).
 struct PlanArgs {
   ListArgs l;
   const Seg *live;
   const AccRep *acc;
   const uint64_t *split;
-  uint32_t *zero_a;  // count arrays the next level accumulates into
+  uint32_t *zero_a;  // count arrays the next level accumulates into (zero_b nullable)
   uint32_t *zero_b;
   uint64_t zero_n;
   int level;
@@ -518,16 +520,15 @@ struct PlanArgs {
   int idx64;
   int no_skip;
   int no_finish;
-  int inplace;  // the level partitioned in place: no buffers, no reversal, no counts
+  int inplace;  // the level partitioned in place: no buffers, no counts
 };
 
 __global__ void plan_kernel(PlanArgs a) {
   const uint32_t S = (uint32_t)(a.l.hdr->packed[a.level] >> 32);
-  const uint32_t buf_out = (!a.inplace && ((a.level + 1) & 1)) ? META_BUF : 0u;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.zero_n; i += stride) {
     a.zero_a[i] = 0;
-    a.zero_b[i] = 0;
+    if (a.zero_b) a.zero_b[i] = 0;
   }
   for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x; base < S; base += stride) {
     const uint64_t q = base + threadIdx.x;
@@ -563,12 +564,16 @@ __global__ void plan_kernel(PlanArgs a) {
       const int bit = (int)(p.meta & BIT_MASK);
       const uint64_t F = a.split[q];
       const uint32_t nt_p = (uint32_t)((p.len + a.l.tile - 1) / a.l.tile);
+      // where the children's keys are: moved to the other buffer, or left
+      // in place by a split with an empty side
+      const bool moved = !a.inplace && F != 0 && F != p.len;
+      const uint32_t cbuf = moved ? ((p.meta & META_BUF) ^ META_BUF) : (p.meta & META_BUF);
+      const uint32_t ciota = (moved || a.inplace) ? 0u : (p.meta & META_IOTA);
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
         const uint64_t len = c ? p.len - F : F;
         const uint64_t andv = c ? and_hi : and_lo;
         const uint64_t orv = c ? or_hi : or_lo;
-        const uint32_t rev = (c && !a.inplace) ? META_REV : 0u;
         ch[c].start = c ? p.start + F : p.start;
         ch[c].len = len;
         if (len == 0) continue;
@@ -582,10 +587,12 @@ __global__ void plan_kernel(PlanArgs a) {
           }
         }
         const uint32_t sign = ((andv >> (a.w - 1)) & 1) ? META_SIGN : 0u;
-        const uint32_t meta = rev | sign | buf_out;
+        const uint32_t meta = sign | cbuf | ciota;
         if (nb < 0) {
-          // retired: every key of the child is the same pattern
-          const bool need = buf_out || (a.with_idx && (rev || a.idx64));
+          // retired: every key of the child is the same pattern; it still
+          // has to reach the caller's buffers if it sits in scratch or its
+          // indices are not written there yet
+          const bool need = cbuf || (a.with_idx && (ciota || a.idx64));
           if (need) {
             ch[c].meta = meta | BIT_NONE;
             ch[c].kind = len <= a.l.t_fin ? KIND_FINISH : KIND_COPY;
@@ -595,7 +602,7 @@ __global__ void plan_kernel(PlanArgs a) {
           ch[c].kind = KIND_FINISH;
         } else {
           // the level counted this child's front keys on bit - 1 per tile;
-          // a child that skipped to a lower bit is counted by the count pass
+          // a child that skipped to a lower bit is counted by the prep pass
           const bool pre = nb == bit - 1 && !a.inplace;
           ch[c].meta = meta | (pre ? META_PRE : 0u) | (uint32_t)nb;
           ch[c].kind = KIND_LIVE;
@@ -609,518 +616,560 @@ __global__ void plan_kernel(PlanArgs a) {
 }
 
 // ------------------------------------------------------------ global level
+//
+// One level splits every live segment on its bit.  A level tile is one
+// wave's work: TILE = 64 * IPT consecutive keys of one segment, tile key q
+// at lane q % 64 of item q / 64, so that every load reads 64 consecutive
+// keys.  What a tile needs from other tiles is made before the level by the
+// prep pass: its segment's descriptor, the number of front keys in the tile
+// and in the segment before it, and the segment's total F.  So no tile
+// waits for another and a wave works alone: no block barrier, no LDS.
+//
+// A front key of front rank r (counted in input order over the segment)
+// lands at start + r, a back key of back rank r at start + F + r: both
+// children keep input order, as the stable partitions of Figs. 1-2 do.  A
+// split with an empty side (F = 0 or F = len) is the identity (Algorithm 1
+// with k = ps or k = pe): its tiles write nothing and the child stays in
+// the parent's buffer.
+//
+// While it places the keys, a tile also counts, for each child tile of the
+// next level, the keys that go front on bit - 1 (the usual next bit), and
+// folds the AND and OR of each child's keys into the segment's replicated
+// words, from which the plan picks each child's next bit.
+
+constexpr int PREP_TILES = 256;  // level tiles per prep workgroup: a chunk
+
+// Byte offsets, from the base of the scratch buffer, of the per-level arrays
+// a level tile reads with per-lane buffer loads (one descriptor covers all).
+struct LevelMeta {
+  uint32_t tmap;   // Seg per tile
+  uint32_t pc;     // uint2 per tile: (front keys of its segment before it in its chunk, its front keys)
+  uint32_t carry;  // uint64 per chunk: front keys of the segment open at its start, before it
+  uint32_t acc;    // AccRep replicas of the level
+  uint32_t range;  // bytes the descriptor covers
+};
 
 template <typename KT>
-struct LevelArgs {
-  const KT *keys_in;
-  KT *keys_out;
-  const uint32_t *idx_in;
-  uint32_t *idx_out;
-  const Seg *tiles;   // per-tile descriptor copies (slot in .slot)
-  AccRep *acc;        // per-tile AND/OR replicas
-  uint64_t *split;    // per-slot split
+struct PrepArgs {
+  const KT *keys[2];       // key buffers 0 (the caller's) and 1 (scratch)
+  const Seg *live;         // this level's live segments, in tile order
+  Seg *tmap;               // out: per tile, its segment's descriptor
+  uint2 *pc;               // out: see LevelMeta
+  uint64_t *agg;           // per chunk: front keys after its last segment start (or all), bit 63 = has one
+  uint64_t *carry;         // out: see LevelMeta
+  const uint32_t *cnt_in;  // front keys per tile of counted segments, at cbase + j (previous level)
   Header *hdr;
-  const uint32_t *tcnt_in;  // this level: front keys per tile
-  const uint32_t *scnt_in;  //   ... and per group of 64 tiles
-  uint32_t *tcnt_out;       // next level: front keys on bit - 1 per child tile
-  uint32_t *scnt_out;
   int w, mode, desc, level;
 };
 
-// Kernel arguments read where they are used (a scalar load from the
-// argument segment) instead of held in scalar registers across the tile
-// loop, whose other uniform values already fill them.
-template <typename T>
-__device__ __forceinline__ T karg_at(size_t off) {
-  const __attribute__((address_space(4))) char *k =
-      (const __attribute__((address_space(4))) char *)__builtin_amdgcn_kernarg_segment_ptr();
-  return *(const volatile __attribute__((address_space(4))) T *)(k + off);
+// Front keys of one level tile, counted by the whole wave from its keys:
+// loads only; the caller reduces (so several tiles' loads are in flight).
+template <typename KT, int IPT>
+__device__ __forceinline__ void tile_keys(const KT *keys, uint64_t start, uint64_t len,
+                                          uint64_t lo, KT (&k)[IPT], uint32_t &cnt) {
+  constexpr uint32_t TILE = 64 * IPT;
+  const int lane = threadIdx.x & 63;
+  cnt = lo < len ? (uint32_t)(len - lo < TILE ? len - lo : TILE) : 0u;
+  const rsrc_t kr = make_rsrc(keys + start + lo, cnt * (uint32_t)sizeof(KT));
+#pragma unroll
+  for (int i = 0; i < IPT; ++i) k[i] = buf_load<KT>(kr, (uint32_t)(i * 64 + lane) * (uint32_t)sizeof(KT));
 }
-#define LARG(f) karg_at<decltype(LevelArgs<KT>::f)>(offsetof(LevelArgs<KT>, f))
 
-// Uniform description of one tile of a level (every lane holds the same).
-struct TileInfo {
+// Before each level.  Workgroup b takes the chunk of level tiles
+// [256 b, 256 b + 256), a wave 64 of them, a lane one:
+//  - the tile's segment (one 64-ary wave search for the wave's first tile,
+//    then the segments that start among its tiles) and descriptor;
+//  - its front keys: made by the previous level for segments split on the
+//    bit below their parent's, else counted here from the keys (level 0,
+//    and segments that reached their bit by skipping);
+//  - an exclusive scan of the counts over the chunk that restarts at every
+//    segment start; and the chunk's sum after its last segment start.
+// The last workgroup to finish (a ticket) turns the chunk sums into each
+// chunk's carry, the front keys of the segment that is open at the chunk's
+// start, before it.  A tile's front prefix is then its scan value plus,
+// when its segment started in an earlier chunk, its chunk's carry.
+template <typename KT, int IPT>
+__global__ __launch_bounds__(256) void prep_kernel(PrepArgs<KT> a) {
+  constexpr uint32_t TILE = 64 * IPT;
+  constexpr int RB = 4;  // tiles counted at once by a wave
+  using RT = typename std::conditional<sizeof(KT) == 8, uint64_t, uint32_t>::type;
+  __shared__ uint32_t s_tail[4], s_hh[4], s_last;
+  __shared__ uint64_t s_v[256];
+  __shared__ uint32_t s_f[256];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const uint64_t pk = a.hdr->packed[a.level];
+  const uint32_t S = (uint32_t)(pk >> 32), ntiles = (uint32_t)pk;
+  const uint32_t nchunks = (ntiles + PREP_TILES - 1) / PREP_TILES;
+  const uint32_t chunk = blockIdx.x;
+  if (chunk >= nchunks) return;
+  const uint32_t t0 = chunk * PREP_TILES + (uint32_t)wave * 64;
+  const uint32_t t = t0 + (uint32_t)lane;
+  const bool valid = t < ntiles;
+  uint32_t c = 0;
+  bool head = false;
+  if (t0 < ntiles) {
+    const uint32_t s0 = wave_search_le(S, [&](uint32_t i) { return a.live[i].tile0 <= t0; });
+    // bit d of M: a segment starts at tile t0 + d (d >= 1)
+    const uint32_t sl = s0 + 1 + (uint32_t)lane;
+    const uint32_t e = sl < S ? a.live[sl].tile0 : 0xffffffffu;
+    const uint32_t d = e - t0;
+    const uint64_t M = wave_or_dpp(d < 64u ? 1ull << d : 0ull);
+    const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1);
+    const uint32_t s = s0 + (uint32_t)__popcll(M & upto);
+    Seg sg = {};
+    if (valid) {
+      sg = a.live[s];
+      a.tmap[t] = sg;
+    }
+    const uint32_t j = t - sg.tile0;
+    head = valid && j == 0;
+    const bool counted = (sg.meta & META_PRE) != 0;
+    if (valid && counted) c = a.cnt_in[sg.cbase + j];
+    uint64_t todo = __ballot(valid && !counted);
+    while (todo) {
+      uint32_t who[RB], cnt[RB];
+      KT k[RB][IPT];
+      int bit[RB];
+      uint32_t f[RB];
+#pragma unroll
+      for (int u = 0; u < RB; ++u) {
+        who[u] = todo ? (uint32_t)(__ffsll((unsigned long long)todo) - 1) : 64u;
+        todo &= todo ? todo - 1 : 0ull;
+        const int wl = who[u] < 64u ? (int)who[u] : 0;
+        const uint32_t mt = (uint32_t)__builtin_amdgcn_readlane((int)sg.meta, wl);
+        const uint64_t st = (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)sg.start, wl) |
+                            ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(sg.start >> 32), wl) << 32);
+        const uint64_t ln = who[u] < 64u
+            ? ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)sg.len, wl) |
+               ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(sg.len >> 32), wl) << 32))
+            : 0ull;
+        const uint32_t jj = (uint32_t)__builtin_amdgcn_readlane((int)j, wl);
+        bit[u] = (int)(mt & BIT_MASK);
+        f[u] = (uint32_t)flip_of(bit[u], a.w, a.mode, a.desc, (mt & META_SIGN) ? 1 : 0);
+        tile_keys<KT, IPT>(a.keys[(mt & META_BUF) ? 1 : 0], st, ln, (uint64_t)jj * TILE, k[u], cnt[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < RB; ++u) {
+        uint32_t n = 0;
+#pragma unroll
+        for (int i = 0; i < IPT; ++i) {
+          const bool fr = (uint32_t)(i * 64 + lane) < cnt[u] &&
+                          ((((RT)k[u][i] >> bit[u]) & 1u) ^ f[u]) == 0;
+          n += (uint32_t)__popcll(__ballot(fr));
+        }
+        if ((uint32_t)lane == who[u]) c = n;
+      }
+    }
+  }
+  // exclusive scan of c over the chunk, restarting at segment starts
+  const uint32_t inc = wave_incl_scan_dpp(c);
+  const uint32_t exc = inc - c;
+  const uint64_t hm = __ballot(head);
+  const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1);
+  const uint64_t hb = hm & upto;
+  const int hl = hb ? 63 - __clzll((long long)hb) : -1;  // last segment start at or before the lane
+  uint32_t pre = exc - (hl >= 0 ? (uint32_t)__shfl((int)exc, hl) : 0u);
+  const int hlast = hm ? 63 - __clzll((long long)hm) : -1;
+  const uint32_t wtot = (uint32_t)__shfl((int)inc, 63);
+  const uint32_t wtail = wtot - (hlast >= 0 ? (uint32_t)__shfl((int)exc, hlast) : 0u);
+  if (lane == 0) {
+    s_tail[wave] = wtail;
+    s_hh[wave] = hm != 0;
+  }
+  __syncthreads();
+  if (hl < 0) {
+    // the segment started in an earlier wave (or chunk): add the earlier
+    // waves' fronts back to its start
+    uint32_t cw = 0;
+    for (int w2 = wave - 1; w2 >= 0; --w2) {
+      cw += s_tail[w2];
+      if (s_hh[w2]) break;
+    }
+    pre += cw;
+  }
+  if (valid) a.pc[t] = make_uint2(pre, c);
+  if (tid == 0) {
+    uint64_t A = 0;
+    bool hh = false;
+    for (int w2 = 3; w2 >= 0 && !hh; --w2) {
+      A += s_tail[w2];
+      hh = s_hh[w2] != 0;
+    }
+    a.agg[chunk] = A | (hh ? 1ull << 63 : 0ull);
+    __threadfence();
+    s_last = atomic_add_u32(&a.hdr->prep_ticket[a.level], 1u) == nchunks - 1;
+  }
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  // carry[0] = 0; carry[i + 1] = sum_i + (chunk i has a segment start ? 0 : carry[i]):
+  // per thread a run of chunks, then a scan of the runs' (restart, sum) pairs
+  constexpr uint64_t HEAD = 1ull << 63;
+  const uint32_t per = (nchunks + 255) / 256;
+  const uint32_t c0 = (uint32_t)tid * per, c1 = c0 + per < nchunks ? c0 + per : nchunks;
+  uint64_t v = 0;
+  uint32_t fl = 0;
+  for (uint32_t i = c0; i < c1; ++i) {
+    const uint64_t x = ld_relaxed(&a.agg[i]);
+    if (x & HEAD) {
+      fl = 1;
+      v = x & ~HEAD;
+    } else {
+      v += x;
+    }
+  }
+  s_v[tid] = v;
+  s_f[tid] = fl;
+  for (int dd = 1; dd < 256; dd <<= 1) {
+    __syncthreads();
+    const uint64_t pv = tid >= dd ? s_v[tid - dd] : 0ull;
+    const uint32_t pf = tid >= dd ? s_f[tid - dd] : 0u;
+    __syncthreads();
+    if (!fl) {
+      v += pv;
+      fl = pf;
+    }
+    s_v[tid] = v;
+    s_f[tid] = fl;
+  }
+  __syncthreads();
+  uint64_t cin = tid ? s_v[tid - 1] : 0ull;
+  for (uint32_t i = c0; i < c1; ++i) {
+    a.carry[i] = cin;
+    const uint64_t x = ld_relaxed(&a.agg[i]);
+    cin = (x & HEAD) ? (x & ~HEAD) : cin + x;
+  }
+}
+
+template <typename KT>
+struct LevelArgs {
+  KT *keys[2];             // key buffers 0 (the caller's) and 1 (scratch)
+  uint32_t *idx[2];        // the index buffers paired with them
+  const char *meta;        // scratch base: the per-level arrays of LevelMeta
+  LevelMeta off;
+  AccRep *acc;             // the replicas again, for the atomics
+  uint64_t *split;         // per segment slot: its front keys F (for the plan)
+  Header *hdr;
+  uint32_t *cnt_out;       // next level: front keys on bit - 1 per child tile
+  int w, mode, desc, level;
+};
+
+// A tile's registers, loaded one tile ahead of its use.
+template <typename KT, int IPT>
+struct WaveRegs {
+  uint32_t mw;        // lanes 8-15: its prefix words (see issue_tile)
+  KT key[IPT];
+  uint32_t ix[IPT];
+};
+
+// Uniform description of a tile, from its descriptor dwords (lanes 0-7).
+struct WaveTile {
   uint64_t start, len, lo;
-  uint32_t t, slot, meta, tile0, cbase, j, cnt;
+  uint32_t meta, tile0, cbase, slot, t, j, cnt, nt;
   bool valid;
 };
 
+// A wave's AND/OR of the keys of its current segment's two children, per
+// lane, carried across the wave's tiles while they belong to one segment
+// and folded into one of the segment's replicas when the segment changes
+// (once per wave and segment, not once per tile).
+template <typename RT>
+struct WaveAcc {
+  uint32_t slot;  // segment slot, or ~0 for none
+  uint32_t rep;   // replica entry the wave folds into
+  RT and_lo, or_lo, and_hi, or_hi;
+};
+
+__device__ __forceinline__ uint32_t rl(uint32_t v, int l) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
+}
+
+// The descriptor dword of tile t for lanes 0-7 (0 elsewhere or past the end).
+__device__ __forceinline__ uint32_t load_desc(rsrc_t mr, uint32_t off, uint32_t t, uint32_t ntiles) {
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t o = (t < ntiles && lane < 8u) ? off + t * (uint32_t)sizeof(Seg) + lane * 4u : ~0u;
+  return buf_load<uint32_t>(mr, o);
+}
+
 template <int TILE>
-__device__ __forceinline__ TileInfo tile_info(const Seg &sg, uint32_t t, uint32_t ntiles) {
-  TileInfo ti;
-  ti.t = uni(t);
-  ti.valid = ti.t < ntiles;
-  ti.start = uni(sg.start);
-  ti.len = uni(sg.len);
-  ti.meta = uni(sg.meta);
-  ti.tile0 = uni(sg.tile0);
-  ti.cbase = uni(sg.cbase);
-  ti.slot = uni(sg.slot);
-  ti.j = ti.t - ti.tile0;
-  ti.lo = (uint64_t)ti.j * TILE;
-  ti.cnt = ti.valid ? (uint32_t)((ti.len - ti.lo) < (uint64_t)TILE ? (ti.len - ti.lo) : (uint64_t)TILE)
-                    : 0u;
-  return ti;
+__device__ __forceinline__ WaveTile wave_tile(uint32_t dsc, uint32_t t, uint32_t ntiles) {
+  WaveTile w;
+  w.t = t;
+  w.valid = t < ntiles;
+  w.start = (uint64_t)rl(dsc, 0) | ((uint64_t)rl(dsc, 1) << 32);
+  w.len = (uint64_t)rl(dsc, 2) | ((uint64_t)rl(dsc, 3) << 32);
+  w.meta = rl(dsc, 4);
+  w.tile0 = rl(dsc, 5);
+  w.cbase = rl(dsc, 6);
+  w.slot = rl(dsc, 7);
+  w.j = t - w.tile0;
+  w.lo = (uint64_t)w.j * TILE;
+  w.cnt = w.valid ? (uint32_t)(w.len - w.lo < (uint64_t)TILE ? w.len - w.lo : (uint64_t)TILE) : 0u;
+  w.nt = (uint32_t)((w.len + TILE - 1) / TILE);
+  return w;
 }
 
-// A tile's data in registers, loaded one tile ahead of its use.
-template <typename KT, int IPT>
-struct TileRegs {
-  KT key[IPT];
-  uint32_t ix[IPT];
-  uint32_t pv0, pv1;  // front keys of earlier tiles: a group sum and a tile count
-  uint64_t pvx;       // the rest, for segments of more than BLOCK tile groups
-  uint32_t acd;       // lanes 0-7: one dword of the segment's child AND/OR words
-};
-
-// Control work is spread over waves so that no single wave waits on all of
-// it: thread 0 claims tiles, lane 0 of wave 1 updates the AND/OR replicas
-// and the split, lanes 0-3 of wave 2 add the next level's counts.
-constexpr int ACC_THREAD = 64;
-constexpr int CNT_WAVE = 2;
-
-
-// Every load is issued on every path -- an invalid tile or an index
-// that is an iota gets an empty range, whose reads return 0 without a
-// memory access -- so that the number of loads in flight does not depend on
-// the path and the compiler waits only for the loads a use needs (the
-// counter of outstanding loads retires in order).
-template <typename KT, bool IDX, int BLOCK, int IPT>
-__device__ __forceinline__ void issue_loads(const LevelArgs<KT> &a, const TileInfo &ti,
-                                            TileRegs<KT, IPT> &r) {
-  const int tid = threadIdx.x;
-  const bool v = ti.valid;
-  const bool rev = (ti.meta & META_REV) != 0;
-  const bool iota = (ti.meta & META_IOTA) != 0;
-  // front keys before this tile in its segment: the sums of the 64-tile
-  // groups before its group and the counts of its group's earlier tiles,
-  // one load per thread, summed only when the tile is ranked
-  const uint32_t js = v ? (ti.j >> 6) : 0u;
-  const uint32_t jt = v ? (ti.j & 63u) : 0u;
-  const rsrc_t gs = make_rsrc(LARG(scnt_in) + (v ? ti.cbase : 0u),
-                              (js < (uint32_t)BLOCK ? js : (uint32_t)BLOCK) * 4u);
-  const rsrc_t ts = make_rsrc(LARG(tcnt_in) + (v ? ti.cbase + (js << 6) : 0u), jt * 4u);
-  r.pv0 = buf_load<uint32_t>(gs, (uint32_t)tid * 4u);
-  r.pv1 = buf_load<uint32_t>(ts, (uint32_t)tid * 4u);
-  // the segment's child AND/OR words as they stand (for the atomics that
-  // the tile may skip): lanes 0-7 read one dword each, published in LDS
-  const uint32_t ai =
-      v ? ti.tile0 + ACC_STRIDE * (ti.j % acc_repl(ti.len, (uint32_t)(BLOCK * IPT))) : 0u;
-  const rsrc_t ar = make_rsrc(LARG(acc) + ai, v ? (uint32_t)sizeof(AccRep) : 0u);
-  r.acd = buf_load<uint32_t>(ar, (uint32_t)(tid & 63) * 4u);
-  // storage of the tile: [sbase, sbase + cnt); logical q is at sbase + q
-  // (forward) or sbase + cnt - 1 - q (reversed)
-  const uint64_t end = ti.start + ti.len;
-  const uint64_t sbase = v ? (rev ? (end - ti.lo - ti.cnt) : (ti.start + ti.lo)) : 0u;
-  const rsrc_t kr = make_rsrc(LARG(keys_in) + sbase, ti.cnt * (uint32_t)sizeof(KT));
-  const rsrc_t ir = make_rsrc(IDX ? LARG(idx_in) + sbase : nullptr, IDX && !iota ? ti.cnt * 4u : 0u);
+// Every load of a tile is issued on every path -- a tile past the end, an
+// index that is an iota, or a lane with nothing to fetch gets an empty range,
+// whose reads return 0 without a memory access -- so that the number of
+// loads in flight does not depend on the path and each use waits only for
+// its own loads (the counter of outstanding loads retires in order).
+// Lanes 8-15 fetch: 8-9 the tile's (prefix, count), 10-11 its chunk's carry,
+// 12-13 the (prefix, count) of the segment's last tile, 14-15 that tile's
+// chunk carry.
+template <typename KT, bool IDX, int IPT>
+__device__ __forceinline__ void issue_tile(const LevelArgs<KT> &a, rsrc_t mr, const WaveTile &w,
+                                           WaveRegs<KT, IPT> &r) {
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t L = w.tile0 + w.nt - 1;
+  // one selected offset per lane (selects, not branches)
+  const uint32_t odd = (lane & 1u) * 4u;
+  uint32_t o = ~0u;
+  o = lane - 8u < 2u ? a.off.pc + w.t * 8u + odd : o;
+  o = lane - 10u < 2u ? a.off.carry + (w.t / PREP_TILES) * 8u + odd : o;
+  o = lane - 12u < 2u ? a.off.pc + L * 8u + odd : o;
+  o = lane - 14u < 2u ? a.off.carry + (L / PREP_TILES) * 8u + odd : o;
+  o = w.valid ? o : ~0u;
+  r.mw = buf_load<uint32_t>(mr, o);
+  const bool iota = (w.meta & META_IOTA) != 0;
+  const int buf = (w.meta & META_BUF) ? 1 : 0;
+  const uint64_t sbase = w.valid ? w.start + w.lo : 0u;
+  const rsrc_t kr = make_rsrc(a.keys[buf] + sbase, w.cnt * (uint32_t)sizeof(KT));
+  const rsrc_t ir = make_rsrc(IDX ? a.idx[buf] + sbase : nullptr, IDX && !iota ? w.cnt * 4u : 0u);
 #pragma unroll
   for (int i = 0; i < IPT; ++i) {
-    const uint32_t q = (uint32_t)(i * BLOCK + tid);
-    const uint32_t o = rev ? (ti.cnt - 1 - q) : q;  // past cnt: out of range, reads 0
-    r.key[i] = buf_load<KT>(kr, o * (uint32_t)sizeof(KT));
-    if (IDX) r.ix[i] = buf_load<uint32_t>(ir, o * 4u);  // an iota is added at use
+    const uint32_t q = (uint32_t)(i * 64) + lane;  // past cnt: out of range, reads 0
+    r.key[i] = buf_load<KT>(kr, q * (uint32_t)sizeof(KT));
+    if (IDX) r.ix[i] = buf_load<uint32_t>(ir, q * 4u);  // an iota is added at use
   }
-  // segments of more than BLOCK groups: the remaining group sums (rare)
-  r.pvx = 0;
-  for (uint32_t s = (uint32_t)(BLOCK + tid); s < js; s += BLOCK) r.pvx += LARG(scnt_in)[ti.cbase + s];
 }
 
-template <int NCNT, int WAVES>
-struct LevelShared {
-  uint32_t cnt[NCNT];  // (item, wave) front counts, position order
-  uint64_t pw[WAVES];  // per-wave sums of the tile's prefix loads
-  uint32_t nxt[4];     // next-level front counts of the tile, by child tile
-  uint64_t red[4];     // child AND/OR of the tile
-  uint64_t acw[2][4];  // the segment's child AND/OR words as read, per tile slot
-  Seg seg[2];          // descriptors of the next tiles (double buffer)
-  uint32_t tile[2];
-};
-
-// Tiles are dealt out statically: workgroup b takes tiles b, b + G,
-// b + 2G, ... (G workgroups); tiles have equal sizes, so the work is even,
-// and no tile id has to come back from an atomic.  Lanes 0-7 of wave 0
-// fetch the descriptor of the tile after next, one dword each, and put it
-// in LDS at the end of the tile.
-struct Claim {
-  uint32_t t;   // the tile after next
-  uint32_t dw;  // lanes 0-7 of wave 0: one dword of its descriptor
-};
-__device__ __forceinline__ uint32_t seg_dword(const Seg *tiles, uint32_t t, uint32_t ntiles,
-                                             int lane) {
-  // lanes 8 and up, and tiles past the end, read 0 (out of range)
-  const rsrc_t r = make_rsrc(tiles + (t < ntiles ? t : 0u), t < ntiles ? (uint32_t)sizeof(Seg) : 0u);
-  return buf_load<uint32_t>(r, (uint32_t)lane * 4u);
+// Folds the wave's AND/OR words into its replica of the segment's children
+// and starts over.
+template <typename KT, typename RT>
+__device__ __forceinline__ void flush_acc(const LevelArgs<KT> &a, WaveAcc<RT> &acc) {
+  if (acc.slot != ~0u) {
+    uint64_t al, ol, ah, oh;
+    if (sizeof(RT) == 8) {
+      al = wave_and_dpp((uint64_t)acc.and_lo);
+      ol = wave_or_dpp((uint64_t)acc.or_lo);
+      ah = wave_and_dpp((uint64_t)acc.and_hi);
+      oh = wave_or_dpp((uint64_t)acc.or_hi);
+    } else {
+      al = (uint64_t)wave_and_dpp32((uint32_t)acc.and_lo) | (~0ull << 32);
+      ol = (uint64_t)wave_or_dpp32((uint32_t)acc.or_lo);
+      ah = (uint64_t)wave_and_dpp32((uint32_t)acc.and_hi) | (~0ull << 32);
+      oh = (uint64_t)wave_or_dpp32((uint32_t)acc.or_hi);
+    }
+    if ((threadIdx.x & 63) == 0) {
+      AccRep *ac = &a.acc[acc.rep];
+      if (al != ~0ull) atomic_and_u64(&ac->and_lo, al);
+      if (ol != 0) atomic_or_u64(&ac->or_lo, ol);
+      if (ah != ~0ull) atomic_and_u64(&ac->and_hi, ah);
+      if (oh != 0) atomic_or_u64(&ac->or_hi, oh);
+    }
+  }
+  acc.and_lo = (RT)~(RT)0;
+  acc.or_lo = 0;
+  acc.and_hi = (RT)~(RT)0;
+  acc.or_hi = 0;
 }
 
-// One tile.  The next tile's loads go out first (a whole tile ahead of
-// their use); then the tile is ranked and written, and the tile after next
-// is published for the following call.
-template <typename KT, bool IDX, int BLOCK, int IPT>
-__device__ __forceinline__ void level_tile(const LevelArgs<KT> &a, const TileInfo &ti,
-                                           TileRegs<KT, IPT> &r, TileInfo &tn,
-                                           TileRegs<KT, IPT> &rn,
-                                           LevelShared<IPT * (BLOCK / 64), BLOCK / 64> &sh,
-                                           int &cur, Claim &cin, Claim &cout, uint32_t ntiles) {
-  constexpr int WAVES = BLOCK / 64;
-  constexpr int TILE = BLOCK * IPT;
-  constexpr int NCNT = IPT * WAVES;
-  using RT = typename std::conditional<sizeof(KT) == 8, uint64_t, uint32_t>::type;
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  tn = tile_info<TILE>(sh.seg[cur ^ 1], sh.tile[cur ^ 1], ntiles);
-  issue_loads<KT, IDX, BLOCK, IPT>(a, tn, rn);
-  // the tile after next: its id and (lanes 0-7) its descriptor
-  cout.t = cin.t + gridDim.x;
-  cin.dw = seg_dword(LARG(tiles), cin.t, ntiles, lane);
+// The per-key work of a tile: rank each key on its side, store it (and its
+// index), fold it into its child's AND/OR words, and count the keys that go
+// front on the next bit per child tile.  NEAR: byte offsets from the
+// segment's start fit 32 bits (one descriptor per array); otherwise each of
+// the tile's two runs, which are far apart, gets its own.
+struct TileConsts {
+  uint32_t pf, pb;      // offset of the tile's first front / back key from its descriptor
+  uint32_t cnt, len32;  // keys in the tile; out-of-range offset for NEAR
+  uint32_t xf, xb;      // ranks from which a key lies in its child's following tile
+  uint32_t ibase;       // index of an iota input (position), or 0
+  int bit, nbit;
+  uint32_t f, fnf, fnb;
+  bool iota;
+};
 
-  const int bit = (int)(ti.meta & BIT_MASK);
-  const uint32_t f = (uint32_t)flip_of(bit, LARG(w), LARG(mode), LARG(desc), (ti.meta & META_SIGN) ? 1 : 0);
-  const uint32_t cnt = ti.cnt;
-  const uint64_t end = ti.start + ti.len;
-
-  uint32_t fbits = 0;  // bit i: item i goes front
-  RT and_lo = (RT)~(RT)0, or_lo = 0, and_hi = (RT)~(RT)0, or_hi = 0;
+template <bool NEAR, typename KT, bool IDX, int IPT, typename RT>
+__device__ __forceinline__ void tile_keys_pass(const WaveRegs<KT, IPT> &r, const TileConsts &c,
+                                               rsrc_t kwf, rsrc_t kwb, rsrc_t iwf, rsrc_t iwb,
+                                               uint32_t &cf, RT &and_lo, RT &or_lo, RT &and_hi,
+                                               RT &or_hi, uint32_t (&n)[4]) {
+  constexpr uint32_t TILE = 64 * IPT;
+  const uint32_t lane = threadIdx.x & 63;
 #pragma unroll
   for (int i = 0; i < IPT; ++i) {
-    const bool valid = (uint32_t)(i * BLOCK + tid) < cnt;
+    const uint32_t q = (uint32_t)(i * 64) + lane;
     const RT k = (RT)r.key[i];
-    const bool back = valid && ((((k >> bit) & 1u) ^ f) != 0);
-    const bool front = valid && !back;
+    const bool valid = q < c.cnt;
+    const bool front = valid && ((((k >> c.bit) & 1u) ^ c.f) == 0);
+    const bool back = valid && !front;
     const uint64_t fm = __ballot(front);
-    if (lane == 0) sh.cnt[i * WAVES + wave] = (uint32_t)__popcll(fm);
-    fbits |= (uint32_t)front << i;
+    const uint32_t r1 = cf + lanes_below(fm);
+    const uint32_t r2 = q - r1;
+    cf += (uint32_t)__popcll(fm);
+    // a lane past the tile's end stores out of range (dropped); so does,
+    // with two descriptors, the store of the other side
+    const uint32_t iv = r.ix[i] + c.ibase + (c.iota ? (uint32_t)(i * 64) : 0u);
+    if (NEAR) {
+      const uint32_t fs = 0u - (uint32_t)front, vs = 0u - (uint32_t)valid;
+      const uint32_t dst = ((((c.pf + r1) & fs) | ((c.pb + r2) & ~fs)) & vs) | (c.len32 & ~vs);
+      buf_store(kwf, dst * (uint32_t)sizeof(KT), r.key[i]);
+      if (IDX) buf_store(iwf, dst * 4u, iv);
+    } else {
+      const uint32_t of = front ? c.pf + r1 : TILE, ob = back ? c.pb + r2 : TILE;
+      buf_store(kwf, of * (uint32_t)sizeof(KT), r.key[i]);
+      buf_store(kwb, ob * (uint32_t)sizeof(KT), r.key[i]);
+      if (IDX) {
+        buf_store(iwf, of * 4u, iv);
+        buf_store(iwb, ob * 4u, iv);
+      }
+    }
     const RT mf = front ? (RT)~(RT)0 : (RT)0;
     const RT mb = back ? (RT)~(RT)0 : (RT)0;
     and_lo &= k | ~mf;
     or_lo |= k & mf;
     and_hi &= k | ~mb;
     or_hi |= k & mb;
-  }
-  {
-    uint64_t al, ol, ah, oh;
-    if (sizeof(KT) == 8) {
-      al = wave_and_dpp((uint64_t)and_lo);
-      ol = wave_or_dpp((uint64_t)or_lo);
-      ah = wave_and_dpp((uint64_t)and_hi);
-      oh = wave_or_dpp((uint64_t)or_hi);
-    } else {
-      al = (uint64_t)wave_and_dpp32((uint32_t)and_lo) | (~0ull << 32);
-      ol = (uint64_t)wave_or_dpp32((uint32_t)or_lo);
-      ah = (uint64_t)wave_and_dpp32((uint32_t)and_hi) | (~0ull << 32);
-      oh = (uint64_t)wave_or_dpp32((uint32_t)or_hi);
-    }
-    if (lane == 0) {
-      atomicAnd((unsigned long long *)&sh.red[0], (unsigned long long)al);
-      atomicOr((unsigned long long *)&sh.red[1], (unsigned long long)ol);
-      atomicAnd((unsigned long long *)&sh.red[2], (unsigned long long)ah);
-      atomicOr((unsigned long long *)&sh.red[3], (unsigned long long)oh);
-    }
-  }
-  {
-    // this wave's share of the tile's front prefix
-    const uint32_t ws =
-        (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan_dpp(r.pv0 + r.pv1), 63);
-    uint64_t wx = 0;
-    if ((ti.j >> 6) > (uint32_t)BLOCK) wx = wave_sum_u64(r.pvx);  // segments of > BLOCK groups
-    if (lane == 0) sh.pw[wave] = (uint64_t)ws + wx;
-  }
-  __syncthreads();
-
-  const uint32_t cv = lane < NCNT ? sh.cnt[lane] : 0u;
-  const uint32_t cinc = wave_incl_scan_dpp(cv);
-  const uint32_t c1 = (uint32_t)__builtin_amdgcn_readlane((int)cinc, 63);
-  uint64_t pacc = 0;
+    // next-level counts, per lane, split at the child tile boundary
+    const bool nf = valid && (((uint32_t)(k >> c.nbit) & 1u) == (front ? c.fnf : c.fnb));
+    const bool later = front ? r1 >= c.xf : r2 >= c.xb;
+    const uint32_t slot = (front ? 0u : 2u) + (later ? 1u : 0u);
 #pragma unroll
-  for (int w2 = 0; w2 < WAVES; ++w2) pacc += sh.pw[w2];
-  // the front flags are re-read from this register below: without the
-  // empty asm the compiler keeps every item's lane mask alive in scalar
-  // registers across the barrier, and spills
-  asm volatile("" : "+v"(fbits));
-  const uint64_t P1 = uni(pacc);
-  if (tid == ACC_THREAD) {
-    // An AND word only loses bits and an OR word only gains them, so an
-    // atomic whose value the (even stale) read already absorbs is skipped:
-    // big segments would otherwise send every tile's atomics to the same
-    // four words.
-    AccRep *ac = &LARG(acc)[ti.tile0 + ACC_STRIDE * (ti.j % acc_repl(ti.len, (uint32_t)TILE))];
-    const uint64_t al = sh.red[0], ol = sh.red[1], ah = sh.red[2], oh = sh.red[3];
-    sh.red[0] = ~0ull;
-    sh.red[1] = 0;
-    sh.red[2] = ~0ull;
-    sh.red[3] = 0;
-    const uint64_t *acw = sh.acw[cur];
-    if ((acw[0] & al) != acw[0]) atomic_and_u64(&ac->and_lo, al);
-    if ((acw[1] | ol) != acw[1]) atomic_or_u64(&ac->or_lo, ol);
-    if ((acw[2] & ah) != acw[2]) atomic_and_u64(&ac->and_hi, ah);
-    if ((acw[3] | oh) != acw[3]) atomic_or_u64(&ac->or_hi, oh);
-    if (ti.lo + cnt == ti.len) LARG(split)[ti.slot] = P1 + c1;
+    for (int z = 0; z < 4; ++z) n[z] += (nf && slot == (uint32_t)z) ? 1u : 0u;
   }
+}
 
-  const uint32_t c2 = cnt - c1;
-  const uint64_t P2 = ti.lo - P1;
-  const bool iota = (ti.meta & META_IOTA) != 0;
-  // Within the tile every front rank is below c1 and every back rank below
-  // c2; with P1 <= lo (no more fronts before the tile than keys) both runs
-  // lie inside the segment, so the per-lane stores below need no bounds.
-  // A prefix that broke this would be an internal error: the tile then
-  // writes nothing and the status word says so.
-  const bool sane = P1 <= ti.lo;
-  if (!sane && tid == ACC_THREAD) atomic_or_u32(&LARG(hdr)->status, STATUS_BAD_COUNTS);
-  const uint32_t wcnt = sane ? cnt : 0u;
-  uint32_t rk[IPT];  // rank within the key's own side of this tile
-  // index of an iota input: the tile position, added to the zero that the
-  // empty load range returned
-  const uint32_t ibase = iota ? (uint32_t)ti.lo + (uint32_t)tid : 0u;
-  if (ti.len <= (uint64_t)(0xffffffffu / (sizeof(KT) > 4 ? sizeof(KT) : 4))) {
-    // Byte offsets from the front run's start fit 32 bits: one uniform base
-    // per array and a 32-bit offset per lane.  A back key's place,
-    // len - 1 - P2 - r2, is at least len - lo - cnt + P1 >= P1 when the
-    // prefix is sane, so its offset does not wrap.
-    char *const kb = reinterpret_cast<char *>(LARG(keys_out) + ti.start + P1);
-    char *const ib = IDX ? reinterpret_cast<char *>(LARG(idx_out) + ti.start + P1) : nullptr;
-    const uint32_t dback = (uint32_t)(ti.len - 1 - P2 - P1);
-#pragma unroll
-    for (int i = 0; i < IPT; ++i) {
-      const uint32_t q = (uint32_t)(i * BLOCK + tid);
-      const bool front = (fbits >> i) & 1u;
-      const uint64_t fm = __ballot(front);
-      const uint32_t base = (uint32_t)__builtin_amdgcn_readlane((int)(cinc - cv), i * WAVES + wave);
-      const uint32_t r1 = base + lanes_below(fm);
-      const uint32_t r2 = q - r1;
-      if (q < wcnt) {
-        const uint32_t off = front ? r1 : dback - r2;
-        *reinterpret_cast<KT *>(kb + off * (uint32_t)sizeof(KT)) = r.key[i];
-        if (IDX)
-          *reinterpret_cast<uint32_t *>(ib + off * 4u) =
-              r.ix[i] + ibase + (iota ? (uint32_t)(i * BLOCK) : 0u);
-      }
-      rk[i] = front ? r1 : r2;
-    }
+template <typename KT, bool IDX, int IPT, typename RT>
+__device__ __forceinline__ void process_tile(const LevelArgs<KT> &a, const WaveTile &w,
+                                             const WaveRegs<KT, IPT> &r, WaveAcc<RT> &acc,
+                                             uint32_t wave_id) {
+  constexpr uint32_t TILE = 64 * IPT;
+  const uint32_t lane = threadIdx.x & 63;
+  if (!w.valid) return;
+  if (w.slot != acc.slot) {
+    flush_acc<KT, RT>(a, acc);
+    acc.slot = w.slot;
+    acc.rep = w.tile0 + ACC_STRIDE * (wave_id & (acc_repl(w.len, TILE) - 1));
+  }
+  TileConsts c;
+  c.bit = (int)(w.meta & BIT_MASK);
+  c.f = (uint32_t)flip_of(c.bit, a.w, a.mode, a.desc, (w.meta & META_SIGN) ? 1 : 0);
+  // the tile's front prefix P and the segment's front total F
+  const uint32_t h = w.tile0 / PREP_TILES;
+  const uint32_t L = w.tile0 + w.nt - 1;
+  const uint32_t c_t = rl(r.mw, 9);
+  const uint64_t car_t = (uint64_t)rl(r.mw, 10) | ((uint64_t)rl(r.mw, 11) << 32);
+  const uint64_t car_L = (uint64_t)rl(r.mw, 14) | ((uint64_t)rl(r.mw, 15) << 32);
+  const uint64_t P = (uint64_t)rl(r.mw, 8) + (w.t / PREP_TILES != h ? car_t : 0ull);
+  const uint64_t F = (uint64_t)rl(r.mw, 12) + rl(r.mw, 13) + (L / PREP_TILES != h ? car_L : 0ull);
+  const bool moved = F != 0 && F != w.len;
+  c.iota = (w.meta & META_IOTA) != 0;
+  const int out = (w.meta & META_BUF) ? 0 : 1;
+  const uint64_t B0 = w.lo - P;  // back keys before the tile (with a sane prefix)
+  c.ibase = c.iota ? (uint32_t)w.lo + lane : 0u;
+  c.cnt = w.cnt;
+  c.len32 = (uint32_t)w.len;
+  // next level (bit - 1): a child's keys have the segment's sign, or their
+  // side's when this level splits the sign bit
+  c.nbit = c.bit > 0 ? c.bit - 1 : 0;
+  uint32_t sgn_f = (w.meta & META_SIGN) ? 1u : 0u, sgn_b = sgn_f;
+  if (c.bit == a.w - 1) {
+    sgn_f = c.f;
+    sgn_b = 1u - c.f;
+  }
+  c.fnf = (uint32_t)a.desc ^ (uint32_t)(a.mode == MODE_F && sgn_f);
+  c.fnb = (uint32_t)a.desc ^ (uint32_t)(a.mode == MODE_F && sgn_b);
+  c.xf = (uint32_t)((P / TILE + 1) * TILE - P);
+  c.xb = (uint32_t)((B0 / TILE + 1) * TILE - B0);
+  uint32_t n[4] = {0, 0, 0, 0};
+  uint32_t cf = 0;  // front keys so far in the tile
+  RT and_lo = acc.and_lo, or_lo = acc.or_lo, and_hi = acc.and_hi, or_hi = acc.or_hi;
+  // Descriptors are bounded to the segment, so that no store can leave it,
+  // and empty when the split has an empty side.
+  if (w.len * (sizeof(KT) > 4 ? sizeof(KT) : 4) < (1ull << 32)) {
+    const uint32_t rg = moved ? (uint32_t)w.len : 0u;
+    const rsrc_t kw = make_rsrc(a.keys[out] + w.start, rg * (uint32_t)sizeof(KT));
+    const rsrc_t iw = make_rsrc(IDX ? a.idx[out] + w.start : nullptr, IDX ? rg * 4u : 0u);
+    c.pf = (uint32_t)P;
+    c.pb = (uint32_t)(F + B0);
+    tile_keys_pass<true, KT, IDX, IPT, RT>(r, c, kw, kw, iw, iw, cf, and_lo, or_lo, and_hi, or_hi, n);
   } else {
-    KT *const kseg = LARG(keys_out) + ti.start;
-    uint32_t *const iseg = IDX ? LARG(idx_out) + ti.start : nullptr;
+    const uint64_t fo = P < w.len ? P : w.len, bo = F + B0 < w.len ? F + B0 : w.len;
+    const uint32_t fr = moved ? (uint32_t)((w.len - fo) < TILE ? (w.len - fo) : TILE) : 0u;
+    const uint32_t br = moved ? (uint32_t)((w.len - bo) < TILE ? (w.len - bo) : TILE) : 0u;
+    const rsrc_t kwf = make_rsrc(a.keys[out] + w.start + fo, fr * (uint32_t)sizeof(KT));
+    const rsrc_t kwb = make_rsrc(a.keys[out] + w.start + bo, br * (uint32_t)sizeof(KT));
+    const rsrc_t iwf = make_rsrc(IDX ? a.idx[out] + w.start + fo : nullptr, IDX ? fr * 4u : 0u);
+    const rsrc_t iwb = make_rsrc(IDX ? a.idx[out] + w.start + bo : nullptr, IDX ? br * 4u : 0u);
+    c.pf = 0;
+    c.pb = 0;
+    tile_keys_pass<false, KT, IDX, IPT, RT>(r, c, kwf, kwb, iwf, iwb, cf, and_lo, or_lo, and_hi,
+                                            or_hi, n);
+  }
+  acc.and_lo = and_lo;
+  acc.or_lo = or_lo;
+  acc.and_hi = and_hi;
+  acc.or_hi = or_hi;
+  // counts that broke the prefix would be an internal error: the status
+  // word says so (the stores above stayed inside the segment regardless)
+  const bool sane = cf == c_t && P <= w.lo && P + cf <= F && F + B0 + (w.cnt - cf) <= w.len;
+  uint32_t v = 0;
 #pragma unroll
-    for (int i = 0; i < IPT; ++i) {
-      const uint32_t q = (uint32_t)(i * BLOCK + tid);
-      const bool front = (fbits >> i) & 1u;
-      const uint64_t fm = __ballot(front);
-      const uint32_t base = (uint32_t)__builtin_amdgcn_readlane((int)(cinc - cv), i * WAVES + wave);
-      const uint32_t r1 = base + lanes_below(fm);
-      const uint32_t r2 = q - r1;
-      // front key of tile rank r1 -> P1 + r1 in the segment; back key of
-      // tile back rank r2 -> len - 1 - P2 - r2 (the back child runs right to
-      // left).  One store per array, per-lane addresses: each wave's front
-      // lanes and back lanes write two contiguous runs, which L2 merges.
-      if (q < wcnt) {
-        const uint64_t rel = front ? (P1 + r1) : (ti.len - 1 - P2 - r2);
-        kseg[rel] = r.key[i];
-        if (IDX) iseg[rel] = r.ix[i] + ibase + (iota ? (uint32_t)(i * BLOCK) : 0u);
-      }
-      rk[i] = front ? r1 : r2;
-    }
+  for (int z = 0; z < 4; ++z) {
+    const uint32_t tz = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan_dpp(n[z]), 63);
+    v = lane == (uint32_t)z ? tz : v;
   }
-
-  // next level (bit - 1): for each child tile it will read, the number of
-  // keys that go front.  A child's keys have the segment's sign, or their
-  // side's when this level splits the sign bit.
-  const bool nxt = bit > 0;
-  if (nxt) {
-    const int nbit = bit - 1;
-    uint32_t sgn_f = (ti.meta & META_SIGN) ? 1u : 0u, sgn_b = sgn_f;
-    if (bit == LARG(w) - 1) {
-      sgn_f = f;
-      sgn_b = 1u - f;
-    }
-    const uint32_t fnf = (uint32_t)LARG(desc) ^ (uint32_t)(LARG(mode) == MODE_F && sgn_f);
-    const uint32_t fnb = (uint32_t)LARG(desc) ^ (uint32_t)(LARG(mode) == MODE_F && sgn_b);
-    // ranks from which a key lies in its child's following tile
-    const uint32_t xf = (uint32_t)((P1 / TILE + 1) * TILE - P1);
-    const uint32_t xb = (uint32_t)((P2 / TILE + 1) * TILE - P2);
-    uint32_t n0 = 0, n1 = 0, n2 = 0, n3 = 0;
-#pragma unroll
-    for (int i = 0; i < IPT; ++i) {
-      const bool valid = (uint32_t)(i * BLOCK + tid) < cnt;
-      const uint32_t front = (fbits >> i) & 1u;
-      const uint32_t nb = (uint32_t)(((RT)r.key[i] >> nbit) & 1u);
-      const bool nf = valid && nb == (front ? fnf : fnb);
-      const bool later = rk[i] >= (front ? xf : xb);
-      const uint64_t fm = __ballot(front);
-      const uint64_t nfm = __ballot(nf);
-      const uint64_t lm = __ballot(later);
-      n0 += (uint32_t)__popcll(nfm & fm & ~lm);
-      n1 += (uint32_t)__popcll(nfm & fm & lm);
-      n2 += (uint32_t)__popcll(nfm & ~fm & ~lm);
-      n3 += (uint32_t)__popcll(nfm & ~fm & lm);
-    }
-    if (lane == 0) {
-      if (n0) atomicAdd(&sh.nxt[0], n0);
-      if (n1) atomicAdd(&sh.nxt[1], n1);
-      if (n2) atomicAdd(&sh.nxt[2], n2);
-      if (n3) atomicAdd(&sh.nxt[3], n3);
-    }
+  if (lane < 4u && c.bit > 0 && sane && v) {
+    // child c's tile jj of the next level counts at 2 * tile0 + c * nt + jj
+    const uint32_t base = (lane >> 1) ? 2 * w.tile0 + w.nt : 2 * w.tile0;
+    const uint32_t jj = (uint32_t)(((lane >> 1) ? B0 : P) / TILE) + (lane & 1u);
+    atomic_add_u32(&a.cnt_out[base + jj], v);
   }
-  if (wave == 0) {
-    // publish the tile after next into this tile's slot (this tile's
-    // descriptor was read at the start of the previous call), and the next
-    // tile's AND/OR words into its slot
-    if (lane == 0) sh.tile[cur] = cin.t;
-    if (lane < 8) {
-      reinterpret_cast<uint32_t *>(&sh.seg[cur])[lane] = cin.dw;
-      reinterpret_cast<uint32_t *>(sh.acw[cur ^ 1])[lane] = rn.acd;
-    }
+  if (lane == 0) {
+    if (!sane) atomic_or_u32(&a.hdr->status, STATUS_BAD_COUNTS);
+    if (w.j == 0) a.split[w.slot] = F;
   }
-  __syncthreads();
-  if (nxt && wave == CNT_WAVE && lane < 4) {
-    // child c's tile j of the next level counts at 2*tile0 + c*nt + j
-    // (added only with a sane prefix, from which P2 and the index derive)
-    const int k = lane;
-    const uint32_t c = sh.nxt[k];
-    sh.nxt[k] = 0;
-    const uint32_t nt = (uint32_t)((ti.len + TILE - 1) / TILE);
-    const uint32_t base = (k >> 1) ? 2 * ti.tile0 + nt : 2 * ti.tile0;
-    const uint32_t jj = (uint32_t)(((k >> 1) ? P2 : P1) / TILE) + (uint32_t)(k & 1);
-    if (c && sane) {
-      atomic_add_u32(&LARG(tcnt_out)[base + jj], c);
-      atomic_add_u32(&LARG(scnt_out)[base + (jj >> 6)], c);
-    }
-  }
-  cur ^= 1;
 }
 
-// One global level: every live segment is split on its bit.  Workgroups
-// take tiles in increasing order (claimed two tiles ahead, loaded one tile
-// ahead).  A tile's front offset inside its segment comes from the counts
-// that the previous level (or the count pass) produced for this bit: the
-// sum over the tile's 64-tile group predecessors plus its own group's
-// earlier tiles.  Segments whose bit was reached by skipping are counted by
-// the count pass before the level.  Front keys go to start + prefix, back
-// keys are placed from the segment's right end leftwards, so the back child
-// is stored reversed.  While writing, each tile also counts, for every
-// child tile of the next level, how many keys will go front on bit - 1
-// (the usual next bit).
-template <typename KT, bool IDX, int BLOCK, int IPT>
-__global__ __launch_bounds__(BLOCK) void level_kernel(LevelArgs<KT> a) {
-  constexpr int WAVES = BLOCK / 64;
-  constexpr int TILE = BLOCK * IPT;
-  constexpr int NCNT = IPT * WAVES;
-  static_assert(NCNT <= 64, "one count per lane in the per-wave scan");
-  static_assert(WAVES > CNT_WAVE && BLOCK > ACC_THREAD, "control lanes exist");
-  __shared__ LevelShared<NCNT, WAVES> sh;
-  const int tid = threadIdx.x;
+// One global level.  Waves take tiles t = g, g + G, g + 2G, ... (G waves in
+// the grid).  A tile's descriptor is fetched two tiles ahead and its counts
+// and keys one tile ahead of its use.
+template <typename KT, bool IDX, int IPT>
+__global__ __launch_bounds__(256) void level_kernel(LevelArgs<KT> a) {
+  constexpr int TILE = 64 * IPT;
+  using RT = typename std::conditional<sizeof(KT) == 8, uint64_t, uint32_t>::type;
   const uint32_t ntiles = (uint32_t)(a.hdr->packed[a.level] & 0xffffffffu);
-
-  Claim ca, cb;
-  const uint32_t t0 = blockIdx.x, t1 = blockIdx.x + gridDim.x;
-  ca.t = blockIdx.x + 2 * gridDim.x;
-  cb.t = 0;
-  ca.dw = cb.dw = 0;
-  if (tid < 8) {
-    reinterpret_cast<uint32_t *>(&sh.seg[0])[tid] = seg_dword(a.tiles, t0, ntiles, tid);
-    reinterpret_cast<uint32_t *>(&sh.seg[1])[tid] = seg_dword(a.tiles, t1, ntiles, tid);
-  }
-  if (tid == 0) {
-    sh.tile[0] = t0;
-    sh.tile[1] = t1;
-    sh.nxt[0] = sh.nxt[1] = sh.nxt[2] = sh.nxt[3] = 0;
-    sh.red[0] = ~0ull;
-    sh.red[1] = 0;
-    sh.red[2] = ~0ull;
-    sh.red[3] = 0;
-  }
-  __syncthreads();
-  int cur = 0;
-  TileInfo ta = tile_info<TILE>(sh.seg[0], sh.tile[0], ntiles), tb;
-  TileRegs<KT, IPT> ra, rb;
-  issue_loads<KT, IDX, BLOCK, IPT>(a, ta, ra);
-  if (tid < 8) reinterpret_cast<uint32_t *>(sh.acw[0])[tid] = ra.acd;  // seen after the first barrier
+  const rsrc_t mr = make_rsrc(a.meta, a.off.range);
+  const uint32_t G = gridDim.x * 4u;
+  const uint32_t g = uni(blockIdx.x * 4u + (threadIdx.x >> 6));
+  uint32_t t = g;
+  WaveAcc<RT> acc;
+  acc.slot = ~0u;
+  acc.rep = 0;
+  acc.and_lo = (RT)~(RT)0;
+  acc.or_lo = 0;
+  acc.and_hi = (RT)~(RT)0;
+  acc.or_hi = 0;
+  uint32_t dA = load_desc(mr, a.off.tmap, t, ntiles);
+  uint32_t dB = load_desc(mr, a.off.tmap, t + G, ntiles);
+  WaveTile A = wave_tile<TILE>(dA, t, ntiles), B;
+  WaveRegs<KT, IPT> rA, rB;
+  issue_tile<KT, IDX, IPT>(a, mr, A, rA);
   for (;;) {
-    if (!ta.valid) break;
-    level_tile<KT, IDX, BLOCK, IPT>(a, ta, ra, tb, rb, sh, cur, ca, cb, ntiles);
-    if (!tb.valid) break;
-    level_tile<KT, IDX, BLOCK, IPT>(a, tb, rb, ta, ra, sh, cur, cb, ca, ntiles);
+    if (!A.valid) break;
+    const uint32_t dC = load_desc(mr, a.off.tmap, t + 2 * G, ntiles);
+    B = wave_tile<TILE>(dB, t + G, ntiles);
+    issue_tile<KT, IDX, IPT>(a, mr, B, rB);
+    process_tile<KT, IDX, IPT, RT>(a, A, rA, acc, g);
+    if (!B.valid) break;
+    dB = load_desc(mr, a.off.tmap, t + 3 * G, ntiles);
+    A = wave_tile<TILE>(dC, t + 2 * G, ntiles);
+    issue_tile<KT, IDX, IPT>(a, mr, A, rA);
+    process_tile<KT, IDX, IPT, RT>(a, B, rB, acc, g);
+    t += 2 * G;
   }
-}
-
-// Before each level: (1) the per-tile descriptor map of the level, one
-// thread per tile finding its segment by binary search over the live list
-// (which is in tile order); (2) the front keys of every tile of the
-// segments on the recount list -- level-0 segments and segments that
-// reached their bit by skipping -- since the previous level counted only
-// bit - 1.  With these, no tile of the level waits for another.
-template <typename KT>
-struct CountArgs {
-  const KT *keys;
-  const Seg *live;
-  const Seg *rec;
-  Seg *tiles;
-  Header *hdr;
-  uint32_t *tcnt;
-  uint32_t *scnt;
-  int w, mode, desc, level;
-};
-
-template <typename KT, int BLOCK, int IPT>
-__global__ __launch_bounds__(BLOCK) void count_kernel(CountArgs<KT> a) {
-  constexpr int WAVES = BLOCK / 64;
-  constexpr int TILE = BLOCK * IPT;
-  __shared__ uint32_t s_w[WAVES];
-  __shared__ Seg s_rs;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const uint64_t pk = a.hdr->packed[a.level];
-  const uint32_t S = (uint32_t)(pk >> 32), ntiles = (uint32_t)pk;
-  for (uint32_t t = blockIdx.x * BLOCK + tid; t < ntiles; t += gridDim.x * BLOCK) {
-    uint32_t lo = 0, hi = S - 1;
-    while (lo < hi) {
-      const uint32_t mid = (lo + hi + 1) >> 1;
-      if (a.live[mid].tile0 <= t) lo = mid;
-      else hi = mid - 1;
-    }
-    a.tiles[t] = a.live[lo];
-  }
-
-  const uint64_t rk = a.hdr->rec_packed[a.level];
-  const uint32_t R = (uint32_t)(rk >> 32), rtiles = (uint32_t)rk;
-  for (uint32_t u = blockIdx.x; u < rtiles; u += gridDim.x) {
-    if (tid == 0) {
-      uint32_t lo = 0, hi = R - 1;
-      while (lo < hi) {
-        const uint32_t mid = (lo + hi + 1) >> 1;
-        if (a.rec[mid].slot <= u) lo = mid;
-        else hi = mid - 1;
-      }
-      s_rs = a.rec[lo];
-    }
-    __syncthreads();
-    const uint64_t start = uni(s_rs.start), len = uni(s_rs.len);
-    const uint32_t meta = uni(s_rs.meta), cbase = uni(s_rs.cbase);
-    const uint32_t j = u - uni(s_rs.slot);
-    const int bit = (int)(meta & BIT_MASK);
-    const uint32_t f = (uint32_t)flip_of(bit, a.w, a.mode, a.desc, (meta & META_SIGN) ? 1 : 0);
-    const uint64_t lo = (uint64_t)j * TILE;
-    const uint32_t cnt = (uint32_t)((len - lo) < (uint64_t)TILE ? (len - lo) : (uint64_t)TILE);
-    // the tile's keys as a set: [start+lo, +cnt) forward, [end-lo-cnt, +cnt) reversed
-    const uint64_t sbase = (meta & META_REV) ? (start + len - lo - cnt) : (start + lo);
-    const rsrc_t kr = make_rsrc(a.keys + sbase, cnt * (uint32_t)sizeof(KT));
-    uint32_t c = 0;
-#pragma unroll
-    for (int i = 0; i < IPT; ++i) {
-      const uint32_t q = (uint32_t)(i * BLOCK + tid);
-      const uint64_t k = (uint64_t)buf_load<KT>(kr, q * (uint32_t)sizeof(KT));
-      c += (q < cnt) && ((((k >> bit) & 1ull) ^ (uint64_t)f) == 0);
-    }
-    c = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan_dpp(c), 63);
-    if (lane == 0) s_w[wave] = c;
-    __syncthreads();
-    if (tid == 0) {
-      uint32_t sum = 0;
-#pragma unroll
-      for (int w2 = 0; w2 < WAVES; ++w2) sum += s_w[w2];
-      a.tcnt[cbase + j] = sum;
-      if (sum) atomic_add_u32(&a.scnt[cbase + (j >> 6)], sum);
-    }
-    __syncthreads();
-  }
+  flush_acc<KT, RT>(a, acc);
 }
 
 // ------------------------------------------------------------- LDS finish
@@ -1216,12 +1265,10 @@ void finish_kernel(FinishArgs<KT> a) {
     const uint32_t len = (uint32_t)(slen < (uint64_t)T ? slen : (uint64_t)T);
     const uint32_t meta = uni(s_seg.meta);
     const int bit0 = (int)(meta & BIT_MASK);
-    const bool rev = (meta & META_REV) != 0;
     const bool iota = (meta & META_IOTA) != 0;
     const int buf = (meta & META_BUF) ? 1 : 0;
     if (tid == 0 && slen > (uint64_t)T) atomic_or_u32(&a.hdr->status, STATUS_OVERSIZE);
 
-    // logical position p is at sbase + p (forward) or sbase + len - 1 - p
     const rsrc_t kr = make_rsrc(a.keys_buf[buf] + start, len * (uint32_t)sizeof(KT));
     const rsrc_t ir = make_rsrc(IDX ? a.idx_buf[buf] + start : nullptr, IDX && !iota ? len * 4u : 0u);
     RT u[IPT];
@@ -1229,7 +1276,7 @@ void finish_kernel(FinishArgs<KT> a) {
 #pragma unroll
     for (int i = 0; i < IPT; ++i) {
       const uint32_t p = (uint32_t)(i * BLOCK + tid);
-      const uint32_t o = rev ? (len - 1 - p) : p;  // past len: out of range, reads 0
+      const uint32_t o = p;  // past len: out of range, reads 0
       u[i] = (RT)rank_word<KT>(buf_load<KT>(kr, o * (uint32_t)sizeof(KT)), a.w, a.mode, a.desc);
       ix[i] = 0;
       if (IDX) ix[i] = iota ? p : buf_load<uint32_t>(ir, o * 4u);
@@ -1448,8 +1495,9 @@ struct CopyArgs {
 };
 
 // Retired segments larger than the finish threshold whose data is not yet
-// final (in scratch, stored right to left, or needing 64-bit indices).  All
-// keys of a retired segment are the same pattern, so keys are filled.
+// final: in scratch, or with indices not yet in the caller's buffer (still
+// the identity, or to be widened).  All keys of a retired segment are the
+// same pattern, so keys are filled.
 template <typename KT, bool IDX>
 __global__ void copy_kernel(CopyArgs<KT> a) {
   const uint32_t nc = a.hdr->n_copy;
@@ -1457,24 +1505,22 @@ __global__ void copy_kernel(CopyArgs<KT> a) {
   const uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   for (uint32_t e = 0; e < nc; ++e) {
     const Seg s = a.list[e];
-    const bool rev = (s.meta & META_REV) != 0;
+    const bool iota = (s.meta & META_IOTA) != 0;
     const int buf = (s.meta & META_BUF) ? 1 : 0;
     if (buf) {
       const KT kv = a.keys_buf[1][s.start];
       for (uint64_t i = i0; i < s.len; i += stride) a.keys_final[s.start + i] = kv;
     }
     if (!IDX) continue;
-    if (buf == 0 && rev && !a.idx64) {
-      uint32_t *x = a.idx_buf[0] + s.start;
-      for (uint64_t i = i0; i < s.len / 2; i += stride) {
-        const uint32_t u = x[i], v = x[s.len - 1 - i];
-        x[i] = v;
-        x[s.len - 1 - i] = u;
+    if (iota) {
+      for (uint64_t i = i0; i < s.len; i += stride) {
+        if (a.idx64) static_cast<int64_t *>(a.idx_final)[s.start + i] = (int64_t)i;
+        else static_cast<uint32_t *>(a.idx_final)[s.start + i] = (uint32_t)i;
       }
-    } else {
+    } else if (buf || a.idx64) {
       const uint32_t *src = a.idx_buf[buf] + s.start;
       for (uint64_t i = i0; i < s.len; i += stride) {
-        const uint32_t v = src[rev ? (s.len - 1 - i) : i];
+        const uint32_t v = src[i];
         if (a.idx64) static_cast<int64_t *>(a.idx_final)[s.start + i] = (int64_t)v;
         else static_cast<uint32_t *>(a.idx_final)[s.start + i] = v;
       }
@@ -1559,24 +1605,6 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *s_w, u
   __syncthreads();
   total = tot;
   return before + inc - v;
-}
-
-// Largest i in [0, n) with le(i), for a predicate that holds on a prefix of
-// [0, n) and at 0: a 64-ary search by one whole wave (every lane probes one
-// point per round), so a search over 2^14 entries takes three dependent
-// loads instead of fourteen.  All 64 lanes must call it.
-template <typename Le>
-__device__ __forceinline__ uint32_t wave_search_le(uint32_t n, Le le) {
-  const uint32_t lane = threadIdx.x & 63;
-  uint32_t lo = 0, hi = n - 1;
-  while (lo < hi) {
-    const uint32_t step = (hi - lo + 64) / 64;
-    const uint32_t idx = lo + lane * step;
-    const uint64_t ok = __ballot(idx <= hi && le(idx));
-    lo += ((uint32_t)__popcll(ok) - 1) * step;
-    hi = lo + step - 1 < hi ? lo + step - 1 : hi;
-  }
-  return lo;
 }
 
 // Position of the r-th key (from 0, in position order) of the given side
