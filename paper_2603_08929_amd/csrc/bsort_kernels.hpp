@@ -994,16 +994,24 @@ template <bool NEAR, typename KT, bool IDX, int IPT, typename RT>
 __device__ __forceinline__ void tile_keys_pass(const WaveRegs<KT, IPT> &r, const TileConsts &c,
                                                rsrc_t kwf, rsrc_t kwb, rsrc_t iwf, rsrc_t iwb,
                                                uint32_t &cf, RT &and_lo, RT &or_lo, RT &and_hi,
-                                               RT &or_hi, uint32_t (&n)[4]) {
+                                               RT &or_hi, uint32_t &nfr, uint32_t &nbk) {
   constexpr uint32_t TILE = 64 * IPT;
   const uint32_t lane = threadIdx.x & 63;
+  // A key goes front when its bit equals the flip f: with bm the bit spread
+  // over the word (0 or all ones), the front mask is bm XNOR (f ? ~0 : 0)
+  // -- selects and masks, no branches
+  const RT fx = c.f ? (RT)0 : (RT)~(RT)0;
+  const uint32_t xs0 = c.xf, xs1 = c.xb;
 #pragma unroll
   for (int i = 0; i < IPT; ++i) {
     const uint32_t q = (uint32_t)(i * 64) + lane;
     const RT k = (RT)r.key[i];
-    const bool valid = q < c.cnt;
-    const bool front = valid && ((((k >> c.bit) & 1u) ^ c.f) == 0);
-    const bool back = valid && !front;
+    const RT vm = q < c.cnt ? (RT)~(RT)0 : (RT)0;
+    const RT bm = (RT)0 - (RT)((k >> c.bit) & 1u);
+    const RT mf = (bm ^ fx) & vm;   // front key
+    const RT mb = ~(bm ^ fx) & vm;  // back key
+    const bool front = mf != 0;
+    const bool valid = vm != 0;
     const uint64_t fm = __ballot(front);
     const uint32_t r1 = cf + lanes_below(fm);
     const uint32_t r2 = q - r1;
@@ -1012,12 +1020,11 @@ __device__ __forceinline__ void tile_keys_pass(const WaveRegs<KT, IPT> &r, const
     // with two descriptors, the store of the other side
     const uint32_t iv = r.ix[i] + c.ibase + (c.iota ? (uint32_t)(i * 64) : 0u);
     if (NEAR) {
-      const uint32_t fs = 0u - (uint32_t)front, vs = 0u - (uint32_t)valid;
-      const uint32_t dst = ((((c.pf + r1) & fs) | ((c.pb + r2) & ~fs)) & vs) | (c.len32 & ~vs);
+      const uint32_t dst = valid ? (front ? c.pf + r1 : c.pb + r2) : c.len32;
       buf_store(kwf, dst * (uint32_t)sizeof(KT), r.key[i]);
       if (IDX) buf_store(iwf, dst * 4u, iv);
     } else {
-      const uint32_t of = front ? c.pf + r1 : TILE, ob = back ? c.pb + r2 : TILE;
+      const uint32_t of = front ? c.pf + r1 : TILE, ob = (valid && !front) ? c.pb + r2 : TILE;
       buf_store(kwf, of * (uint32_t)sizeof(KT), r.key[i]);
       buf_store(kwb, ob * (uint32_t)sizeof(KT), r.key[i]);
       if (IDX) {
@@ -1025,18 +1032,18 @@ __device__ __forceinline__ void tile_keys_pass(const WaveRegs<KT, IPT> &r, const
         buf_store(iwb, ob * 4u, iv);
       }
     }
-    const RT mf = front ? (RT)~(RT)0 : (RT)0;
-    const RT mb = back ? (RT)~(RT)0 : (RT)0;
     and_lo &= k | ~mf;
     or_lo |= k & mf;
     and_hi &= k | ~mb;
     or_hi |= k & mb;
-    // next-level counts, per lane, split at the child tile boundary
-    const bool nf = valid && (((uint32_t)(k >> c.nbit) & 1u) == (front ? c.fnf : c.fnb));
-    const bool later = front ? r1 >= c.xf : r2 >= c.xb;
-    const uint32_t slot = (front ? 0u : 2u) + (later ? 1u : 0u);
-#pragma unroll
-    for (int z = 0; z < 4; ++z) n[z] += (nf && slot == (uint32_t)z) ? 1u : 0u;
+    // next-level counts per lane, two 16-bit fields a side: keys before and
+    // after the child tile boundary
+    const uint32_t nb = (uint32_t)(k >> c.nbit) & 1u;
+    const bool nf = valid && nb == (front ? c.fnf : c.fnb);
+    const uint32_t rk = front ? r1 : r2;
+    const uint32_t inc = nf ? (rk >= (front ? xs0 : xs1) ? 0x10000u : 1u) : 0u;
+    nfr += front ? inc : 0u;
+    nbk += front ? 0u : inc;
   }
 }
 
@@ -1082,7 +1089,7 @@ __device__ __forceinline__ void process_tile(const LevelArgs<KT> &a, const WaveT
   c.fnb = (uint32_t)a.desc ^ (uint32_t)(a.mode == MODE_F && sgn_b);
   c.xf = (uint32_t)((P / TILE + 1) * TILE - P);
   c.xb = (uint32_t)((B0 / TILE + 1) * TILE - B0);
-  uint32_t n[4] = {0, 0, 0, 0};
+  uint32_t nfr = 0, nbk = 0;
   uint32_t cf = 0;  // front keys so far in the tile
   RT and_lo = acc.and_lo, or_lo = acc.or_lo, and_hi = acc.and_hi, or_hi = acc.or_hi;
   // Descriptors are bounded to the segment, so that no store can leave it,
@@ -1093,7 +1100,8 @@ __device__ __forceinline__ void process_tile(const LevelArgs<KT> &a, const WaveT
     const rsrc_t iw = make_rsrc(IDX ? a.idx[out] + w.start : nullptr, IDX ? rg * 4u : 0u);
     c.pf = (uint32_t)P;
     c.pb = (uint32_t)(F + B0);
-    tile_keys_pass<true, KT, IDX, IPT, RT>(r, c, kw, kw, iw, iw, cf, and_lo, or_lo, and_hi, or_hi, n);
+    tile_keys_pass<true, KT, IDX, IPT, RT>(r, c, kw, kw, iw, iw, cf, and_lo, or_lo, and_hi, or_hi,
+                                           nfr, nbk);
   } else {
     const uint64_t fo = P < w.len ? P : w.len, bo = F + B0 < w.len ? F + B0 : w.len;
     const uint32_t fr = moved ? (uint32_t)((w.len - fo) < TILE ? (w.len - fo) : TILE) : 0u;
@@ -1105,7 +1113,7 @@ __device__ __forceinline__ void process_tile(const LevelArgs<KT> &a, const WaveT
     c.pf = 0;
     c.pb = 0;
     tile_keys_pass<false, KT, IDX, IPT, RT>(r, c, kwf, kwb, iwf, iwb, cf, and_lo, or_lo, and_hi,
-                                            or_hi, n);
+                                            or_hi, nfr, nbk);
   }
   acc.and_lo = and_lo;
   acc.or_lo = or_lo;
@@ -1114,12 +1122,11 @@ __device__ __forceinline__ void process_tile(const LevelArgs<KT> &a, const WaveT
   // counts that broke the prefix would be an internal error: the status
   // word says so (the stores above stayed inside the segment regardless)
   const bool sane = cf == c_t && P <= w.lo && P + cf <= F && F + B0 + (w.cnt - cf) <= w.len;
-  uint32_t v = 0;
-#pragma unroll
-  for (int z = 0; z < 4; ++z) {
-    const uint32_t tz = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan_dpp(n[z]), 63);
-    v = lane == (uint32_t)z ? tz : v;
-  }
+  // wave totals: at most 64 * IPT per field, so the 16-bit halves do not carry
+  const uint32_t tf = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan_dpp(nfr), 63);
+  const uint32_t tb = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan_dpp(nbk), 63);
+  const uint32_t tsel = (lane >> 1) ? tb : tf;
+  const uint32_t v = (lane & 1u) ? (tsel >> 16) : (tsel & 0xffffu);
   if (lane < 4u && c.bit > 0 && sane && v) {
     // child c's tile jj of the next level counts at 2 * tile0 + c * nt + jj
     const uint32_t base = (lane >> 1) ? 2 * w.tile0 + w.nt : 2 * w.tile0;
