@@ -149,9 +149,9 @@ size_t up256(size_t x) { return (x + 255) & ~(size_t)255; }
 // it there).  Bounds: a live segment holds more than T keys (at least 2
 // with BSORT_NO_FINISH); a level's tiles are at most n/TILE + segments;
 // every parent yields at most two finish entries per level; copy entries
-// hold more than T keys each.  The small per-level arrays come first: the
-// level kernel reads them through one buffer descriptor with 32-bit
-// offsets (`meta` bytes from the start).
+// hold more than T keys each.  The level kernel reads the per-tile prefix
+// words and the chunk carries through one buffer descriptor with 32-bit
+// offsets (`meta` bytes from the start of pc).
 struct Layout {
   size_t hdr, cnts, segs[2], acc[2], split[2], tmap, pc, agg, carry, fin, fins, fint, finm, cpy,
       meta, keys1, idx0, idx1, keys0, total;
@@ -179,10 +179,10 @@ bool make_layout(int key_bytes, uint64_t n, uint64_t B, bool with_idx, uint32_t 
   for (int i = 0; i < 2; ++i) { L->acc[i] = off; off = up256(off + L->tmax * sizeof(AccRep)); }
   for (int i = 0; i < 2; ++i) { L->split[i] = off; off = up256(off + L->smax * 8); }
   L->tmap = off; off = up256(off + L->tmax * sizeof(Seg));
-  L->pc = off; off = up256(off + L->tmax * 8);
   L->agg = off; off = up256(off + L->nchunks * 8);
+  L->pc = off; off = up256(off + L->tmax * 8);
   L->carry = off; off = up256(off + L->nchunks * 8);
-  L->meta = off;
+  L->meta = off - L->pc;  // bytes of pc and carry, read through one 32-bit descriptor
   L->fin = off; off = up256(off + L->fmax * sizeof(Seg));
   L->fins = off; off = up256(off + L->fmax * sizeof(Seg));
   L->fint = off; off = up256(off + L->fmax * sizeof(Seg));
@@ -325,11 +325,10 @@ int launch_all(KT *keys, uint64_t n, const int64_t *offsets, uint64_t B, int mod
     a.keys[1] = kbuf[1];
     a.idx[0] = ibuf[0];
     a.idx[1] = ibuf[1];
-    a.meta = scr;
-    a.off.tmap = (uint32_t)L.tmap;
-    a.off.pc = (uint32_t)L.pc;
-    a.off.carry = (uint32_t)L.carry;
-    a.off.acc = (uint32_t)L.acc[lvl & 1];
+    a.tmap = tmap;
+    a.meta = scr + L.pc;
+    a.off.pc = 0;
+    a.off.carry = (uint32_t)(L.carry - L.pc);
     a.off.range = (uint32_t)L.meta;
     a.acc = acc[lvl & 1];
     a.split = split[lvl & 1];

@@ -639,13 +639,11 @@ __global__ void plan_kernel(PlanArgs a) {
 
 constexpr int PREP_TILES = 256;  // level tiles per prep workgroup: a chunk
 
-// Byte offsets, from the base of the scratch buffer, of the per-level arrays
-// a level tile reads with per-lane buffer loads (one descriptor covers all).
+// The per-tile prefix words a level tile reads with per-lane buffer loads:
+// one descriptor covers both arrays (byte offsets from the first).
 struct LevelMeta {
-  uint32_t tmap;   // Seg per tile
   uint32_t pc;     // uint2 per tile: (front keys of its segment before it in its chunk, its front keys)
   uint32_t carry;  // uint64 per chunk: front keys of the segment open at its start, before it
-  uint32_t acc;    // AccRep replicas of the level
   uint32_t range;  // bytes the descriptor covers
 };
 
@@ -845,7 +843,8 @@ template <typename KT>
 struct LevelArgs {
   KT *keys[2];             // key buffers 0 (the caller's) and 1 (scratch)
   uint32_t *idx[2];        // the index buffers paired with them
-  const char *meta;        // scratch base: the per-level arrays of LevelMeta
+  const Seg *tmap;         // per tile: its segment's descriptor (from the prep pass)
+  const char *meta;        // base of the prefix arrays of LevelMeta
   LevelMeta off;
   AccRep *acc;             // the replicas again, for the atomics
   uint64_t *split;         // per segment slot: its front keys F (for the plan)
@@ -885,10 +884,11 @@ __device__ __forceinline__ uint32_t rl(uint32_t v, int l) {
 }
 
 // The descriptor dword of tile t for lanes 0-7 (0 elsewhere or past the end).
-__device__ __forceinline__ uint32_t load_desc(rsrc_t mr, uint32_t off, uint32_t t, uint32_t ntiles) {
+__device__ __forceinline__ uint32_t load_desc(const Seg *tmap, uint32_t t, uint32_t ntiles) {
   const uint32_t lane = threadIdx.x & 63;
-  const uint32_t o = (t < ntiles && lane < 8u) ? off + t * (uint32_t)sizeof(Seg) + lane * 4u : ~0u;
-  return buf_load<uint32_t>(mr, o);
+  const bool v = t < ntiles;
+  const rsrc_t r = make_rsrc(tmap + (v ? t : 0u), v ? (uint32_t)sizeof(Seg) : 0u);
+  return buf_load<uint32_t>(r, lane < 8u ? lane * 4u : ~0u);
 }
 
 template <int TILE>
@@ -1158,19 +1158,19 @@ __global__ __launch_bounds__(256) void level_kernel(LevelArgs<KT> a) {
   acc.or_lo = 0;
   acc.and_hi = (RT)~(RT)0;
   acc.or_hi = 0;
-  uint32_t dA = load_desc(mr, a.off.tmap, t, ntiles);
-  uint32_t dB = load_desc(mr, a.off.tmap, t + G, ntiles);
+  uint32_t dA = load_desc(a.tmap, t, ntiles);
+  uint32_t dB = load_desc(a.tmap, t + G, ntiles);
   WaveTile A = wave_tile<TILE>(dA, t, ntiles), B;
   WaveRegs<KT, IPT> rA, rB;
   issue_tile<KT, IDX, IPT>(a, mr, A, rA);
   for (;;) {
     if (!A.valid) break;
-    const uint32_t dC = load_desc(mr, a.off.tmap, t + 2 * G, ntiles);
+    const uint32_t dC = load_desc(a.tmap, t + 2 * G, ntiles);
     B = wave_tile<TILE>(dB, t + G, ntiles);
     issue_tile<KT, IDX, IPT>(a, mr, B, rB);
     process_tile<KT, IDX, IPT, RT>(a, A, rA, acc, g);
     if (!B.valid) break;
-    dB = load_desc(mr, a.off.tmap, t + 3 * G, ntiles);
+    dB = load_desc(a.tmap, t + 3 * G, ntiles);
     A = wave_tile<TILE>(dC, t + 2 * G, ntiles);
     issue_tile<KT, IDX, IPT>(a, mr, A, rA);
     process_tile<KT, IDX, IPT, RT>(a, B, rB, acc, g);
