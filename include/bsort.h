@@ -139,6 +139,28 @@ int bsort_segmented_i32(int32_t *keys, const int64_t *offsets, uint64_t num_segm
                         size_t scratch_bytes, void *stream);
 
 /*
+ * The sort stopped after its first `levels` global levels, for checking the
+ * per-level property of Theorem 3's induction (after the k most significant
+ * bits, the array is ordered by its k-bit prefix; Algorithm 2's recursion
+ * run breadth first).  Runs the BSORT_PLAIN path (forced on, whatever flags
+ * say: every bit is a partition of every part of two keys or more), splits
+ * every part on bits w-1 .. w-levels of the order key (the inverse direction
+ * on the sign pass of signed and float keys, and on the lower bits of
+ * negative floats, as in Algorithms 3-5), and writes the array as it then
+ * stands to keys and indices: ordered by the top `levels` bits of the order
+ * key, keys with an equal prefix in input order.  levels = 0 writes the
+ * input and the identity permutation; levels = w is the full sort.  offsets
+ * NULL sorts one array of n keys (num_segments ignored), else as
+ * bsort_segmented.  Scratch as for the full sort
+ * (bsort_scratch_bytes(key_bytes, n, offsets ? num_segments : 1,
+ * indices != NULL, flags | BSORT_PLAIN)).  levels outside [0, w] returns
+ * BSORT_EINVAL; other arguments and errors as bsort_sort / bsort_segmented.
+ */
+int bsort_levels(void *keys, int key_type, int key_bytes, const int64_t *offsets,
+                 uint64_t num_segments, uint64_t n, uint32_t flags, int levels, void *indices,
+                 void *scratch, size_t scratch_bytes, void *stream);
+
+/*
  * Allocation-free form of bsort_segmented, for callers that cannot allocate
  * device memory or pass a workspace: code recorded under HIP graph capture,
  * tight serving loops, harnesses that forbid hipMalloc.  Same arguments,

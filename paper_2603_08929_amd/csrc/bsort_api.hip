@@ -219,7 +219,7 @@ uint32_t clamp_grid(uint64_t want, uint64_t cap) {
 template <typename KT, bool IDX, int LV, int FV>
 int launch_all(KT *keys, uint64_t n, const int64_t *offsets, uint64_t B, int mode,
                uint32_t flags, void *indices, char *scr, const Layout &L, int cus, int half,
-               hipStream_t st) {
+               hipStream_t st, int stop) {
   using LS = LevelShape<KT, LV>;
   using FS = FinishShape<KT, FV>;
   const uint64_t gdiv = half ? 2 : 1;
@@ -302,7 +302,11 @@ int launch_all(KT *keys, uint64_t n, const int64_t *offsets, uint64_t B, int mod
   // A single array that fits the LDS finish never has a live segment: the
   // seed hands it straight to the finish, so the level passes and the copy
   // would all find empty lists.
-  const int levels = (!offsets && !no_finish && n <= FS::TFIN) ? 0 : w;
+  int levels = (!offsets && !no_finish && n <= FS::TFIN) ? 0 : w;
+  // a stop before the last level: the level-`stop` live segments are
+  // written out as they stand (bsort_levels)
+  const bool snapshot = stop < levels;
+  if (snapshot) levels = stop;
   for (int lvl = 0; lvl < levels; ++lvl) {
     PrepArgs<KT> ca;
     ca.keys[0] = kbuf[0];
@@ -366,6 +370,22 @@ int launch_all(KT *keys, uint64_t n, const int64_t *offsets, uint64_t B, int mod
     pa.no_finish = no_finish;
     pa.inplace = 0;
     hipLaunchKernelGGL(plan_kernel, dim3(pgrid), dim3(256), 0, st, pa);
+  }
+
+  if (snapshot) {
+    SnapArgs<KT> sn;
+    sn.keys_buf[0] = kbuf[0];
+    sn.keys_buf[1] = kbuf[1];
+    sn.idx_buf[0] = ibuf[0];
+    sn.idx_buf[1] = ibuf[1];
+    sn.keys_final = keys;
+    sn.idx_final = indices;
+    sn.live = segs[levels & 1];
+    sn.hdr = hdr;
+    sn.level = levels;
+    sn.tile = LS::TILE;
+    sn.idx64 = idx64;
+    hipLaunchKernelGGL((snapshot_kernel<KT, IDX>), dim3(lgrid), dim3(256), 0, st, sn);
   }
 
   CopyArgs<KT> ca;
@@ -453,11 +473,11 @@ int choose_config(int dev, int key_bytes, bool with_idx, uint64_t n, uint64_t B)
 template <typename KT, bool IDX>
 int launch_cfg(const Config &c, KT *k, uint64_t n, const int64_t *off, uint64_t b, int mode,
                uint32_t flags, void *indices, char *scr, const Layout &L, int cus,
-               hipStream_t st) {
+               hipStream_t st, int stop) {
 #define BSORT_CFG(LV, FV)                                                                    \
   case LV * 3 + FV:                                                                          \
     return launch_all<KT, IDX, LV, FV>(k, n, off, b, mode, flags, indices, scr, L, cus,      \
-                                       c.grid, st)
+                                       c.grid, st, stop)
   switch (c.lv * 3 + c.fv) {
     BSORT_CFG(0, 0);
     BSORT_CFG(0, 1);
@@ -473,7 +493,7 @@ int launch_cfg(const Config &c, KT *k, uint64_t n, const int64_t *off, uint64_t 
 template <typename KT>
 int run(void *keys, uint64_t n, const int64_t *offsets, uint64_t B, bool segmented, int mode,
         uint32_t flags, void *indices, void *scratch, size_t scratch_bytes, void *stream,
-        int force_config) {
+        int force_config, int stop) {
   if (flags & ~ALL_FLAGS) return BSORT_EINVAL;
   if (segmented && B > 0 && !offsets) return BSORT_EINVAL;
   if (segmented && B == 0 && n != 0) return BSORT_EINVAL;
@@ -511,28 +531,29 @@ int run(void *keys, uint64_t n, const int64_t *offsets, uint64_t B, bool segment
     if (e != hipSuccess) return hip_fail(e, "key copy");
   }
   const int64_t *off = segmented ? offsets : nullptr;
-  if (with_idx) return launch_cfg<KT, true>(c, k, n, off, b, mode, flags, indices, scr, L, cus, st);
-  return launch_cfg<KT, false>(c, k, n, off, b, mode, flags, indices, scr, L, cus, st);
+  if (with_idx)
+    return launch_cfg<KT, true>(c, k, n, off, b, mode, flags, indices, scr, L, cus, st, stop);
+  return launch_cfg<KT, false>(c, k, n, off, b, mode, flags, indices, scr, L, cus, st, stop);
 }
 
 int dispatch(void *keys, int key_type, int key_bytes, uint64_t n, const int64_t *offsets,
              uint64_t B, bool segmented, uint32_t flags, void *indices, void *scratch,
-             size_t scratch_bytes, void *stream, int force_config = -1) {
+             size_t scratch_bytes, void *stream, int force_config = -1, int stop = 64) {
   if (key_type != BSORT_KEY_U && key_type != BSORT_KEY_I && key_type != BSORT_KEY_F)
     return BSORT_EINVAL;
   switch (key_bytes) {
     case 1:
       return run<uint8_t>(keys, n, offsets, B, segmented, key_type, flags, indices, scratch,
-                          scratch_bytes, stream, force_config);
+                          scratch_bytes, stream, force_config, stop);
     case 2:
       return run<uint16_t>(keys, n, offsets, B, segmented, key_type, flags, indices, scratch,
-                           scratch_bytes, stream, force_config);
+                           scratch_bytes, stream, force_config, stop);
     case 4:
       return run<uint32_t>(keys, n, offsets, B, segmented, key_type, flags, indices, scratch,
-                           scratch_bytes, stream, force_config);
+                           scratch_bytes, stream, force_config, stop);
     case 8:
       return run<uint64_t>(keys, n, offsets, B, segmented, key_type, flags, indices, scratch,
-                           scratch_bytes, stream, force_config);
+                           scratch_bytes, stream, force_config, stop);
     default:
       return BSORT_EINVAL;
   }
@@ -1092,6 +1113,15 @@ int bsort_segmented(void *keys, int key_type, int key_bytes, const int64_t *offs
                     void *scratch, size_t scratch_bytes, void *stream) {
   return dispatch(keys, key_type, key_bytes, n, offsets, num_segments, true, flags, indices,
                   scratch, scratch_bytes, stream);
+}
+
+int bsort_levels(void *keys, int key_type, int key_bytes, const int64_t *offsets,
+                 uint64_t num_segments, uint64_t n, uint32_t flags, int levels, void *indices,
+                 void *scratch, size_t scratch_bytes, void *stream) {
+  if (levels < 0 || levels > 8 * key_bytes) return BSORT_EINVAL;
+  const bool seg = offsets != nullptr;
+  return dispatch(keys, key_type, key_bytes, n, offsets, seg ? num_segments : 1, seg,
+                  flags | BSORT_PLAIN, indices, scratch, scratch_bytes, stream, -1, levels);
 }
 
 #define BSORT_TYPED(name, T, kt, kb)                                                        \

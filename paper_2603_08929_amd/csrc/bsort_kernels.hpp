@@ -1535,6 +1535,53 @@ __global__ void copy_kernel(CopyArgs<KT> a) {
   }
 }
 
+// --------------------------------------------------------- level snapshot
+//
+// The per-level property of Theorem 3's induction (after the k most
+// significant bits, the array is ordered by its k-bit prefix) made visible:
+// a sort stopped after `level` global levels leaves every live segment of
+// that level in the buffer its meta names, its indices possibly still the
+// identity.  One wave per level tile writes the tile's keys and indices to
+// the caller's buffers; retired segments reach them through the copy and
+// finish lists as in a full sort.
+template <typename KT>
+struct SnapArgs {
+  const KT *keys_buf[2];
+  const uint32_t *idx_buf[2];
+  KT *keys_final;
+  void *idx_final;
+  const Seg *live;  // the live list of level `level`, in tile order
+  const Header *hdr;
+  int level;
+  uint32_t tile;    // keys per level tile
+  int idx64;
+};
+
+template <typename KT, bool IDX>
+__global__ __launch_bounds__(256) void snapshot_kernel(SnapArgs<KT> a) {
+  const uint64_t pk = a.hdr->packed[a.level];
+  const uint32_t S = (uint32_t)(pk >> 32), ntiles = (uint32_t)pk;
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t G = gridDim.x * 4;
+  for (uint32_t t = blockIdx.x * 4 + (threadIdx.x >> 6); t < ntiles; t += G) {
+    const uint32_t s = wave_search_le(S, [&](uint32_t i) { return a.live[i].tile0 <= t; });
+    const Seg sg = a.live[s];
+    const uint64_t lo = (uint64_t)(t - sg.tile0) * a.tile;
+    const uint64_t hi = lo + a.tile < sg.len ? lo + a.tile : sg.len;
+    const int buf = (sg.meta & META_BUF) ? 1 : 0;
+    const bool iota = (sg.meta & META_IOTA) != 0;
+    for (uint64_t q = lo + lane; q < hi; q += 64) {
+      const uint64_t p = sg.start + q;
+      if (buf) a.keys_final[p] = a.keys_buf[1][p];
+      if (IDX && (iota || buf || a.idx64)) {
+        const uint32_t v = iota ? (uint32_t)q : a.idx_buf[buf][p];
+        if (a.idx64) static_cast<int64_t *>(a.idx_final)[p] = (int64_t)v;
+        else static_cast<uint32_t *>(a.idx_final)[p] = v;
+      }
+    }
+  }
+}
+
 // ------------------------------------------------------- in-place levels
 //
 // A keys-only variant whose scratch is O(n / tile): each level partitions

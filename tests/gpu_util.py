@@ -104,3 +104,49 @@ def gpu_segmented(name: str, bits: np.ndarray, lengths, asc: bool = True, flags:
 def oracle_sort(name: str, bits: np.ndarray, asc: bool = True):
     k, i = oracle.sort_dtype(bits.astype(np.uint64), name, asc=asc)
     return k.astype(DTYPES[name][2]), i
+
+
+def gpu_levels(name: str, bits: np.ndarray, levels: int, asc: bool = True, idx: str = "u32",
+               lengths=None):
+    """The sort stopped after `levels` global levels (bsort_levels), one array
+    or back-to-back segments of the given lengths.  Returns (keys as raw
+    patterns, indices as int64 numpy or None)."""
+    n = bits.size
+    keys = to_device(bits, name)
+    fl = _lib.PLAIN | (0 if asc else _lib.DESCENDING)
+    ind = None
+    if idx == "u32":
+        ind = torch.empty(n, dtype=torch.int32, device="cuda")
+    elif idx == "i64":
+        ind = torch.empty(n, dtype=torch.int64, device="cuda")
+        fl |= _lib.IDX64
+    offsets, B = None, 1
+    if lengths is not None:
+        offs = np.concatenate([[0], np.cumsum(np.asarray(lengths, dtype=np.int64))])
+        assert offs[-1] == n
+        offsets = torch.from_numpy(offs).to("cuda")
+        B = len(lengths)
+    need = _lib.bsort_scratch_bytes(key_bytes(name), n, B, int(ind is not None), fl)
+    scratch = torch.empty(max(need, 256), dtype=torch.uint8, device="cuda")
+    rc = _lib.bsort_levels(keys.data_ptr(), FAMILY[DTYPES[name][1]], key_bytes(name),
+                           offsets.data_ptr() if offsets is not None else None, B, n, fl,
+                           levels, ind.data_ptr() if ind is not None else None,
+                           scratch.data_ptr(), scratch.numel(), stream())
+    _lib.check(rc, "bsort_levels")
+    torch.cuda.synchronize()
+    status = _lib.bsort_device_status(scratch.data_ptr(), stream()) if n else 0
+    assert status == 0, f"device status {status}"
+    out_i = None
+    if ind is not None:
+        out_i = ind.cpu().numpy()
+        out_i = (out_i.view(np.uint32).astype(np.int64) if idx == "u32" else out_i)
+    return from_device(keys, name), out_i
+
+
+def oracle_snapshots(name: str, bits: np.ndarray, asc: bool = True):
+    """The oracle's breadth-first snapshots: row d is the array after every
+    partition on the top d bits.  Returns (keys (w+1, n), idx (w+1, n))."""
+    w, mode, mant = oracle.DTYPES[name]
+    _, _, snap, snap_i = oracle.sort(bits.astype(np.uint64), w, mode, asc=asc, mant_bits=mant,
+                                     snapshots=True)
+    return snap.astype(DTYPES[name][2]), snap_i

@@ -298,3 +298,15 @@ def test_noalloc_validation_before_any_device_work():
     assert _lib.bsort_scratch_bytes(4, n, 1, 1, 0) > cap
     assert f(fake, _lib.KEY_U, 4, fake, 1, n, 0, fake, None) == _lib.ENOSPACE
     assert "allocation-free" in _lib.strerror(_lib.ENOSPACE)
+
+
+def test_levels_validation_before_any_device_work():
+    """bsort_levels: a level count outside [0, w] is refused, n = 0 succeeds
+    with null pointers -- before a device is queried."""
+    f = _lib.bsort_levels
+    fake = 1 << 40
+    assert f(None, _lib.KEY_U, 4, None, 1, 0, 0, 3, None, None, 0, None) == _lib.OK
+    for kb, bad in ((1, 9), (2, 17), (4, 33), (8, 65), (4, -1)):
+        assert f(fake, _lib.KEY_U, kb, None, 1, 10, 0, bad, None, fake, 1 << 30,
+                 None) == _lib.EINVAL, (kb, bad)
+    assert f(fake, _lib.KEY_U, 3, None, 1, 10, 0, 1, None, fake, 1 << 30, None) == _lib.EINVAL
