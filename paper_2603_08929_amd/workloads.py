@@ -90,6 +90,41 @@ def plant_specials(bits: np.ndarray, name: str, frac: float, seed: int) -> np.nd
     return out
 
 
+def plant_nans(bits: np.ndarray, name: str, frac: float, seed: int) -> np.ndarray:
+    """Overwrite frac*n seeded positions with NaN patterns: all exponent bits
+    set, a nonzero random mantissa (quiet and signalling payloads alike), a
+    random sign."""
+    w, fam, raw, _ = DTYPES[name]
+    assert fam == "F"
+    mant = {"f16": 10, "bf16": 7, "f32": 23, "f64": 52, "e5m2": 2}[name]
+    n = bits.size
+    m = int(round(frac * n))
+    if m == 0:
+        return bits
+    rng = np.random.default_rng(seed)
+    out = bits.copy()
+    pos = rng.choice(n, size=m, replace=False)
+    one = np.uint64(1)
+    sign = one << np.uint64(w - 1)
+    expo_all = ((one << np.uint64(w - 1 - mant)) - one) << np.uint64(mant)
+    payload = rng.integers(1, 1 << mant, size=m, dtype=np.uint64)
+    signs = np.where(rng.integers(0, 2, m) == 1, sign, np.uint64(0))
+    out[pos] = (expo_all | payload | signs).astype(raw)
+    return out
+
+
+def all_patterns(name: str, dup_frac: float, seed: int) -> np.ndarray:
+    """Every bit pattern of an 8- or 16-bit dtype once, plus dup_frac * 2^w
+    seeded repeats, in a seeded random order."""
+    w, _, raw, _ = DTYPES[name]
+    assert w <= 16
+    rng = np.random.default_rng(seed)
+    every = np.arange(1 << w, dtype=np.uint64)
+    extra = rng.integers(0, 1 << w, size=int(dup_frac * (1 << w)), dtype=np.uint64)
+    out = np.concatenate([every, extra])
+    return out[rng.permutation(out.size)].astype(raw)
+
+
 def heavy_duplicates_u32(n: int, seed: int) -> np.ndarray:
     return np.random.default_rng(seed).integers(0, 16, size=n, dtype=np.uint32)
 
