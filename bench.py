@@ -20,7 +20,10 @@ key and index: 2 * (4 + 4) bytes; level 0 reads no index: 4 + 4 + 4).
 WRITE_SIZE counters measured for this kernel (committed summary under
 profiles/, scaled by the same counters' reading of a plain 1 GiB copy), or
 null if the kernel sources changed since.
-`cpu_baseline` times the oracle (single thread) on a prefix sample.
+`cpu_baseline` times the oracle on the host: the stable flavour on the seven
+whole arrays on one pinned core (the value), the Lomuto flavour beside it on
+another, and a pinned thread pool over the 4096-array batch and the rows
+of the differentiable sort; host CPU model and core count included.
 
 The other workloads are reported beside the headline (`extras`, skipped
 with --no-extras): the word-size sweep (8-, 16- and 64-bit keys at 2^28 /
@@ -635,6 +638,136 @@ def extras_backward(lib, torch, np, dev, stream):
     return out
 
 
+# ---------------------------------------------------------------- CPU baseline
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def pinned_thread(core, body):
+    """Start body() on a thread pinned to one host core (sched_setaffinity
+    with pid 0 applies to the calling thread only)."""
+    import threading
+
+    def run():
+        os.sched_setaffinity(0, {core})
+        body()
+
+    t = threading.Thread(target=run)
+    t.start()
+    return t
+
+
+def oracle_pool(jobs, cores):
+    """Sort every (bits, dtype name, ascending) job with the stable oracle on
+    one thread per core, each pinned, largest jobs first; wall seconds."""
+    import queue
+    import oracle
+    q = queue.Queue()
+    for j in sorted(jobs, key=lambda j: -j[0].size):
+        q.put(j)
+
+    def worker():
+        while True:
+            try:
+                bits, name, asc = q.get_nowait()
+            except queue.Empty:
+                return
+            oracle.sort_dtype(bits, name, asc=asc)
+
+    t0 = time.perf_counter()
+    ts = [pinned_thread(c, worker) for c in cores]
+    for t in ts:
+        t.join()
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(arrays, pool: bool, batch=None, rows=None):
+    """The oracle as it stands, on the host's cores, beside the GPU figure.
+      - value: the stable flavour (keys + stable indices: the GPU's work) on
+        every whole array of the headline workload, one after the other on
+        one thread pinned to one core;
+      - lomuto: the in-place keys-only flavour (Algorithm 1's exchange) on
+        the same whole arrays, at the same time on a second pinned core;
+      - pool (the batch of 4096 arrays and the rows of the differentiable
+        sort): the stable flavour over all arrays or rows at once, one
+        pinned thread per available core (at most 16).
+    arrays: (label, dtype name, raw bits, descending)."""
+    import numpy as np
+    import oracle
+    from paper_2603_08929_amd import workloads as W
+    avail = sorted(os.sched_getaffinity(0))
+    keys = sum(int(a[2].size) for a in arrays)
+    log(f"oracle: {len(arrays)} whole arrays, stable and Lomuto, pinned to cores "
+        f"{avail[0]} and {avail[-1]}")
+    times = {"stable": [], "lomuto": []}
+
+    def flavour(kind):
+        def body():
+            for (label, name, bits, desc) in arrays:
+                w, mode, mant = oracle.DTYPES[name]
+                u = bits.astype(np.uint64)
+                t = time.perf_counter()
+                if kind == "stable":
+                    oracle.sort(u, w, mode, asc=not desc, mant_bits=mant, flavour=oracle.STABLE)
+                else:
+                    oracle.sort(u, w, mode, asc=not desc, mant_bits=mant, flavour=oracle.LOMUTO,
+                                with_idx=False)
+                times[kind].append(time.perf_counter() - t)
+        return body
+
+    ts = [pinned_thread(avail[0], flavour("stable")),
+          pinned_thread(avail[-1], flavour("lomuto"))]
+    for t in ts:
+        t.join()
+    st, lo = sum(times["stable"]), sum(times["lomuto"])
+    same = len(avail) == 1
+    out = {"value": round(keys / st / 1e9, 6), "unit": "Gkeys/s", "cores": 1,
+           "kind": "oracle",
+           "sample": f"the {len(arrays)} whole arrays of {arrays[0][2].size} keys, keys + "
+                     f"stable indices, stable oracle on one pinned core, {st:.1f} s"
+                     + (" (sharing its core with the Lomuto run)" if same else
+                        " (the Lomuto run beside it on another core)"),
+           "host": {"cpu_model": cpu_model(), "cores_available": len(avail),
+                    "os_cpu_count": os.cpu_count()},
+           "per_array_s": {a[0]: [round(times["stable"][i], 3), round(times["lomuto"][i], 3)]
+                           for i, a in enumerate(arrays)},
+           "lomuto": {"value": round(keys / lo / 1e9, 6), "unit": "Gkeys/s", "cores": 1,
+                      "sample": "same arrays, keys only, in-place exchange flavour, "
+                                f"{lo:.1f} s"}}
+    if pool:
+        cores = avail[:16]
+        res = {"threads": len(cores)}
+        if batch is None:
+            lengths = W.batched_lengths()
+            offs = np.concatenate([[0], np.cumsum(lengths)])
+            bits = W.normal_bits("f32", int(offs[-1]), 0)
+            batch = [bits[offs[s]:offs[s + 1]] for s in range(lengths.size)]
+        nb = sum(b.size for b in batch)
+        log(f"oracle pool: {len(batch)} arrays, {nb} keys, {len(cores)} threads")
+        t = oracle_pool([(b, "f32", True) for b in batch], cores)
+        res["batched_f32"] = {"arrays": len(batch), "keys": int(nb), "s": round(t, 3),
+                              "gkeys_s": round(nb / t / 1e9, 6)}
+        if rows is None:
+            rows = [("f32", 1024, 65536), ("f16", 4096, 16384)]
+        for (name, r, c) in rows:
+            x = W.normal_bits(name, r * c, 5).reshape(r, c)
+            log(f"oracle pool: {name} {r}x{c} rows")
+            t = oracle_pool([(x[i], name, True) for i in range(r)], cores)
+            res[f"rows_{name}_{r}x{c}"] = {"keys": r * c, "s": round(t, 3),
+                                          "gkeys_s": round(r * c / t / 1e9, 6)}
+        out["pool"] = res
+    return out
+
+
 # --------------------------------------------------------------------- main
 
 EXTRAS_GROUPS = ("word_size_sweep", "batched_vs_per_array", "small_u32_64k",
@@ -651,8 +784,6 @@ def main() -> int:
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--extras", default="all",
                     help="comma-separated extras groups to run (default: all of them)")
-    ap.add_argument("--cpu-sample", type=int, default=1 << 25,
-                    help="keys per array in the oracle's timed sample")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
     args = ap.parse_args()
     if args.summarize_pmc:
@@ -778,19 +909,8 @@ def main() -> int:
 
     cpu = None
     if not args.no_cpu_baseline:
-        import oracle
-        m = min(args.cpu_sample, N)
-        log(f"oracle on {m} keys per array")
-        tot = 0.0
-        for (label, name, bits, desc) in arrays:
-            sample = bits[:m].astype(np.uint64)
-            t = time.perf_counter()
-            oracle.sort_dtype(sample, name, asc=not desc)
-            tot += time.perf_counter() - t
-        cpu = {"value": round(len(arrays) * m / tot / 1e9, 6), "unit": "Gkeys/s", "cores": 1,
-               "kind": "oracle",
-               "sample": f"first {m} keys of each of the {len(arrays)} arrays, keys + stable "
-                         f"indices, single-threaded stable oracle, {tot:.1f} s"}
+        cpu = cpu_baseline([(a[0], a[1], a[2], a[3]) for a in arrays], pool=True)
+        cpu["gpu_over_oracle"] = round(value / cpu["value"], 1)
 
     out = {
         "metric": METRIC,

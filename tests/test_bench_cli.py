@@ -60,3 +60,26 @@ def test_counter_summary(tmp_path):
     # (1000 + 3000) KiB fetched x 2, (500 + 1500) KiB written, over 2 launches
     assert int(float(vals["level_fetch_bytes_per_launch"])) == 4000 * 1024
     assert int(float(vals["level_write_bytes_per_launch"])) == 1000 * 1024
+
+
+def test_cpu_baseline_leg_small():
+    """The CPU-baseline leg on small arrays: whole arrays timed with both
+    oracle flavours on pinned threads, the pool over a batch and rows, and
+    the host description.  The process's own affinity is left alone."""
+    import numpy as np
+    import bench
+    from paper_2603_08929_amd import workloads as W
+    before = os.sched_getaffinity(0)
+    arrays = [("i32_uniform", "i32", W.uniform_bits("i32", 4096, 0), False),
+              ("u32_reverse_desc", "u32", W.presorted_u32(4096, 0, reverse=True), True)]
+    r = bench.cpu_baseline(arrays, pool=True,
+                           batch=[W.normal_bits("f32", 100 + i, i) for i in range(20)],
+                           rows=[("f16", 8, 256)])
+    assert os.sched_getaffinity(0) == before
+    assert r["kind"] == "oracle" and r["cores"] == 1 and r["value"] > 0
+    assert r["lomuto"]["value"] > 0
+    assert set(r["per_array_s"]) == {"i32_uniform", "u32_reverse_desc"}
+    assert r["host"]["cores_available"] == len(before) and r["host"]["cpu_model"]
+    assert r["pool"]["threads"] == min(16, len(before))
+    assert r["pool"]["batched_f32"]["arrays"] == 20
+    assert r["pool"]["rows_f16_8x256"]["keys"] == 8 * 256
