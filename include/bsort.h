@@ -238,7 +238,10 @@ int bsort_segmented_inplace(void *keys, int key_type, int key_bytes, const int64
  * scratch.  Flags as for the sorts (BSORT_KEYS_UNCHANGED leaves the keys as
  * they were and permutes only the values).  Scratch: at least
  * bsort_pairs_scratch_bytes(...) bytes, 256-byte aligned.  Offsets as for
- * bsort_segmented.  Arguments are validated before anything is enqueued.
+ * bsort_segmented: offsets that fail the device-side check leave keys and
+ * values as they were (bsort_device_status on this scratch reports bit 1;
+ * the indices are then undefined).  Arguments are validated before
+ * anything is enqueued.
  */
 size_t bsort_pairs_scratch_bytes(int key_bytes, uint64_t n, uint64_t num_segments,
                                  int value_bytes, int with_indices, uint32_t flags);

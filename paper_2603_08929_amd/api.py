@@ -86,16 +86,22 @@ def sort(x: torch.Tensor, dim: int = -1, descending: bool = False, idx64: bool =
     rows = xm.numel() // cols if cols else 0
     v = xm.clone().reshape(-1)
     offsets = torch.arange(rows + 1, device=x.device, dtype=torch.int64) * cols
+    # offsets made here are valid: no status read (the call stays asynchronous)
     idx = segmented_sort_(v, offsets, descending=descending, return_indices=True, idx64=idx64,
-                          flags=flags)
+                          flags=flags, check=False)
     return v.reshape(xm.shape).movedim(-1, d), idx.reshape(xm.shape).movedim(-1, d)
 
 
 def segmented_sort_(keys: torch.Tensor, offsets: torch.Tensor, descending: bool = False,
                     return_indices: bool = True, idx64: bool = False, flags: int = 0,
-                    scratch: Optional[torch.Tensor] = None) -> Optional[torch.Tensor]:
+                    scratch: Optional[torch.Tensor] = None,
+                    check: Optional[bool] = None) -> Optional[torch.Tensor]:
     """Sorts the segments [offsets[s], offsets[s+1]) of a 1-D tensor in place,
-    all in one pass.  offsets: int64 device tensor of num_segments + 1."""
+    all in one pass.  offsets: int64 device tensor of num_segments + 1.
+    Offsets are validated on the device; check (default: on) reads the
+    verdict back and raises RuntimeError if they were bad (nothing sorted,
+    indices undefined) -- a host synchronisation; check=False leaves the
+    call asynchronous (device_status(scratch) reads the word later)."""
     if not keys.is_cuda or keys.dim() != 1 or not keys.is_contiguous():
         raise ValueError("bsort.segmented_sort_: need a contiguous 1-D GPU tensor")
     if offsets.dtype != torch.int64 or not offsets.is_cuda or not offsets.is_contiguous():
@@ -114,6 +120,7 @@ def segmented_sort_(keys: torch.Tensor, offsets: torch.Tensor, descending: bool 
                               idx.data_ptr() if idx is not None else None,
                               scratch.data_ptr(), scratch.numel(), _stream(keys.device))
     _lib.check(rc, "bsort_segmented")
+    _raise_on_status(scratch, "segmented_sort_", True if check is None else check, offsets)
     return idx
 
 
@@ -141,10 +148,13 @@ def backward_scatter(grad_sorted: torch.Tensor, indices: torch.Tensor,
 
 
 def argsort(keys: torch.Tensor, offsets: Optional[torch.Tensor] = None,
-            descending: bool = False, idx64: bool = False, flags: int = 0) -> torch.Tensor:
+            descending: bool = False, idx64: bool = False, flags: int = 0,
+            check: Optional[bool] = None) -> torch.Tensor:
     """The stable permutation that sorts a contiguous 1-D tensor (or each
     segment of it), keys left unchanged: int32 storage of uint32 indices, or
-    int64 with idx64."""
+    int64 with idx64.  With offsets, the device's verdict on them is read
+    back and bad offsets raise RuntimeError (check=False skips that host
+    synchronisation; check=True reads the status without offsets too)."""
     kt, kb = key_type(keys.dtype)
     B, off = _segment_args(keys, offsets)
     n = keys.numel()
@@ -159,6 +169,7 @@ def argsort(keys: torch.Tensor, offsets: Optional[torch.Tensor] = None,
         rc = _lib.bsort_segmented(keys.data_ptr(), kt, kb, off, B, n, fl, idx.data_ptr(),
                                   scratch.data_ptr(), scratch.numel(), _stream(keys.device))
     _lib.check(rc, "argsort")
+    _raise_on_status(scratch, "argsort", check, offsets)
     return idx
 
 
@@ -176,10 +187,10 @@ def _value_bytes(values: torch.Tensor, n: int) -> int:
 
 def sort_pairs_(keys: torch.Tensor, values: torch.Tensor, offsets: Optional[torch.Tensor] = None,
                 descending: bool = False, return_indices: bool = False, idx64: bool = False,
-                flags: int = 0) -> Optional[torch.Tensor]:
+                flags: int = 0, check: Optional[bool] = None) -> Optional[torch.Tensor]:
     """Sorts keys (1-D, or each segment) in place and permutes values (one
     row of 1, 2, 4, 8 or 16 bytes per key) the same way; returns the
-    permutation when asked."""
+    permutation when asked.  check as for argsort."""
     kt, kb = key_type(keys.dtype)
     B, off = _segment_args(keys, offsets)
     n = keys.numel()
@@ -199,6 +210,7 @@ def sort_pairs_(keys: torch.Tensor, values: torch.Tensor, offsets: Optional[torc
                                         values.data_ptr(), vb, ip, scratch.data_ptr(),
                                         scratch.numel(), _stream(keys.device))
     _lib.check(rc, "sort_pairs")
+    _raise_on_status(scratch, "sort_pairs_", check, offsets)
     return idx
 
 
@@ -303,10 +315,11 @@ def sort_layout_(keys: torch.Tensor, bit_order, family: Optional[str] = None,
 
 
 def sort_inplace_(keys: torch.Tensor, offsets: Optional[torch.Tensor] = None,
-                  descending: bool = False, flags: int = 0) -> None:
+                  descending: bool = False, flags: int = 0,
+                  check: Optional[bool] = None) -> None:
     """Sorts a contiguous 1-D GPU tensor (or each segment of it) in place
     with the small-scratch in-place variant: keys only, the same sorted keys
-    as sort_, no permutation."""
+    as sort_, no permutation.  check as for argsort."""
     kt, kb = key_type(keys.dtype)
     B, offp = _segment_args(keys, offsets)
     n = keys.numel()
@@ -321,10 +334,32 @@ def sort_inplace_(keys: torch.Tensor, offsets: Optional[torch.Tensor] = None,
                                           scratch.data_ptr(), scratch.numel(),
                                           _stream(keys.device))
     _lib.check(rc, "bsort_sort_inplace")
+    _raise_on_status(scratch, "sort_inplace_", check, offsets)
 
 
 def device_status(scratch: torch.Tensor) -> int:
     return int(_lib.bsort_device_status(scratch.data_ptr(), _stream(scratch.device)))
+
+
+_STATUS_BITS = ((1, "a part exceeded the in-LDS finish capacity (internal error)"),
+                (2, "the segment offsets failed the device-side check: nothing was sorted "
+                    "and the indices are undefined"),
+                (4, "a level tile's count prefix was inconsistent (internal error)"))
+
+
+def _raise_on_status(scratch: torch.Tensor, what: str, check: Optional[bool],
+                     offsets: Optional[torch.Tensor]) -> None:
+    """Reads the device status word (a host synchronisation on the keys'
+    stream) when check is True, or when check is None and the caller passed
+    offsets, which only the device checks; raises if it is not 0."""
+    if check is False or (check is None and offsets is None):
+        return
+    st = device_status(scratch)
+    if st < 0:
+        _lib.check(st, what)
+    if st:
+        why = "; ".join(text for bit, text in _STATUS_BITS if st & bit)
+        raise RuntimeError(f"bsort.{what}: device status {st}: {why}")
 
 
 def _segment_args(keys: torch.Tensor, offsets: Optional[torch.Tensor]):

@@ -569,12 +569,12 @@ bool value_args_ok(const void *p, int value_bytes) {
 
 int launch_gather(const void *values, int value_bytes, const void *indices, bool i64,
                   const int64_t *offsets, uint64_t B, uint64_t n, void *out, int cus,
-                  hipStream_t st, bool scatter = false) {
+                  hipStream_t st, bool scatter = false, const uint32_t *status = nullptr) {
   const uint32_t grid = clamp_grid((n + GCH - 1) / GCH, (uint64_t)cus * 8);
 #define BG_ONE(VT, I, S)                                                                    \
   hipLaunchKernelGGL((gather_kernel<VT, I, S>), dim3(grid), dim3(256), 0, st,               \
                      static_cast<const VT *>(values), indices, offsets, B, n,               \
-                     static_cast<VT *>(out))
+                     static_cast<VT *>(out), status)
 #define BG_LAUNCH(VT)                                                                       \
   do {                                                                                      \
     if (i64 && scatter) BG_ONE(VT, true, true);                                             \
@@ -651,8 +651,12 @@ int sort_pairs(void *keys, int key_type, int key_bytes, const int64_t *offsets, 
   if (rc != BSORT_OK) return rc;
   hipStream_t st = static_cast<hipStream_t>(stream);
   void *tmp = scr + P.vals;
+  // the sort's status word (its header starts the scratch): bad offsets
+  // leave the values as they were, like the keys
+  const uint32_t *status = &reinterpret_cast<const Header *>(scr)->status;
   rc = launch_gather(values, value_bytes, idx, (flags & BSORT_IDX64) != 0,
-                     segmented ? offsets : nullptr, segmented ? B : 1, n, tmp, cus, st);
+                     segmented ? offsets : nullptr, segmented ? B : 1, n, tmp, cus, st, false,
+                     status);
   if (rc != BSORT_OK) return rc;
   const hipError_t e =
       hipMemcpyAsync(values, tmp, n * (size_t)value_bytes, hipMemcpyDeviceToDevice, st);

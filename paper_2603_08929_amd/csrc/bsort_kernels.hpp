@@ -2207,8 +2207,17 @@ constexpr uint32_t GCH = 4096;
 template <typename VT, bool I64, bool SCATTER = false>
 __global__ __launch_bounds__(256) void gather_kernel(const VT *values, const void *indices,
                                                      const int64_t *offsets, uint64_t B,
-                                                     uint64_t n, VT *out) {
+                                                     uint64_t n, VT *out,
+                                                     const uint32_t *status) {
   __shared__ uint64_t s_rng[2];
+  // after a sort that rejected its offsets the indices are undefined: the
+  // values are passed through unchanged
+  if (!SCATTER && status && (*status & STATUS_BAD_OFFSETS)) {
+    for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n;
+         j += (uint64_t)gridDim.x * blockDim.x)
+      out[j] = values[j];
+    return;
+  }
   for (uint64_t c0 = (uint64_t)blockIdx.x * GCH; c0 < n; c0 += (uint64_t)gridDim.x * GCH) {
     const uint64_t c1 = c0 + GCH < n ? c0 + GCH : n;
     uint64_t lo = 0, hi = 0;

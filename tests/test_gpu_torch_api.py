@@ -32,3 +32,30 @@ def test_sort_matches_torch(dtype, shape, dim):
         assert torch.equal(v.cpu(), rv)
         assert torch.equal(i.cpu(), ri)
     assert torch.equal(xd, before)
+
+
+def test_bad_offsets_raise_in_the_torch_api():
+    """Offsets the device rejects: segmented_sort_, argsort, sort_pairs_ and
+    sort_inplace_ read the status word and raise; with check=False the call
+    returns and the keys are left as they were."""
+    from paper_2603_08929_amd import api
+    keys = torch.arange(100, 0, -1, dtype=torch.int32, device="cuda")
+    vals = torch.arange(100, dtype=torch.float32, device="cuda")
+    bad = torch.tensor([0, 60, 40, 100], dtype=torch.int64, device="cuda")  # decreasing
+    orig = keys.clone()
+    for call in (lambda: api.segmented_sort_(keys, bad),
+                 lambda: api.argsort(keys, bad),
+                 lambda: api.sort_pairs_(keys, vals, bad),
+                 lambda: api.sort_inplace_(keys, bad)):
+        with pytest.raises(RuntimeError, match="offsets failed"):
+            call()
+        assert torch.equal(keys, orig)
+        assert torch.equal(vals, torch.arange(100, dtype=torch.float32, device="cuda"))
+    api.segmented_sort_(keys, bad, check=False)
+    torch.cuda.synchronize()
+    assert torch.equal(keys, orig)
+    good = torch.tensor([0, 40, 60, 100], dtype=torch.int64, device="cuda")
+    api.segmented_sort_(keys, good)
+    ref = torch.cat([torch.sort(orig[a:b].cpu(), stable=True)[0]
+                     for a, b in ((0, 40), (40, 60), (60, 100))])
+    assert torch.equal(keys.cpu(), ref)
