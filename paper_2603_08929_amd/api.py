@@ -120,7 +120,8 @@ def segmented_sort_(keys: torch.Tensor, offsets: torch.Tensor, descending: bool 
                               idx.data_ptr() if idx is not None else None,
                               scratch.data_ptr(), scratch.numel(), _stream(keys.device))
     _lib.check(rc, "bsort_segmented")
-    _raise_on_status(scratch, "segmented_sort_", True if check is None else check, offsets)
+    _raise_on_status(scratch, "segmented_sort_", True if check is None else check, offsets,
+                     n)
     return idx
 
 
@@ -169,7 +170,7 @@ def argsort(keys: torch.Tensor, offsets: Optional[torch.Tensor] = None,
         rc = _lib.bsort_segmented(keys.data_ptr(), kt, kb, off, B, n, fl, idx.data_ptr(),
                                   scratch.data_ptr(), scratch.numel(), _stream(keys.device))
     _lib.check(rc, "argsort")
-    _raise_on_status(scratch, "argsort", check, offsets)
+    _raise_on_status(scratch, "argsort", check, offsets, n)
     return idx
 
 
@@ -210,7 +211,7 @@ def sort_pairs_(keys: torch.Tensor, values: torch.Tensor, offsets: Optional[torc
                                         values.data_ptr(), vb, ip, scratch.data_ptr(),
                                         scratch.numel(), _stream(keys.device))
     _lib.check(rc, "sort_pairs")
-    _raise_on_status(scratch, "sort_pairs_", check, offsets)
+    _raise_on_status(scratch, "sort_pairs_", check, offsets, n)
     return idx
 
 
@@ -334,7 +335,7 @@ def sort_inplace_(keys: torch.Tensor, offsets: Optional[torch.Tensor] = None,
                                           scratch.data_ptr(), scratch.numel(),
                                           _stream(keys.device))
     _lib.check(rc, "bsort_sort_inplace")
-    _raise_on_status(scratch, "sort_inplace_", check, offsets)
+    _raise_on_status(scratch, "sort_inplace_", check, offsets, n)
 
 
 def device_status(scratch: torch.Tensor) -> int:
@@ -348,12 +349,14 @@ _STATUS_BITS = ((1, "a part exceeded the in-LDS finish capacity (internal error)
 
 
 def _raise_on_status(scratch: torch.Tensor, what: str, check: Optional[bool],
-                     offsets: Optional[torch.Tensor]) -> None:
+                     offsets: Optional[torch.Tensor], n: int) -> None:
     """Reads the device status word (a host synchronisation on the keys'
     stream) when check is True, or when check is None and the caller passed
     offsets, which only the device checks; raises if it is not 0."""
     if check is False or (check is None and offsets is None):
         return
+    if n == 0:
+        return  # no keys: the call enqueued nothing and wrote no status
     st = device_status(scratch)
     if st < 0:
         _lib.check(st, what)

@@ -91,11 +91,6 @@ int device_check(int *cus, int *device = nullptr) {
 constexpr int N_LEVEL_SHAPES = 2, N_FINISH_SHAPES = 3, N_GRIDS = 2;
 constexpr int N_CONFIGS = N_LEVEL_SHAPES * N_FINISH_SHAPES * N_GRIDS;
 
-template <typename KT, int V>
-struct LevelShape {
-  static constexpr int LIPT = V == 0 ? 8 : 4;
-  static constexpr uint32_t TILE = 64 * LIPT;
-};
 // The in-place path's tile: a 512-thread workgroup.
 template <typename KT>
 struct InplaceShape {
@@ -131,10 +126,15 @@ Config config_of(int id) { return Config{id / 6, (id / 2) % 3, id % 2}; }
 constexpr int CONFIG_DRY_RUN = -2;  // validate the arguments and the device, launch nothing
 
 // Level tile of a configuration's level shape (the smaller one is lv = 1).
-uint32_t tile_of(int key_bytes, int lv) {
-  (void)key_bytes;
-  return 64u * (lv == 0 ? 8u : 4u);
+constexpr uint32_t tile_of(int key_bytes, int lv) {
+  return 64u * ((lv == 0 ? 16u : 8u) / (key_bytes == 8 ? 2u : 1u));
 }
+static_assert(tile_of(1, 0) == LevelShape<uint8_t, 0>::TILE &&
+                  tile_of(2, 1) == LevelShape<uint16_t, 1>::TILE &&
+                  tile_of(4, 0) == LevelShape<uint32_t, 0>::TILE &&
+                  tile_of(8, 0) == LevelShape<uint64_t, 0>::TILE &&
+                  tile_of(8, 1) == LevelShape<uint64_t, 1>::TILE,
+              "layout tile and launch tile agree");
 uint32_t inplace_tile_of(int key_bytes) { return 512u * (key_bytes == 8 ? 4u : 8u); }
 uint32_t tfin_of(int key_bytes, int fv) {
   const uint32_t fb = fv == 1 ? 256 : 512;
@@ -1361,7 +1361,7 @@ const char *bsort_config_name(int config) {
     const Config c = config_of(config);
     snprintf(names[config], sizeof names[config],
              "level one wave x %d (tile %u keys), finish %dx%d (T %u keys of 4 B), %s grid",
-             c.lv == 0 ? 8 : 4, tile_of(4, c.lv), c.fv == 1 ? 256 : 512,
+             (int)tile_of(4, c.lv) / 64, tile_of(4, c.lv), c.fv == 1 ? 256 : 512,
              c.fv == 2 ? 8 : 16, tfin_of(4, c.fv), c.grid ? "half" : "full");
   }
   return names[config];

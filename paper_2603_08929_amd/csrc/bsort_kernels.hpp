@@ -1179,6 +1179,15 @@ __global__ __launch_bounds__(256) void level_kernel(LevelArgs<KT> a) {
   flush_acc<KT, RT>(a, acc);
 }
 
+// Level launch shape: keys per lane of a level tile.  16 (8 for 64-bit keys)
+// in the default shape -- two waves per SIMD, each with a 1024-key tile in
+// flight -- and half that in the smaller one.
+template <typename KT, int V>
+struct LevelShape {
+  static constexpr int LIPT = (V == 0 ? 16 : 8) / (sizeof(KT) == 8 ? 2 : 1);
+  static constexpr uint32_t TILE = 64 * LIPT;
+};
+
 // ------------------------------------------------------------- LDS finish
 
 template <typename KT>
