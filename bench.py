@@ -840,16 +840,23 @@ def main() -> int:
     log("characterising the arrays")
     live = np.zeros((len(arrays), MAX_LEVELS), dtype=np.uint64)
     per_array = []
+    launches = []  # level-kernel launches per sort of each array
     for j in range(len(arrays)):
         k = pristine[j].clone()
+        _lib.check(_lib.bsort_timing_arm(64), "bsort_timing_arm")
         sort_one(j, k)
+        torch.cuda.synchronize(dev)
+        t_ms = np.zeros(64, dtype=np.float32)
+        t_lv = np.zeros(64, dtype=np.int32)
+        launches.append(int(_lib.bsort_timing_read(t_ms.ctypes.data, t_lv.ctypes.data, 64)))
+        _lib.bsort_timing_disarm()
         buf, fk, ck = level_stats(_lib, scratch, stream)
         st = _lib.bsort_device_status(scratch.data_ptr(), stream)
         if st != 0:
             raise RuntimeError(f"device status {st} on {arrays[j][0]}")
         live[j] = buf
         per_array.append({"array": arrays[j][0], "global_levels": int((buf > 0).sum()),
-                          "finish_keys": fk, "copy_keys": ck})
+                          "level_launches": launches[j], "finish_keys": fk, "copy_keys": ck})
         del k
 
     steps, warm = args.steps, args.warmup
@@ -866,7 +873,7 @@ def main() -> int:
     # the events add a few microseconds between launches, so the later steps
     # run without them.
     ev_steps = max(1, min(args.event_steps, steps))
-    cap = ev_steps * len(arrays) * 32
+    cap = ev_steps * sum(launches)
     _lib.check(_lib.bsort_timing_arm(cap), "bsort_timing_arm")
     log("timed steps")
     torch.cuda.synchronize(dev)
@@ -880,20 +887,26 @@ def main() -> int:
     lv = np.zeros(cap, dtype=np.int32)
     got = _lib.bsort_timing_read(ms.ctypes.data, lv.ctypes.data, cap)
     _lib.bsort_timing_disarm()
-    if got != cap:
-        raise RuntimeError(f"timing: {got} of {cap} level launches recorded")
+    # the level-kernel launches of the first ev_steps steps, in launch order
+    # (step, array, level); levels past the tail depth run in the tail
+    # launch, which is not a level-kernel launch
+    starts = [i for i in range(got) if lv[i] == 0]
+    if got != cap or len(starts) != ev_steps * len(arrays):
+        raise RuntimeError(f"timing: {got} of {cap} level launches recorded in "
+                           f"{len(starts)} sorts")
     del work
 
-    # algorithmic bytes of each timed level launch (launch order: step, array, level)
+    # algorithmic bytes of each timed level launch
     K, I = 4, 4
-    alg = np.zeros(cap, dtype=np.float64)
-    p = 0
-    for s in range(ev_steps):
-        for j in range(len(arrays)):
-            for lvl in range(32):
-                nl = float(live[j][lvl])
-                alg[p] = nl * ((2 * K + I) if lvl == 0 else 2 * (K + I))
-                p += 1
+    alg = np.zeros(got, dtype=np.float64)
+    for q, i0 in enumerate(starts):
+        j = q % len(arrays)
+        i1 = starts[q + 1] if q + 1 < len(starts) else got
+        for i in range(i0, i1):
+            lvl = int(lv[i])
+            alg[i] = float(live[j][lvl]) * ((2 * K + I) if lvl == 0 else 2 * (K + I))
+    ms = ms[:got]
+    cap = got
     level_time_s = float(ms.astype(np.float64).sum()) / 1e3
     achieved = alg.sum() / level_time_s / 1e9
     elapsed = t1 - t0

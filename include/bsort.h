@@ -402,10 +402,12 @@ int bsort_level_stats(const void *scratch, void *stream, uint64_t *live_keys,
                       uint64_t *finish_keys, uint64_t *copy_keys);
 
 /* While armed, each launch of the global-level kernel (by any call of this
- * process) is bracketed by a pair of hipEvents recorded on the call's
- * stream, for the first `capacity` launches.  bsort_timing_read waits for
- * them, writes each launch's elapsed milliseconds and level index, and
- * restarts the count.  Host-side event objects only; not thread-safe. */
+ * process) carries a pair of hipEvents that take the kernel's own start and
+ * end times from its dispatch on the call's stream, for the first
+ * `capacity` launches.  Levels past the depth chosen from n run in one tail
+ * launch, which is not timed.  bsort_timing_read waits for the events,
+ * writes each launch's elapsed milliseconds and level index, and restarts
+ * the count.  Host-side event objects only; not thread-safe. */
 int bsort_timing_arm(int capacity);
 int bsort_timing_read(float *ms, int *levels, int capacity);
 void bsort_timing_disarm(void);

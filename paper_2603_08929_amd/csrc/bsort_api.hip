@@ -308,8 +308,9 @@ int launch_all(KT *keys, uint64_t n, const int64_t *offsets, uint64_t B, int mod
   // written out as they stand (bsort_levels)
   const bool snapshot = stop < levels;
   if (snapshot) levels = stop;
-  for (int lvl = 0; lvl < levels; ++lvl) {
-    PrepArgs<KT> ca;
+
+  // the arguments of level lvl's three kernels (they alternate by parity)
+  auto level_args = [&](int lvl, PrepArgs<KT> &ca, LevelArgs<KT> &a, PlanArgs &pa) {
     ca.keys[0] = kbuf[0];
     ca.keys[1] = kbuf[1];
     ca.live = segs[lvl & 1];
@@ -323,9 +324,7 @@ int launch_all(KT *keys, uint64_t n, const int64_t *offsets, uint64_t B, int mod
     ca.mode = mode;
     ca.desc = desc;
     ca.level = lvl;
-    hipLaunchKernelGGL(pk, dim3(cgrid), dim3(256), 0, st, ca);
 
-    LevelArgs<KT> a;
     a.keys[0] = kbuf[0];
     a.keys[1] = kbuf[1];
     a.idx[0] = ibuf[0];
@@ -343,18 +342,7 @@ int launch_all(KT *keys, uint64_t n, const int64_t *offsets, uint64_t B, int mod
     a.mode = mode;
     a.desc = desc;
     a.level = lvl;
-    const bool timed = g_timing.armed && !g_capturing && g_timing.count < g_timing.cap;
-    if (timed) {
-      // the events take the kernel's own start and end times from its
-      // dispatch: no marker packets between the launches
-      hipExtLaunchKernelGGL(lk, dim3(lgrid), dim3(256), 0, st, g_timing.ev[2 * g_timing.count],
-                            g_timing.ev[2 * g_timing.count + 1], 0u, a);
-      g_timing.lvl[g_timing.count++] = lvl;
-    } else {
-      hipLaunchKernelGGL(lk, dim3(lgrid), dim3(256), 0, st, a);
-    }
 
-    PlanArgs pa;
     pa.l = la;
     pa.l.live_next = segs[(lvl + 1) & 1];
     pa.l.acc_next = acc[(lvl + 1) & 1];
@@ -373,7 +361,49 @@ int launch_all(KT *keys, uint64_t n, const int64_t *offsets, uint64_t B, int mod
     pa.no_skip = no_skip;
     pa.no_finish = no_finish;
     pa.inplace = 0;
+  };
+
+  // Levels below `first_tail` are launched one kernel per phase; the rest
+  // run in one tail launch, which ends at the first empty level (its live
+  // levels run at lower occupancy than a level launch, so the depth leaves
+  // room for skewed data).  Parts of uniform keys reach the finish size
+  // after about log2(n / T) levels (T = finish size); six more levels cover
+  // the skew of normal floats and presorted runs.
+  int first_tail = levels;
+  if (!no_finish && !snapshot) {
+    const uint64_t parts = (n + FS::TFIN - 1) / FS::TFIN;
+    const int depth = parts > 1 ? 64 - __builtin_clzll(parts - 1) : 0;  // ceil(log2(parts))
+    first_tail = depth + 6 < levels ? depth + 6 : levels;
+  }
+  for (int lvl = 0; lvl < first_tail; ++lvl) {
+    PrepArgs<KT> ca;
+    LevelArgs<KT> a;
+    PlanArgs pa;
+    level_args(lvl, ca, a, pa);
+    hipLaunchKernelGGL(pk, dim3(cgrid), dim3(256), 0, st, ca);
+    const bool timed = g_timing.armed && !g_capturing && g_timing.count < g_timing.cap;
+    if (timed) {
+      // the events take the kernel's own start and end times from its
+      // dispatch: no marker packets between the launches
+      hipExtLaunchKernelGGL(lk, dim3(lgrid), dim3(256), 0, st, g_timing.ev[2 * g_timing.count],
+                            g_timing.ev[2 * g_timing.count + 1], 0u, a);
+      g_timing.lvl[g_timing.count++] = lvl;
+    } else {
+      hipLaunchKernelGGL(lk, dim3(lgrid), dim3(256), 0, st, a);
+    }
     hipLaunchKernelGGL(plan_kernel, dim3(pgrid), dim3(256), 0, st, pa);
+  }
+  if (first_tail < levels) {
+    TailArgs<KT> ta;
+    level_args(first_tail, ta.prep0, ta.lvl0, ta.plan0);
+    level_args(first_tail + 1, ta.prep1, ta.lvl1, ta.plan1);
+    ta.hdr = hdr;
+    ta.first = first_tail;
+    ta.last = levels;
+    auto tk = tail_kernel<KT, IDX, LS::LIPT>;
+    // every workgroup resident at once: the barriers wait for all of them
+    static const int occ_tail = occupancy(tk, 256);
+    hipLaunchKernelGGL(tk, dim3((uint32_t)(cus * occ_tail)), dim3(256), 0, st, ta);
   }
 
   if (snapshot) {

@@ -47,6 +47,7 @@ constexpr uint32_t META_PRE = 1u << 11;  // the previous level counted `bit` per
 constexpr uint32_t STATUS_OVERSIZE = 1u;  // a finish entry larger than the workgroup's capacity
 constexpr uint32_t STATUS_BAD_OFFSETS = 2u;
 constexpr uint32_t STATUS_BAD_COUNTS = 4u;  // a tile's precomputed prefix exceeded its position
+constexpr uint32_t STATUS_BARRIER = 8u;  // a grid barrier of the tail kernel timed out
 
 constexpr int MAX_LEVELS = 66;
 
@@ -91,11 +92,16 @@ struct Header {
   uint64_t packed[MAX_LEVELS]; // per level: (live segments << 32) | tiles
   uint32_t prep_ticket[MAX_LEVELS]; // per level: prep workgroups done
   uint64_t live_keys[MAX_LEVELS]; // per level: keys in live segments
+  uint32_t bar_grp[8];         // tail-kernel grid barrier: arrivals per block group
+  uint32_t bar_top;            // ... and groups complete
 };
 
 // ---------------------------------------------------------------- helpers
 
 __device__ __forceinline__ uint64_t ld_relaxed(const uint64_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t ld_relaxed_u32(const uint32_t *p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ void st_relaxed(uint64_t *p, uint64_t v) {
@@ -523,8 +529,8 @@ struct PlanArgs {
   int inplace;  // the level partitioned in place: no buffers, no counts
 };
 
-__global__ void plan_kernel(PlanArgs a) {
-  const uint32_t S = (uint32_t)(a.l.hdr->packed[a.level] >> 32);
+__device__ __forceinline__ void plan_body(const PlanArgs &a) {
+  const uint32_t S = (uint32_t)(ld_relaxed(&a.l.hdr->packed[a.level]) >> 32);
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.zero_n; i += stride) {
     a.zero_a[i] = 0;
@@ -615,6 +621,9 @@ __global__ void plan_kernel(PlanArgs a) {
   }
 }
 
+__global__ void plan_kernel(PlanArgs a) { plan_body(a); }
+
+
 // ------------------------------------------------------------ global level
 //
 // One level splits every live segment on its bit.  A level tile is one
@@ -687,7 +696,7 @@ __device__ __forceinline__ void tile_keys(const KT *keys, uint64_t start, uint64
 // start, before it.  A tile's front prefix is then its scan value plus,
 // when its segment started in an earlier chunk, its chunk's carry.
 template <typename KT, int IPT>
-__global__ __launch_bounds__(256) void prep_kernel(PrepArgs<KT> a) {
+__device__ __forceinline__ void prep_body(const PrepArgs<KT> &a, uint32_t chunk) {
   constexpr uint32_t TILE = 64 * IPT;
   constexpr int RB = 4;  // tiles counted at once by a wave
   using RT = typename std::conditional<sizeof(KT) == 8, uint64_t, uint32_t>::type;
@@ -695,10 +704,9 @@ __global__ __launch_bounds__(256) void prep_kernel(PrepArgs<KT> a) {
   __shared__ uint64_t s_v[256];
   __shared__ uint32_t s_f[256];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const uint64_t pk = a.hdr->packed[a.level];
+  const uint64_t pk = ld_relaxed(&a.hdr->packed[a.level]);
   const uint32_t S = (uint32_t)(pk >> 32), ntiles = (uint32_t)pk;
   const uint32_t nchunks = (ntiles + PREP_TILES - 1) / PREP_TILES;
-  const uint32_t chunk = blockIdx.x;
   if (chunk >= nchunks) return;
   const uint32_t t0 = chunk * PREP_TILES + (uint32_t)wave * 64;
   const uint32_t t = t0 + (uint32_t)lane;
@@ -837,6 +845,11 @@ __global__ __launch_bounds__(256) void prep_kernel(PrepArgs<KT> a) {
     const uint64_t x = ld_relaxed(&a.agg[i]);
     cin = (x & HEAD) ? (x & ~HEAD) : cin + x;
   }
+}
+
+template <typename KT, int IPT>
+__global__ __launch_bounds__(256) void prep_kernel(PrepArgs<KT> a) {
+  prep_body<KT, IPT>(a, blockIdx.x);
 }
 
 template <typename KT>
@@ -1143,10 +1156,10 @@ __device__ __forceinline__ void process_tile(const LevelArgs<KT> &a, const WaveT
 // the grid).  A tile's descriptor is fetched two tiles ahead and its counts
 // and keys one tile ahead of its use.
 template <typename KT, bool IDX, int IPT>
-__global__ __launch_bounds__(256) void level_kernel(LevelArgs<KT> a) {
+__device__ __forceinline__ void level_body(const LevelArgs<KT> &a) {
   constexpr int TILE = 64 * IPT;
   using RT = typename std::conditional<sizeof(KT) == 8, uint64_t, uint32_t>::type;
-  const uint32_t ntiles = (uint32_t)(a.hdr->packed[a.level] & 0xffffffffu);
+  const uint32_t ntiles = (uint32_t)(ld_relaxed(&a.hdr->packed[a.level]) & 0xffffffffu);
   const rsrc_t mr = make_rsrc(a.meta, a.off.range);
   const uint32_t G = gridDim.x * 4u;
   const uint32_t g = uni(blockIdx.x * 4u + (threadIdx.x >> 6));
@@ -1177,6 +1190,110 @@ __global__ __launch_bounds__(256) void level_kernel(LevelArgs<KT> a) {
     t += 2 * G;
   }
   flush_acc<KT, RT>(a, acc);
+}
+
+template <typename KT, bool IDX, int IPT>
+__global__ __launch_bounds__(256) void level_kernel(LevelArgs<KT> a) {
+  level_body<KT, IDX, IPT>(a);
+}
+
+// ------------------------------------------------------------- tail levels
+//
+// The last levels of a sort are usually empty: once every part is small
+// enough for the LDS finish, no segment is live, yet prep, level and plan
+// would each still be launched per level.  From a depth the host picks
+// from n on, the levels run in one launch that walks them itself: it stops
+// at the first level with no live tile (one header read) and otherwise runs
+// the same three phases, separated by grid barriers.  The grid is at most
+// what the device holds at once (occupancy x CUs), so a barrier waits only
+// for running workgroups; each wait is still bounded in time, and one that
+// runs out sets STATUS_BARRIER, after which no barrier waits, so the launch
+// always ends.
+template <typename KT>
+struct TailArgs {
+  // the arguments of levels first + 2i (set 0) and first + 2i + 1 (set 1):
+  // buffers alternate by level parity; the level number is set per level
+  PrepArgs<KT> prep0, prep1;
+  LevelArgs<KT> lvl0, lvl1;
+  PlanArgs plan0, plan1;
+  Header *hdr;
+  int first, last;       // levels [first, last)
+};
+
+// Barrier number `epoch` (1, 2, ...) of the launch.  Workgroups arrive in
+// eight per-group counters, so that no single counter takes every arrival;
+// the last of a group counts the group complete.  Each XCD has its own L2:
+// the fences make every write before the barrier visible after it in every
+// workgroup (L2 written back before the arrival, caches invalidated after
+// the wait).
+__device__ void grid_sync(Header *hdr, uint32_t epoch) {
+  // every wave's stores reach L2 before the workgroup's one write-back: a
+  // barrier alone does not wait for them
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    __builtin_amdgcn_s_waitcnt(0);  // the write-back done before the arrival
+    const uint32_t nb = gridDim.x;
+    const uint32_t grp = blockIdx.x & 7u;
+    const uint32_t gsize = (nb - grp + 7u) / 8u;
+    const uint32_t ngrp = nb < 8u ? nb : 8u;
+    if (atomic_add_u32(&hdr->bar_grp[grp], 1u) + 1u == epoch * gsize)
+      atomic_add_u32(&hdr->bar_top, 1u);
+    const uint64_t t0 = wall_clock64();
+    while (ld_relaxed_u32(&hdr->bar_top) < epoch * ngrp &&
+           !(ld_relaxed_u32(&hdr->status) & STATUS_BARRIER)) {
+      __builtin_amdgcn_s_sleep(4);
+      if (wall_clock64() - t0 > 20000000ull) {  // 0.2 s of the 100 MHz clock
+        atomic_or_u32(&hdr->status, STATUS_BARRIER);
+        break;
+      }
+    }
+    __threadfence();
+    __builtin_amdgcn_s_waitcnt(0);
+  }
+  __syncthreads();
+}
+
+// One level of the tail: false when it has no live tile (nor has any
+// later level).
+template <typename KT, bool IDX, int IPT>
+__device__ __forceinline__ bool tail_level(const PrepArgs<KT> &p, const LevelArgs<KT> &l,
+                                           const PlanArgs &q, Header *hdr, int lvl,
+                                           uint32_t &epoch) {
+  // final since the barrier after the previous level's plan (or the
+  // previous launch): the same value in every workgroup
+  const uint64_t pk = ld_relaxed(&hdr->packed[lvl]);
+  if ((uint32_t)pk == 0u) return false;
+  PrepArgs<KT> pa = p;
+  pa.level = lvl;
+  const uint32_t nchunks = ((uint32_t)pk + PREP_TILES - 1) / PREP_TILES;
+  for (uint32_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+    prep_body<KT, IPT>(pa, c);
+    __syncthreads();
+  }
+  grid_sync(hdr, ++epoch);
+  LevelArgs<KT> la = l;
+  la.level = lvl;
+  level_body<KT, IDX, IPT>(la);
+  grid_sync(hdr, ++epoch);
+  PlanArgs qa = q;
+  qa.level = lvl;
+  qa.l.next_level = lvl + 1;
+  plan_body(qa);
+  grid_sync(hdr, ++epoch);
+  return true;
+}
+
+template <typename KT, bool IDX, int IPT>
+__global__ __launch_bounds__(256) void tail_kernel(TailArgs<KT> a) {
+  uint32_t epoch = 0;
+  for (int lvl = a.first; lvl < a.last; ++lvl) {
+    const bool odd = ((lvl - a.first) & 1) != 0;  // uniform: picks a whole argument set
+    if (!tail_level<KT, IDX, IPT>(odd ? a.prep1 : a.prep0, odd ? a.lvl1 : a.lvl0,
+                                  odd ? a.plan1 : a.plan0, a.hdr, lvl, epoch))
+      break;
+  }
 }
 
 // Level launch shape: keys per lane of a level tile.  16 (8 for 64-bit keys)
