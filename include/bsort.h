@@ -386,7 +386,9 @@ const char *bsort_strerror(int status);
  * (an internal error: the result is invalid); bit 1 = the segment offsets
  * failed the device-side check (nothing was sorted); bit 2 = a level tile's
  * precomputed count prefix was inconsistent (an internal error: that tile
- * wrote nothing, the result is invalid).  Reads
+ * wrote nothing, the result is invalid); bit 3 = a grid barrier of the tail
+ * launch (the levels past the depth chosen from n) waited longer than its
+ * bound, 0.2 s, and went on (the result is invalid).  Reads
  * it synchronously on `stream`.  Returns the word, or a negative status. */
 int bsort_device_status(const void *scratch, void *stream);
 

@@ -345,7 +345,8 @@ def device_status(scratch: torch.Tensor) -> int:
 _STATUS_BITS = ((1, "a part exceeded the in-LDS finish capacity (internal error)"),
                 (2, "the segment offsets failed the device-side check: nothing was sorted "
                     "and the indices are undefined"),
-                (4, "a level tile's count prefix was inconsistent (internal error)"))
+                (4, "a level tile's count prefix was inconsistent (internal error)"),
+                (8, "a grid barrier of the tail launch timed out (the result is invalid)"))
 
 
 def _raise_on_status(scratch: torch.Tensor, what: str, check: Optional[bool],
