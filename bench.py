@@ -17,8 +17,10 @@ first timed step (--event-steps) its launches carry hipEvents on the
 library's stream that take the kernel's own start and end times from the
 dispatch (events add a few microseconds between dependent launches, so the
 other timed steps run without them);
-algorithmic bytes per launch = live keys of that level x (read + write of
-key and index: 2 * (4 + 4) bytes; level 0 reads no index: 4 + 4 + 4).
+algorithmic bytes per launch = the level's live keys read (4 bytes each,
+plus 4 for the index where it is not still the identity) and the keys of
+segments whose split moved them written with their indices (4 + 4 bytes); a
+split with an empty side moves nothing.
 `traffic` is the HBM bytes per level launch that the FETCH_SIZE and
 WRITE_SIZE counters measured for this kernel (committed summary under
 profiles/, scaled by the same counters' reading of a plain 1 GiB copy), or
@@ -173,23 +175,35 @@ def load_traffic():
 # ------------------------------------------------------------------ helpers
 
 def level_stats(lib, scratch, stream):
+    """Per level of the last call on this scratch: (live keys, live keys whose
+    indices are still the identity, keys of segments whose split moved them),
+    then the keys of the LDS finish and of the copy-back."""
     import ctypes
     import numpy as np
-    buf = np.zeros(MAX_LEVELS, dtype=np.uint64)
+    live = np.zeros(MAX_LEVELS, dtype=np.uint64)
+    iota = np.zeros(MAX_LEVELS, dtype=np.uint64)
+    moved = np.zeros(MAX_LEVELS, dtype=np.uint64)
     fk = ctypes.c_uint64(0)
     ck = ctypes.c_uint64(0)
-    lib.bsort_level_stats(scratch.data_ptr(), stream, buf.ctypes.data, None, None, MAX_LEVELS,
+    lib.bsort_level_stats(scratch.data_ptr(), stream, live.ctypes.data, None, None, MAX_LEVELS,
                           ctypes.byref(fk), ctypes.byref(ck))
-    return buf, int(fk.value), int(ck.value)
+    lib.bsort_level_bytes(scratch.data_ptr(), stream, iota.ctypes.data, moved.ctypes.data,
+                          MAX_LEVELS)
+    return (live, iota, moved), int(fk.value), int(ck.value)
 
 
-def alg_bytes(live, finish_keys, K, I):
-    """Algorithmic HBM bytes of one sort: every executed level reads and
-    writes its live keys and indices (level 0 reads no index); the LDS
-    finish reads and writes its keys once for all remaining bits."""
-    tot = 0.0
-    for lvl, nl in enumerate(live):
-        tot += float(nl) * ((2 * K + I) if lvl == 0 else 2 * (K + I))
+def level_alg_bytes(stats, lvl, K, I):
+    """Algorithmic HBM bytes of one level: its live keys are read (with their
+    indices where those are not the identity) and the keys of segments whose
+    split moved them are written with their indices."""
+    live, iota, moved = (float(x[lvl]) for x in stats)
+    return live * K + (live - iota) * I + moved * (K + I)
+
+
+def alg_bytes(stats, finish_keys, K, I):
+    """Algorithmic HBM bytes of one sort: every executed level (above); the
+    LDS finish reads and writes its keys once for all remaining bits."""
+    tot = sum(level_alg_bytes(stats, lvl, K, I) for lvl in range(MAX_LEVELS))
     return tot + finish_keys * 2.0 * (K + I)
 
 
@@ -251,8 +265,9 @@ def extras_word_size(lib, torch, np, dev, stream):
 
         once(0)
         ms = sorted(once(0) for _ in range(3))[1]
-        live, fk, _ = level_stats(lib, scratch, stream)
-        ab = alg_bytes(live, fk, K, I)
+        stats, fk, _ = level_stats(lib, scratch, stream)
+        live = stats[0]
+        ab = alg_bytes(stats, fk, K, I)
         # plain mode: exactly w full passes; per-pass time from the level events
         lib.check(lib.bsort_timing_arm(w), "arm")
         ms_plain = once(lib.PLAIN)
@@ -316,8 +331,9 @@ def extras_batched(lib, torch, np, dev, stream):
 
         once(batched)
         t_b = sorted(once(batched) for _ in range(3))[1]
-        live, fk, _ = level_stats(lib, scratch, stream)
-        ab = alg_bytes(live, fk, 4, 4)
+        stats, fk, _ = level_stats(lib, scratch, stream)
+        live = stats[0]
+        ab = alg_bytes(stats, fk, 4, 4)
         kb, ib = work.clone(), idx.clone()
         once(per_array)
         t_p = once(per_array)
@@ -838,7 +854,7 @@ def main() -> int:
 
     # work statistics per array (deterministic: identical in every step)
     log("characterising the arrays")
-    live = np.zeros((len(arrays), MAX_LEVELS), dtype=np.uint64)
+    stats = []  # per array: per-level (live, identity-index, moved) keys
     per_array = []
     launches = []  # level-kernel launches per sort of each array
     for j in range(len(arrays)):
@@ -850,12 +866,13 @@ def main() -> int:
         t_lv = np.zeros(64, dtype=np.int32)
         launches.append(int(_lib.bsort_timing_read(t_ms.ctypes.data, t_lv.ctypes.data, 64)))
         _lib.bsort_timing_disarm()
-        buf, fk, ck = level_stats(_lib, scratch, stream)
+        st3, fk, ck = level_stats(_lib, scratch, stream)
         st = _lib.bsort_device_status(scratch.data_ptr(), stream)
         if st != 0:
             raise RuntimeError(f"device status {st} on {arrays[j][0]}")
-        live[j] = buf
-        per_array.append({"array": arrays[j][0], "global_levels": int((buf > 0).sum()),
+        stats.append(st3)
+        per_array.append({"array": arrays[j][0], "global_levels": int((st3[0] > 0).sum()),
+                          "levels_moving_keys": int((st3[2] > 0).sum()),
                           "level_launches": launches[j], "finish_keys": fk, "copy_keys": ck})
         del k
 
@@ -904,7 +921,7 @@ def main() -> int:
         i1 = starts[q + 1] if q + 1 < len(starts) else got
         for i in range(i0, i1):
             lvl = int(lv[i])
-            alg[i] = float(live[j][lvl]) * ((2 * K + I) if lvl == 0 else 2 * (K + I))
+            alg[i] = level_alg_bytes(stats[j], lvl, K, I)
     ms = ms[:got]
     cap = got
     level_time_s = float(ms.astype(np.float64).sum()) / 1e3

@@ -403,6 +403,16 @@ int bsort_level_stats(const void *scratch, void *stream, uint64_t *live_keys,
                       uint32_t *live_segments, uint32_t *tiles, int max_levels,
                       uint64_t *finish_keys, uint64_t *copy_keys);
 
+/* The same call's byte accounting, per level, read synchronously on
+ * `stream`: the live keys whose indices are still the identity (never
+ * moved, so the level reads no index for them) and the keys of segments
+ * whose split moved them (a split with an empty side moves nothing).  A
+ * level reads K bytes per live key and I per live key with real indices,
+ * and writes K + I per moved key.  Either output may be NULL.  Returns the
+ * number of levels filled (<= max_levels), or a negative status. */
+int bsort_level_bytes(const void *scratch, void *stream, uint64_t *iota_keys,
+                      uint64_t *moved_keys, int max_levels);
+
 /* While armed, each launch of the global-level kernel (by any call of this
  * process) carries a pair of hipEvents that take the kernel's own start and
  * end times from its dispatch on the call's stream, for the first

@@ -42,7 +42,7 @@ SYMBOLS = ["bsort_scratch_bytes", "bsort_sort", "bsort_segmented", "bsort_segmen
            "bsort_scratch_bytes128", "bsort_sort128", "bsort_sort_layout",
            "bsort_inplace_scratch_bytes", "bsort_sort_inplace", "bsort_segmented_inplace",
            "bsort_scatter", "bsort_autotune_save", "bsort_autotune_load",
-           "bsort_segmented_noalloc", "bsort_levels"] + \
+           "bsort_segmented_noalloc", "bsort_levels", "bsort_level_bytes"] + \
     [f"bsort_{t}" for t in TYPED]
 
 lib.bsort_scratch_bytes.argtypes = [_i, _u64, _u64, _i, _u32]
@@ -59,6 +59,8 @@ lib.bsort_segmented_noalloc.argtypes = [_vp, _i, _i, _vp, _u64, _u64, _u32, _vp,
 lib.bsort_segmented_noalloc.restype = _i
 lib.bsort_levels.argtypes = [_vp, _i, _i, _vp, _u64, _u64, _u32, _i, _vp, _vp, _sz, _vp]
 lib.bsort_levels.restype = _i
+lib.bsort_level_bytes.argtypes = [_vp, _vp, _vp, _vp, _i]
+lib.bsort_level_bytes.restype = _i
 for t in ("f32", "i32"):
     fn = getattr(lib, f"bsort_segmented_{t}")
     fn.argtypes = [_vp, _vp, _u64, _u64, _u32, _vp, _vp, _sz, _vp]
@@ -141,6 +143,7 @@ bsort_sort = lib.bsort_sort
 bsort_segmented = lib.bsort_segmented
 bsort_segmented_noalloc = lib.bsort_segmented_noalloc
 bsort_levels = lib.bsort_levels
+bsort_level_bytes = lib.bsort_level_bytes
 bsort_segmented_f32 = lib.bsort_segmented_f32
 bsort_segmented_i32 = lib.bsort_segmented_i32
 bsort_backward_scatter = lib.bsort_backward_scatter

@@ -1680,6 +1680,22 @@ int bsort_level_stats(const void *scratch, void *stream, uint64_t *live_keys,
   return m;
 }
 
+int bsort_level_bytes(const void *scratch, void *stream, uint64_t *iota_keys,
+                      uint64_t *moved_keys, int max_levels) {
+  if (!scratch || max_levels < 0) return BSORT_EINVAL;
+  Header h;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = hipMemcpyAsync(&h, scratch, sizeof h, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "bsort_level_bytes");
+  const int m = max_levels < MAX_LEVELS ? max_levels : MAX_LEVELS;
+  for (int i = 0; i < m; ++i) {
+    if (iota_keys) iota_keys[i] = h.iota_keys[i];
+    if (moved_keys) moved_keys[i] = h.moved_keys[i];
+  }
+  return m;
+}
+
 int bsort_timing_arm(int capacity) {
   timing_free();
   if (capacity <= 0) return BSORT_OK;

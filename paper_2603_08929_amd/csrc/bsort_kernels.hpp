@@ -94,6 +94,8 @@ struct Header {
   uint64_t live_keys[MAX_LEVELS]; // per level: keys in live segments
   uint32_t bar_grp[8];         // tail-kernel grid barrier: arrivals per block group
   uint32_t bar_top;            // ... and groups complete
+  uint64_t iota_keys[MAX_LEVELS];  // per level: live keys whose indices are still the identity
+  uint64_t moved_keys[MAX_LEVELS]; // per level: keys of segments whose split moved them
 };
 
 // ---------------------------------------------------------------- helpers
@@ -356,11 +358,15 @@ __device__ void emit_children(const ListArgs &a, Child (&ch)[2]) {
   const int lane = threadIdx.x & 63;
   // live: slots and tiles packed in one 64-bit counter so that slot order
   // and tile order agree
-  uint64_t mine = 0, klive = 0, kfin = 0, kcpy = 0;
+  uint64_t mine = 0, klive = 0, kiota = 0, kfin = 0, kcpy = 0;
   uint32_t nfin = 0, nfs = 0, nft = 0, nfm = 0, ncpy = 0;
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
-    if (ch[c].kind == KIND_LIVE) { mine += (1ull << 32) | ch[c].tiles; klive += ch[c].len; }
+    if (ch[c].kind == KIND_LIVE) {
+      mine += (1ull << 32) | ch[c].tiles;
+      klive += ch[c].len;
+      if (ch[c].meta & META_IOTA) kiota += ch[c].len;
+    }
     if (ch[c].kind == KIND_FINISH) {
       if (ch[c].len <= a.t_tiny) nft++;
       else if (ch[c].len <= a.t_small) nfs++;
@@ -372,10 +378,12 @@ __device__ void emit_children(const ListArgs &a, Child (&ch)[2]) {
   }
   // statistics (keys per list), one atomic per wave and list
   klive = wave_sum_u64(klive);
+  kiota = wave_sum_u64(kiota);
   kfin = wave_sum_u64(kfin);
   kcpy = wave_sum_u64(kcpy);
   if (lane == 0) {
     if (klive) atomic_add_u64(&a.hdr->live_keys[a.next_level], klive);
+    if (kiota) atomic_add_u64(&a.hdr->iota_keys[a.next_level], kiota);
     if (kfin) atomic_add_u64(&a.hdr->finish_keys, kfin);
     if (kcpy) atomic_add_u64(&a.hdr->copy_keys, kcpy);
   }
@@ -542,6 +550,7 @@ __device__ __forceinline__ void plan_body(const PlanArgs &a) {
     ch[0].kind = ch[1].kind = KIND_NONE;
     ch[0].tiles = ch[1].tiles = 0;
     ch[0].cbase = ch[1].cbase = 0;
+    uint64_t kmoved = 0;
     if (q < S) {
       const Seg p = a.live[q];
       uint64_t and_lo = ~0ull, or_lo = 0, and_hi = ~0ull, or_hi = 0;
@@ -573,6 +582,7 @@ __device__ __forceinline__ void plan_body(const PlanArgs &a) {
       // where the children's keys are: moved to the other buffer, or left
       // in place by a split with an empty side
       const bool moved = !a.inplace && F != 0 && F != p.len;
+      kmoved = moved ? p.len : 0ull;
       const uint32_t cbuf = moved ? ((p.meta & META_BUF) ^ META_BUF) : (p.meta & META_BUF);
       const uint32_t ciota = (moved || a.inplace) ? 0u : (p.meta & META_IOTA);
 #pragma unroll
@@ -617,6 +627,8 @@ __device__ __forceinline__ void plan_body(const PlanArgs &a) {
         }
       }
     }
+    kmoved = wave_sum_u64(kmoved);
+    if ((threadIdx.x & 63) == 0 && kmoved) atomic_add_u64(&a.l.hdr->moved_keys[a.level], kmoved);
     emit_children(a.l, ch);
   }
 }

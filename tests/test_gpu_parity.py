@@ -92,3 +92,34 @@ def test_scratch_poison_and_determinism():
         assert (k == outs[0][0]).all() and (i == outs[0][1]).all()
     exp_k, exp_i = gpu_util.oracle_sort("f32", bits, True)
     assert (outs[0][0] == exp_k).all() and (outs[0][1] == exp_i).all()
+
+
+def test_level_byte_accounting():
+    """bsort_level_bytes: a split with an empty side moves nothing (keys in
+    [0, 16) at the top bit) and keeps the identity indices; a split of
+    uniform keys moves every key and makes the indices real."""
+    import ctypes
+    import torch
+    n = 300007
+    for bits, moved0, iota1 in ((heavy_duplicates_u32(n, 3), 0, n),
+                                (np.random.default_rng(4).integers(0, 1 << 32, n, dtype=np.uint64)
+                                 .astype(np.uint32), n, 0)):
+        keys = gpu_util.to_device(bits, "u32")
+        ind = torch.empty(n, dtype=torch.int32, device="cuda")
+        need = _lib.bsort_scratch_bytes(4, n, 1, 1, 0)
+        scratch = torch.empty(need, dtype=torch.uint8, device="cuda")
+        _lib.check(_lib.bsort_u32(keys.data_ptr(), n, 0, ind.data_ptr(), scratch.data_ptr(), need,
+                                  gpu_util.stream()), "bsort_u32")
+        live = np.zeros(66, dtype=np.uint64)
+        iota = np.zeros(66, dtype=np.uint64)
+        moved = np.zeros(66, dtype=np.uint64)
+        _lib.bsort_level_stats(scratch.data_ptr(), gpu_util.stream(), live.ctypes.data, None, None,
+                               66, None, None)
+        assert _lib.bsort_level_bytes(scratch.data_ptr(), gpu_util.stream(), iota.ctypes.data,
+                                      moved.ctypes.data, 66) == 66
+        assert live[0] == n and iota[0] == n  # level 0: every index is the identity
+        assert moved[0] == moved0
+        assert iota[1] == iota1
+        assert (moved <= live).all() and (iota <= live).all()
+        exp_k, exp_i = gpu_util.oracle_sort("u32", bits, True)
+        np.testing.assert_array_equal(gpu_util.from_device(keys, "u32"), exp_k)
