@@ -368,12 +368,14 @@ int launch_all(KT *keys, uint64_t n, const int64_t *offsets, uint64_t B, int mod
   // levels run at lower occupancy than a level launch, so the depth leaves
   // room for skewed data).  Parts of uniform keys reach the finish size
   // after about log2(n / T) levels (T = finish size); six more levels cover
-  // the skew of normal floats and presorted runs.
+  // the skew of normal floats and presorted runs.  Below 2^22 keys a live
+  // tail level is cheap and the launches are most of the cost: one more.
   int first_tail = levels;
   if (!no_finish && !snapshot) {
     const uint64_t parts = (n + FS::TFIN - 1) / FS::TFIN;
     const int depth = parts > 1 ? 64 - __builtin_clzll(parts - 1) : 0;  // ceil(log2(parts))
-    first_tail = depth + 6 < levels ? depth + 6 : levels;
+    const int margin = n >= (1ull << 22) ? 6 : 1;
+    first_tail = depth + margin < levels ? depth + margin : levels;
   }
   for (int lvl = 0; lvl < first_tail; ++lvl) {
     PrepArgs<KT> ca;

@@ -715,16 +715,21 @@ __device__ __forceinline__ void prep_body(const PrepArgs<KT> &a, uint32_t chunk)
   __shared__ uint32_t s_tail[4], s_hh[4], s_last;
   __shared__ uint64_t s_v[256];
   __shared__ uint32_t s_f[256];
+  // the chunk's tiles that have to be counted here, for the whole workgroup
+  __shared__ uint64_t s_need[4];
+  __shared__ uint64_t s_tst[PREP_TILES], s_tln[PREP_TILES];
+  __shared__ uint32_t s_tmt[PREP_TILES], s_tj[PREP_TILES], s_list[PREP_TILES], s_cres[PREP_TILES];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const uint64_t pk = ld_relaxed(&a.hdr->packed[a.level]);
   const uint32_t S = (uint32_t)(pk >> 32), ntiles = (uint32_t)pk;
   const uint32_t nchunks = (ntiles + PREP_TILES - 1) / PREP_TILES;
   if (chunk >= nchunks) return;
+  const bool spread = nchunks < 64;  // few workgroups: the chunk's waves share its counting
   const uint32_t t0 = chunk * PREP_TILES + (uint32_t)wave * 64;
   const uint32_t t = t0 + (uint32_t)lane;
   const bool valid = t < ntiles;
   uint32_t c = 0;
-  bool head = false;
+  bool head = false, need = false;
   if (t0 < ntiles) {
     const uint32_t s0 = wave_search_le(S, [&](uint32_t i) { return a.live[i].tile0 <= t0; });
     // bit d of M: a segment starts at tile t0 + d (d >= 1)
@@ -743,28 +748,93 @@ __device__ __forceinline__ void prep_body(const PrepArgs<KT> &a, uint32_t chunk)
     head = valid && j == 0;
     const bool counted = (sg.meta & META_PRE) != 0;
     if (valid && counted) c = a.cnt_in[sg.cbase + j];
-    uint64_t todo = __ballot(valid && !counted);
-    while (todo) {
+    need = valid && !counted;
+    if (!spread) {
+      // a wave counts its own tiles
+      uint64_t todo = __ballot(need);
+      while (todo) {
+        uint32_t who[RB], cnt[RB];
+        KT k[RB][IPT];
+        int bit[RB];
+        uint32_t f[RB];
+#pragma unroll
+        for (int u = 0; u < RB; ++u) {
+          who[u] = todo ? (uint32_t)(__ffsll((unsigned long long)todo) - 1) : 64u;
+          todo &= todo ? todo - 1 : 0ull;
+          const int wl = who[u] < 64u ? (int)who[u] : 0;
+          const uint32_t mt = (uint32_t)__builtin_amdgcn_readlane((int)sg.meta, wl);
+          const uint64_t st =
+              (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)sg.start, wl) |
+              ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(sg.start >> 32), wl)
+               << 32);
+          const uint64_t ln =
+              who[u] < 64u
+                  ? ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)sg.len, wl) |
+                     ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(sg.len >> 32),
+                                                                    wl)
+                      << 32))
+                  : 0ull;
+          const uint32_t jj = (uint32_t)__builtin_amdgcn_readlane((int)j, wl);
+          bit[u] = (int)(mt & BIT_MASK);
+          f[u] = (uint32_t)flip_of(bit[u], a.w, a.mode, a.desc, (mt & META_SIGN) ? 1 : 0);
+          tile_keys<KT, IPT>(a.keys[(mt & META_BUF) ? 1 : 0], st, ln, (uint64_t)jj * TILE, k[u],
+                             cnt[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < RB; ++u) {
+          uint32_t n = 0;
+#pragma unroll
+          for (int i = 0; i < IPT; ++i) {
+            const bool fr = (uint32_t)(i * 64 + lane) < cnt[u] &&
+                            ((((RT)k[u][i] >> bit[u]) & 1u) ^ f[u]) == 0;
+            n += (uint32_t)__popcll(__ballot(fr));
+          }
+          if ((uint32_t)lane == who[u]) c = n;
+        }
+      }
+    } else if (need) {
+      s_tst[tid] = sg.start;
+      s_tln[tid] = sg.len;
+      s_tmt[tid] = sg.meta;
+      s_tj[tid] = j;
+    }
+  }
+  // Tiles whose counts the previous level did not make (level 0, segments
+  // that reached their bit by skipping) are counted from their keys: by
+  // their own wave when the level has many chunks, else by the whole
+  // workgroup, RB tiles at a time per wave, so that a chunk whose tiles to
+  // count sit in one wave does not wait on that wave alone.
+  if (!spread) need = false;
+  const uint64_t nm = spread ? __ballot(need) : 0ull;
+  if (spread && lane == 0) s_need[wave] = nm;
+  if (spread) __syncthreads();
+  uint32_t total = 0, off = 0;
+  if (spread) {
+#pragma unroll
+    for (int w2 = 0; w2 < 4; ++w2) {
+      const uint32_t k = (uint32_t)__popcll(s_need[w2]);
+      if (w2 < wave) off += k;
+      total += k;
+    }
+  }
+  if (total) {
+    const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+    if (need) s_list[off + (uint32_t)__popcll(nm & below)] = (uint32_t)tid;
+    __syncthreads();
+    for (uint32_t base = (uint32_t)wave * RB; base < total; base += 4 * RB) {
       uint32_t who[RB], cnt[RB];
       KT k[RB][IPT];
       int bit[RB];
       uint32_t f[RB];
 #pragma unroll
       for (int u = 0; u < RB; ++u) {
-        who[u] = todo ? (uint32_t)(__ffsll((unsigned long long)todo) - 1) : 64u;
-        todo &= todo ? todo - 1 : 0ull;
-        const int wl = who[u] < 64u ? (int)who[u] : 0;
-        const uint32_t mt = (uint32_t)__builtin_amdgcn_readlane((int)sg.meta, wl);
-        const uint64_t st = (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)sg.start, wl) |
-                            ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(sg.start >> 32), wl) << 32);
-        const uint64_t ln = who[u] < 64u
-            ? ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)sg.len, wl) |
-               ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(sg.len >> 32), wl) << 32))
-            : 0ull;
-        const uint32_t jj = (uint32_t)__builtin_amdgcn_readlane((int)j, wl);
+        const bool v = base + u < total;
+        who[u] = v ? s_list[base + u] : 0u;
+        const uint32_t mt = s_tmt[who[u]];
         bit[u] = (int)(mt & BIT_MASK);
         f[u] = (uint32_t)flip_of(bit[u], a.w, a.mode, a.desc, (mt & META_SIGN) ? 1 : 0);
-        tile_keys<KT, IPT>(a.keys[(mt & META_BUF) ? 1 : 0], st, ln, (uint64_t)jj * TILE, k[u], cnt[u]);
+        tile_keys<KT, IPT>(a.keys[(mt & META_BUF) ? 1 : 0], s_tst[who[u]], v ? s_tln[who[u]] : 0ull,
+                           (uint64_t)s_tj[who[u]] * TILE, k[u], cnt[u]);
       }
 #pragma unroll
       for (int u = 0; u < RB; ++u) {
@@ -775,9 +845,11 @@ __device__ __forceinline__ void prep_body(const PrepArgs<KT> &a, uint32_t chunk)
                           ((((RT)k[u][i] >> bit[u]) & 1u) ^ f[u]) == 0;
           n += (uint32_t)__popcll(__ballot(fr));
         }
-        if ((uint32_t)lane == who[u]) c = n;
+        if (lane == 0 && base + u < total) s_cres[who[u]] = n;
       }
     }
+    __syncthreads();
+    if (need) c = s_cres[tid];
   }
   // exclusive scan of c over the chunk, restarting at segment starts
   const uint32_t inc = wave_incl_scan_dpp(c);
