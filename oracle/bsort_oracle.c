@@ -39,115 +39,130 @@ typedef struct {
   unsigned char *touched; /* (w+1) x n, set where a row was written */
 } bso_ctx;
 
-/* Row of the breadth-first snapshot written after partitioning on mask m:
- * the top bit (m = 2^(w-1)) is row 1, bit 0 is row w. */
-static int row_of(const bso_ctx *c, uint64_t m) {
-  int b = 0;
-  while ((m >> b) != 1) b++;
-  return c->w - b;
+/* Section II: the i-th partitioning step (1 <= i <= s, s = the key width)
+ * tests the single-bit mask m = 1 << (s - i), most significant bit first.
+ * The breadth-first snapshot row written after step i is row i. */
+static uint64_t step_mask(const bso_ctx *c, int i) {
+  return (uint64_t)1 << (c->w - i);
 }
 
-static void record(bso_ctx *c, uint64_t m, uint64_t ps, uint64_t pe) {
+static void record(bso_ctx *c, int i, uint64_t ps, uint64_t pe) {
   if (!c->snap && !c->snap_i) return;
-  const uint64_t r = (uint64_t)row_of(c, m);
-  for (uint64_t i = ps; i < pe; ++i) {
-    if (c->snap) c->snap[r * c->n + i] = c->a[i];
-    if (c->snap_i && c->idx) c->snap_i[r * c->n + i] = c->idx[i];
-    c->touched[r * c->n + i] = 1;
+  const uint64_t r = (uint64_t)i;
+  for (uint64_t j = ps; j < pe; ++j) {
+    if (c->snap) c->snap[r * c->n + j] = c->a[j];
+    if (c->snap_i && c->idx) c->snap_i[r * c->n + j] = c->idx[j];
+    c->touched[r * c->n + j] = 1;
   }
 }
 
 /*
- * Algorithm 1 (singlePassBSort).  An element goes to the front part
- * [ps, k) when (asc and its masked bit is 0) or (not asc and the bit is 1);
- * returns k.  Lomuto flavour: the paper's swap loop.  Stable flavour: the
- * same split with both sides in their input order (the order shown in the
- * traces of Figs. 1 and 2).
+ * The two sub-arrays of a step (Section II's invariants): a' holds the
+ * elements with (a AND m) != 0, a'' those with (a AND m) == 0.  The
+ * direction decides which one comes first: a'' when ascending (a clear bit
+ * is the smaller value), a' when descending.
  */
-static uint64_t single_pass_bsort(bso_ctx *c, uint64_t m, uint64_t ps,
-                                  uint64_t pe, int asc) {
-  uint64_t *a = c->a;
-  int64_t *idx = c->idx;
+static int joins_first(uint64_t key, uint64_t m, int asc) {
+  const int in_a1 = (key & m) != 0; /* a' */
+  return asc ? !in_a1 : in_a1;
+}
+
+static void exchange(bso_ctx *c, uint64_t x, uint64_t y) {
+  const uint64_t t = c->a[x];
+  c->a[x] = c->a[y];
+  c->a[y] = t;
+  if (c->idx) {
+    const int64_t u = c->idx[x];
+    c->idx[x] = c->idx[y];
+    c->idx[y] = u;
+  }
+}
+
+/*
+ * One partitioning step (Algorithm 1, singlePassBSort) on [ps, pe): the
+ * sub-array that comes first ends up in [ps, k), the other in [k, pe);
+ * returns k.
+ *  - BSO_LOMUTO, in place: [ps, k) always holds exactly the first-part
+ *    elements met so far, so each further one is exchanged into slot k.
+ *  - BSO_STABLE: both sub-arrays in their input order (the order the traces
+ *    of Figs. 1 and 2 show), the second one through a staging buffer.
+ */
+static uint64_t partition_step(bso_ctx *c, int i, uint64_t ps, uint64_t pe,
+                               int asc) {
+  const uint64_t m = step_mask(c, i);
   uint64_t k = ps;
   if (c->flavour == BSO_LOMUTO) {
-    for (uint64_t i = ps; i < pe; ++i) {
-      const int set = (a[i] & m) != 0;
-      if ((asc && !set) || (!asc && set)) {
-        uint64_t t = a[i]; a[i] = a[k]; a[k] = t;
-        if (idx) { int64_t u = idx[i]; idx[i] = idx[k]; idx[k] = u; }
-        k++;
-      }
-    }
+    for (uint64_t j = ps; j < pe; ++j)
+      if (joins_first(c->a[j], m, asc)) exchange(c, j, k++);
   } else {
+    /* first-part elements move down to slot k in input order; the others
+     * wait in the staging buffer, in input order, and follow them */
     uint64_t nsecond = 0;
-    for (uint64_t i = ps; i < pe; ++i) {
-      const int set = (a[i] & m) != 0;
-      if ((asc && !set) || (!asc && set)) {
-        a[k] = a[i];
-        if (idx) idx[k] = idx[i];
+    for (uint64_t j = ps; j < pe; ++j) {
+      if (joins_first(c->a[j], m, asc)) {
+        c->a[k] = c->a[j];
+        if (c->idx) c->idx[k] = c->idx[j];
         k++;
       } else {
-        c->tmp_a[nsecond] = a[i];
-        if (idx) c->tmp_i[nsecond] = idx[i];
+        c->tmp_a[nsecond] = c->a[j];
+        if (c->idx) c->tmp_i[nsecond] = c->idx[j];
         nsecond++;
       }
     }
-    memcpy(a + k, c->tmp_a, nsecond * sizeof(uint64_t));
-    if (idx) memcpy(idx + k, c->tmp_i, nsecond * sizeof(int64_t));
+    memcpy(c->a + k, c->tmp_a, nsecond * sizeof(uint64_t));
+    if (c->idx) memcpy(c->idx + k, c->tmp_i, nsecond * sizeof(int64_t));
   }
-  record(c, m, ps, pe);
+  record(c, i, ps, pe);
   return k;
 }
 
-/* Algorithm 2 (binaryQuickSort): partition on m, then sort both sides on
- * the next lower bit until the mask is exhausted. */
-static void binary_quick_sort(bso_ctx *c, uint64_t m, uint64_t ps,
-                              uint64_t pe, int asc) {
-  if (pe - ps < 2 || m == 0) return;
-  const uint64_t k = single_pass_bsort(c, m, ps, pe, asc);
-  const uint64_t m2 = m >> 1;
+/* Algorithm 2 (binaryQuickSort): a step splits the range, then both
+ * sub-arrays are sorted from the next step on.  A range of fewer than two
+ * elements, or a step past s, is left as it is (reading R2 of the design
+ * notes: the result is the same, without 2^s empty calls). */
+static void sort_from_step(bso_ctx *c, int i, uint64_t ps, uint64_t pe,
+                           int asc) {
+  if (pe - ps < 2 || i > c->w) return;
 #if BSO_MUTANT == 8
-  /* mutant: stops one bit early (bit 0 never partitioned) */
-  if (m2 == 1) return;
+  /* mutant: stops one bit early (the last step, bit 0, never runs) */
+  if (i == c->w) return;
 #endif
-  if (m2 == 0) return;
-  binary_quick_sort(c, m2, ps, k, asc);
-  binary_quick_sort(c, m2, k, pe, asc);
+  const uint64_t k = partition_step(c, i, ps, pe, asc);
+  sort_from_step(c, i + 1, ps, k, asc);
+  sort_from_step(c, i + 1, k, pe, asc);
 }
 
-/* Algorithm 5 (bsortF): exponent bits by recursion; once the mask reaches
- * the lowest exponent bit (m = 1 << mant_bits) the mantissa is sorted as an
- * unsigned integer with Algorithm 2. */
-static void bsort_f(bso_ctx *c, uint64_t m, uint64_t ps, uint64_t pe,
-                    int asc, int mant_bits) {
-  if (pe - ps < 2 || m == 0) return;
-  const uint64_t k = single_pass_bsort(c, m, ps, pe, asc);
-  const uint64_t m2 = m >> 1;
-  if (m == ((uint64_t)1 << mant_bits)) {
-    binary_quick_sort(c, m2, ps, k, asc);
-    binary_quick_sort(c, m2, k, pe, asc);
+/* Algorithm 5 (bsortF): the exponent bits by recursion; after the step on
+ * the lowest exponent bit (bit mant_bits, step s - mant_bits) the mantissa
+ * is sorted as an unsigned integer with Algorithm 2. */
+static void bsort_f(bso_ctx *c, int i, uint64_t ps, uint64_t pe, int asc,
+                    int mant_bits) {
+  if (pe - ps < 2 || i > c->w) return;
+  const uint64_t k = partition_step(c, i, ps, pe, asc);
+  if (c->w - i == mant_bits) {
+    sort_from_step(c, i + 1, ps, k, asc);
+    sort_from_step(c, i + 1, k, pe, asc);
     return;
   }
-  bsort_f(c, m2, ps, k, asc, mant_bits);
-  bsort_f(c, m2, k, pe, asc, mant_bits);
+  bsort_f(c, i + 1, ps, k, asc, mant_bits);
+  bsort_f(c, i + 1, k, pe, asc, mant_bits);
 }
 
 #if BSO_MUTANT >= 3 && BSO_MUTANT <= 5
 /* Mutants 3-5 sort the float fields in a wrong hierarchical order (the
  * cases refuted by Theorem 2).  masks[] lists the bits level by level. */
-static void gen_order(bso_ctx *c, const uint64_t *masks, int nm, int lvl,
-                      uint64_t sign_m, uint64_t ps, uint64_t pe, int asc,
-                      int neg) {
+static void gen_order(bso_ctx *c, const int *steps, int nm, int lvl,
+                      uint64_t ps, uint64_t pe, int asc, int neg) {
   if (pe - ps < 2 || lvl >= nm) return;
-  const uint64_t m = masks[lvl];
+  const int i = steps[lvl];
   int dir = asc;
-  if (m == sign_m) dir = !asc;
+  if (i == 1) dir = !asc; /* the sign bit */
   else if (neg) dir = !asc;
-  const uint64_t k = single_pass_bsort(c, m, ps, pe, dir);
+  const uint64_t k = partition_step(c, i, ps, pe, dir);
   int neg_lo = neg, neg_hi = neg;
-  if (m == sign_m) { neg_lo = asc ? 1 : 0; neg_hi = asc ? 0 : 1; }
-  gen_order(c, masks, nm, lvl + 1, sign_m, ps, k, asc, neg_lo);
-  gen_order(c, masks, nm, lvl + 1, sign_m, k, pe, asc, neg_hi);
+  if (i == 1) { neg_lo = asc ? 1 : 0; neg_hi = asc ? 0 : 1; }
+  gen_order(c, steps, nm, lvl + 1, ps, k, asc, neg_lo);
+  gen_order(c, steps, nm, lvl + 1, k, pe, asc, neg_hi);
 }
 #endif
 
@@ -185,63 +200,62 @@ int bso_sort(uint64_t *keys, int64_t *idx, uint64_t n, int w, int mode,
     }
   }
 
-  const uint64_t top = (uint64_t)1 << (w - 1);
   if (n >= 2) {
     if (mode == BSO_UNSIGNED) {
-      binary_quick_sort(&c, top, 0, n, asc);
+      sort_from_step(&c, 1, 0, n, asc);
     } else if (mode == BSO_SIGNED) {
-      /* Algorithm 3: the sign pass runs in the inverse direction, then both
-       * halves are sorted as unsigned on the remaining bits. */
+      /* Algorithm 3: the sign pass (step 1) runs in the inverse direction,
+       * then both halves are sorted as unsigned from step 2 on. */
 #if BSO_MUTANT == 2
-      const uint64_t k = single_pass_bsort(&c, top, 0, n, asc);
+      const uint64_t k = partition_step(&c, 1, 0, n, asc);
 #else
-      const uint64_t k = single_pass_bsort(&c, top, 0, n, !asc);
+      const uint64_t k = partition_step(&c, 1, 0, n, !asc);
 #endif
 #if BSO_MUTANT == 9
-      binary_quick_sort(&c, top >> 1, 0, k, !asc);
-      binary_quick_sort(&c, top >> 1, k, n, !asc);
+      sort_from_step(&c, 2, 0, k, !asc);
+      sort_from_step(&c, 2, k, n, !asc);
 #else
-      binary_quick_sort(&c, top >> 1, 0, k, asc);
-      binary_quick_sort(&c, top >> 1, k, n, asc);
+      sort_from_step(&c, 2, 0, k, asc);
+      sort_from_step(&c, 2, k, n, asc);
 #endif
     } else {
 #if BSO_MUTANT >= 3 && BSO_MUTANT <= 5
-      uint64_t masks[64];
+      int steps[64]; /* the step of bit b is w - b */
       int nm = 0;
       const int e_hi = w - 2, e_lo = mant_bits; /* exponent bits */
       const int m_hi = mant_bits - 1;           /* mantissa bits */
 #if BSO_MUTANT == 3 /* sign, mantissa, exponent (Theorem 2, case 2) */
-      masks[nm++] = top;
-      for (int b = m_hi; b >= 0; --b) masks[nm++] = (uint64_t)1 << b;
-      for (int b = e_hi; b >= e_lo; --b) masks[nm++] = (uint64_t)1 << b;
+      steps[nm++] = 1;
+      for (int b = m_hi; b >= 0; --b) steps[nm++] = w - b;
+      for (int b = e_hi; b >= e_lo; --b) steps[nm++] = w - b;
 #elif BSO_MUTANT == 4 /* exponent, sign, mantissa (case 1) */
-      for (int b = e_hi; b >= e_lo; --b) masks[nm++] = (uint64_t)1 << b;
-      masks[nm++] = top;
-      for (int b = m_hi; b >= 0; --b) masks[nm++] = (uint64_t)1 << b;
+      for (int b = e_hi; b >= e_lo; --b) steps[nm++] = w - b;
+      steps[nm++] = 1;
+      for (int b = m_hi; b >= 0; --b) steps[nm++] = w - b;
 #else /* mantissa, exponent, sign (case 1) */
-      for (int b = m_hi; b >= 0; --b) masks[nm++] = (uint64_t)1 << b;
-      for (int b = e_hi; b >= e_lo; --b) masks[nm++] = (uint64_t)1 << b;
-      masks[nm++] = top;
+      for (int b = m_hi; b >= 0; --b) steps[nm++] = w - b;
+      for (int b = e_hi; b >= e_lo; --b) steps[nm++] = w - b;
+      steps[nm++] = 1;
 #endif
-      gen_order(&c, masks, nm, 0, top, 0, n, asc, 0);
+      gen_order(&c, steps, nm, 0, 0, n, asc, 0);
 #else
-      /* Algorithm 4: sign pass in the inverse direction.  With !asc the
-       * front part [0, k) holds the set sign bits (negatives) when sorting
-       * ascending and the clear ones when sorting descending. */
+      /* Algorithm 4: sign pass (step 1) in the inverse direction.  With
+       * !asc the first part [0, k) holds the set sign bits (negatives) when
+       * sorting ascending and the clear ones when sorting descending. */
 #if BSO_MUTANT == 2
-      const uint64_t k = single_pass_bsort(&c, top, 0, n, asc);
+      const uint64_t k = partition_step(&c, 1, 0, n, asc);
 #else
-      const uint64_t k = single_pass_bsort(&c, top, 0, n, !asc);
+      const uint64_t k = partition_step(&c, 1, 0, n, !asc);
 #endif
       uint64_t neg_ps = asc ? 0 : k, neg_pe = asc ? k : n;
       uint64_t pos_ps = asc ? k : 0, pos_pe = asc ? n : k;
 #if BSO_MUTANT == 1
       /* mutant: the literal pseudocode passes asc to both halves */
-      bsort_f(&c, top >> 1, neg_ps, neg_pe, asc, mant_bits);
+      bsort_f(&c, 2, neg_ps, neg_pe, asc, mant_bits);
 #else
-      bsort_f(&c, top >> 1, neg_ps, neg_pe, !asc, mant_bits);
+      bsort_f(&c, 2, neg_ps, neg_pe, !asc, mant_bits);
 #endif
-      bsort_f(&c, top >> 1, pos_ps, pos_pe, asc, mant_bits);
+      bsort_f(&c, 2, pos_ps, pos_pe, asc, mant_bits);
 #endif
     }
   }
@@ -361,7 +375,7 @@ int bso_sort128(uint64_t *lo, uint64_t *hi, int64_t *idx, uint64_t n, int mode,
 /*
  * Quickselect with the paper's partition: run the same sequence of
  * partitions as bso_sort (stable flavour) but descend only into the side
- * that holds sorted position j.  The mask sequence and directions are those
+ * that holds sorted position j.  The step sequence and directions are those
  * of Algorithms 2-5, tracked explicitly instead of by recursion.
  */
 int bso_select(const uint64_t *keys, uint64_t n, int w, int mode,
@@ -389,12 +403,11 @@ int bso_select(const uint64_t *keys, uint64_t n, int w, int mode,
   }
 
   uint64_t ps = 0, pe = n;
-  uint64_t m = (uint64_t)1 << (w - 1);
   int dir = asc;
   if (mode != BSO_UNSIGNED) dir = !asc; /* sign pass of Alg. 3 / Alg. 4 */
   int first = 1;
-  while (pe - ps >= 2 && m != 0) {
-    const uint64_t k = single_pass_bsort(&c, m, ps, pe, dir);
+  for (int i = 1; pe - ps >= 2 && i <= w; ++i) {
+    const uint64_t k = partition_step(&c, i, ps, pe, dir);
     if (j < k) pe = k; else ps = k;
     if (first && mode != BSO_UNSIGNED) {
       /* after the sign pass: the chosen half's direction */
@@ -408,7 +421,6 @@ int bso_select(const uint64_t *keys, uint64_t n, int w, int mode,
       }
     }
     first = 0;
-    m >>= 1;
   }
   *key_out = a[j];
   *idx_out = ix[j];
