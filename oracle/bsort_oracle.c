@@ -118,8 +118,9 @@ static uint64_t partition_step(bso_ctx *c, int i, uint64_t ps, uint64_t pe,
 
 /* Algorithm 2 (binaryQuickSort): a step splits the range, then both
  * sub-arrays are sorted from the next step on.  A range of fewer than two
- * elements, or a step past s, is left as it is (reading R2 of the design
- * notes: the result is the same, without 2^s empty calls). */
+ * elements, or a step past s, is left as it is: splitting it changes
+ * nothing, and stopping there avoids the 2^s calls a literal recursion
+ * makes (Theorem 4's linear bound assumes it stops). */
 static void sort_from_step(bso_ctx *c, int i, uint64_t ps, uint64_t pe,
                            int asc) {
   if (pe - ps < 2 || i > c->w) return;
