@@ -155,7 +155,7 @@ size_t up256(size_t x) { return (x + 255) & ~(size_t)255; }
 // offsets (`meta` bytes from the start of pc).
 struct Layout {
   size_t hdr, cnts, segs[2], acc[2], split[2], tmap, pc, agg, carry, fin, fins, fint, finm, cpy,
-      meta, keys1, idx0, idx1, keys0, total;
+      tiny[2], meta, keys1, idx0, idx1, keys0, total;
   uint64_t smax, tmax, fmax, cmax, cn, nchunks;
 };
 
@@ -189,6 +189,10 @@ bool make_layout(int key_bytes, uint64_t n, uint64_t B, bool with_idx, uint32_t 
   L->fint = off; off = up256(off + L->fmax * sizeof(Seg));
   L->finm = off; off = up256(off + L->fmax * sizeof(Seg));
   L->cpy = off; off = up256(off + L->cmax * sizeof(Seg));
+  // without the LDS finish: the tiny-segment lists of two level parities
+  L->tiny[0] = L->tiny[1] = 0;
+  if (no_finish)
+    for (int i = 0; i < 2; ++i) { L->tiny[i] = off; off = up256(off + L->smax * sizeof(Seg)); }
   L->keys1 = off; off = up256(off + n * (size_t)key_bytes);
   L->idx0 = L->idx1 = 0;
   if (with_idx) {
@@ -277,6 +281,12 @@ int launch_all(KT *keys, uint64_t n, const int64_t *offsets, uint64_t B, int mod
   la.t_tiny = TinyFinish::T;
   la.t_med = FS::TFIN / 2;
   la.recount = (uint32_t)(2 * L.tmax);  // never read: the prep pass counts such segments
+  la.tiny_next = nullptr;
+  Seg *tiny[2] = {nullptr, nullptr};
+  if (no_finish) {
+    tiny[0] = reinterpret_cast<Seg *>(scr + L.tiny[0]);
+    tiny[1] = reinterpret_cast<Seg *>(scr + L.tiny[1]);
+  }
 
   SeedArgs sa;
   sa.l = la;
@@ -284,6 +294,7 @@ int launch_all(KT *keys, uint64_t n, const int64_t *offsets, uint64_t B, int mod
   sa.l.acc_next = acc[0];
   sa.l.split_next = split[0];
   sa.l.next_level = 0;
+  sa.l.tiny_next = tiny[0];
   sa.offsets = offsets;
   sa.B = B;
   sa.n = n;
@@ -347,6 +358,7 @@ int launch_all(KT *keys, uint64_t n, const int64_t *offsets, uint64_t B, int mod
     pa.l.live_next = segs[(lvl + 1) & 1];
     pa.l.acc_next = acc[(lvl + 1) & 1];
     pa.l.split_next = split[(lvl + 1) & 1];
+    pa.l.tiny_next = tiny[(lvl + 1) & 1];
     pa.l.next_level = lvl + 1;
     pa.live = segs[lvl & 1];
     pa.acc = acc[lvl & 1];
@@ -362,6 +374,30 @@ int launch_all(KT *keys, uint64_t n, const int64_t *offsets, uint64_t B, int mod
     pa.no_finish = no_finish;
     pa.inplace = 0;
   };
+
+  // the tiny-segment pass of a level (without the LDS finish), or the
+  // write-out of a stopped sort's tiny segments
+  auto tiny_args = [&](int lvl, int snap) {
+    TinyArgs<KT> ta;
+    ta.keys[0] = kbuf[0];
+    ta.keys[1] = kbuf[1];
+    ta.idx[0] = ibuf[0];
+    ta.idx[1] = ibuf[1];
+    ta.keys_final = keys;
+    ta.idx_final = indices;
+    ta.list = tiny[lvl & 1];
+    ta.l = la;
+    ta.l.tiny_next = tiny[(lvl + 1) & 1];
+    ta.l.next_level = lvl + 1;
+    ta.level = lvl;
+    ta.w = w;
+    ta.mode = mode;
+    ta.desc = desc;
+    ta.idx64 = idx64;
+    ta.snapshot = snap;
+    return ta;
+  };
+  const uint32_t tsgrid = clamp_grid((L.smax + 255) / 256, (uint64_t)cus * 8);
 
   // Levels below `first_tail` are launched one kernel per phase; the rest
   // run in one tail launch, which ends at the first empty level (its live
@@ -394,6 +430,10 @@ int launch_all(KT *keys, uint64_t n, const int64_t *offsets, uint64_t B, int mod
       hipLaunchKernelGGL(lk, dim3(lgrid), dim3(256), 0, st, a);
     }
     hipLaunchKernelGGL(plan_kernel, dim3(pgrid), dim3(256), 0, st, pa);
+    if (no_finish) {
+      TinyArgs<KT> ta = tiny_args(lvl, 0);
+      hipLaunchKernelGGL((tiny_kernel<KT, IDX>), dim3(tsgrid), dim3(256), 0, st, ta);
+    }
   }
   if (first_tail < levels) {
     TailArgs<KT> ta;
@@ -422,6 +462,10 @@ int launch_all(KT *keys, uint64_t n, const int64_t *offsets, uint64_t B, int mod
     sn.tile = LS::TILE;
     sn.idx64 = idx64;
     hipLaunchKernelGGL((snapshot_kernel<KT, IDX>), dim3(lgrid), dim3(256), 0, st, sn);
+    if (no_finish) {
+      TinyArgs<KT> ta = tiny_args(levels, 1);
+      hipLaunchKernelGGL((tiny_kernel<KT, IDX>), dim3(tsgrid), dim3(256), 0, st, ta);
+    }
   }
 
   CopyArgs<KT> ca;
@@ -911,6 +955,7 @@ int launch_inplace(KT *keys, uint64_t n, const int64_t *offsets, uint64_t B, int
   la.t_tiny = TinyFinish::T;
   la.t_med = FS::TFIN / 2;
   la.recount = (uint32_t)(2 * L.tmax);
+  la.tiny_next = nullptr;  // the in-place levels take every segment in tiles
 
   SeedArgs sa;
   sa.l = la;

@@ -96,6 +96,7 @@ struct Header {
   uint32_t bar_top;            // ... and groups complete
   uint64_t iota_keys[MAX_LEVELS];  // per level: live keys whose indices are still the identity
   uint64_t moved_keys[MAX_LEVELS]; // per level: keys of segments whose split moved them
+  uint32_t n_tiny[MAX_LEVELS];     // per level: entries of the tiny-segment list (no-finish mode)
 };
 
 // ---------------------------------------------------------------- helpers
@@ -315,7 +316,12 @@ __global__ void validate_kernel(const int64_t *offsets, uint64_t B, uint64_t n, 
 
 // ------------------------------------------------------- work-list building
 
-constexpr int KIND_NONE = 0, KIND_LIVE = 1, KIND_FINISH = 2, KIND_COPY = 3;
+constexpr int KIND_NONE = 0, KIND_LIVE = 1, KIND_FINISH = 2, KIND_COPY = 3, KIND_TINY = 4;
+
+// Without the LDS finish (every bit a global level), a live segment of at
+// most this many keys is split by one thread per level instead of taking a
+// whole level tile.
+constexpr uint32_t TINY_MAX = 32;
 
 struct ListArgs {
   Header *hdr;
@@ -334,6 +340,7 @@ struct ListArgs {
   uint32_t t_tiny;      // ... and up to this size, one key per lane
   uint32_t t_med;       // ... and up to this size, half the full finish shape
   uint32_t recount;     // count base of segments whose counts the level did not make
+  Seg *tiny_next;       // level (lvl+1) tiny-segment list (nullptr: none)
 };
 
 struct Child {
@@ -359,7 +366,7 @@ __device__ void emit_children(const ListArgs &a, Child (&ch)[2]) {
   // live: slots and tiles packed in one 64-bit counter so that slot order
   // and tile order agree
   uint64_t mine = 0, klive = 0, kiota = 0, kfin = 0, kcpy = 0;
-  uint32_t nfin = 0, nfs = 0, nft = 0, nfm = 0, ncpy = 0;
+  uint32_t nfin = 0, nfs = 0, nft = 0, nfm = 0, ncpy = 0, ntiny = 0;
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
     if (ch[c].kind == KIND_LIVE) {
@@ -375,6 +382,11 @@ __device__ void emit_children(const ListArgs &a, Child (&ch)[2]) {
       kfin += ch[c].len;
     }
     if (ch[c].kind == KIND_COPY) { ncpy++; kcpy += ch[c].len; }
+    if (ch[c].kind == KIND_TINY) {
+      ntiny++;
+      klive += ch[c].len;
+      if (ch[c].meta & META_IOTA) kiota += ch[c].len;
+    }
   }
   // statistics (keys per list), one atomic per wave and list
   klive = wave_sum_u64(klive);
@@ -393,14 +405,16 @@ __device__ void emit_children(const ListArgs &a, Child (&ch)[2]) {
   const uint32_t inc_ft = wave_incl_scan_u32(nft);
   const uint32_t inc_fm = wave_incl_scan_u32(nfm);
   const uint32_t inc_cpy = wave_incl_scan_u32(ncpy);
+  const uint32_t inc_tiny = wave_incl_scan_u32(ntiny);
   const uint64_t tot_live = __shfl(inc_live, 63);
   const uint32_t tot_fin = __shfl(inc_fin, 63);
   const uint32_t tot_fs = __shfl(inc_fs, 63);
   const uint32_t tot_ft = __shfl(inc_ft, 63);
   const uint32_t tot_fm = __shfl(inc_fm, 63);
   const uint32_t tot_cpy = __shfl(inc_cpy, 63);
+  const uint32_t tot_tiny = __shfl(inc_tiny, 63);
   uint64_t b_live = 0;
-  uint32_t b_fin = 0, b_fs = 0, b_ft = 0, b_fm = 0, b_cpy = 0;
+  uint32_t b_fin = 0, b_fs = 0, b_ft = 0, b_fm = 0, b_cpy = 0, b_tiny = 0;
   if (lane == 0) {
     if (tot_live) b_live = atomic_add_u64(&a.hdr->packed[a.next_level], tot_live);
     if (tot_fin) b_fin = atomic_add_u32(&a.hdr->n_finish, tot_fin);
@@ -408,6 +422,7 @@ __device__ void emit_children(const ListArgs &a, Child (&ch)[2]) {
     if (tot_ft) b_ft = atomic_add_u32(&a.hdr->n_finish_tiny, tot_ft);
     if (tot_fm) b_fm = atomic_add_u32(&a.hdr->n_finish_med, tot_fm);
     if (tot_cpy) b_cpy = atomic_add_u32(&a.hdr->n_copy, tot_cpy);
+    if (tot_tiny) b_tiny = atomic_add_u32(&a.hdr->n_tiny[a.next_level], tot_tiny);
   }
   b_live = __shfl(b_live, 0);
   b_fin = __shfl(b_fin, 0);
@@ -415,12 +430,14 @@ __device__ void emit_children(const ListArgs &a, Child (&ch)[2]) {
   b_ft = __shfl(b_ft, 0);
   b_fm = __shfl(b_fm, 0);
   b_cpy = __shfl(b_cpy, 0);
+  b_tiny = __shfl(b_tiny, 0);
   uint64_t pos = b_live + (inc_live - mine);
   uint32_t fpos = b_fin + (inc_fin - nfin);
   uint32_t fspos = b_fs + (inc_fs - nfs);
   uint32_t ftpos = b_ft + (inc_ft - nft);
   uint32_t fmpos = b_fm + (inc_fm - nfm);
   uint32_t cpos = b_cpy + (inc_cpy - ncpy);
+  uint32_t tpos = b_tiny + (inc_tiny - ntiny);
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
     Seg s;
@@ -453,6 +470,8 @@ __device__ void emit_children(const ListArgs &a, Child (&ch)[2]) {
       else a.fin[fpos++] = s;
     } else if (ch[c].kind == KIND_COPY) {
       a.cpy[cpos++] = s;
+    } else if (ch[c].kind == KIND_TINY) {
+      a.tiny_next[tpos++] = s;
     }
   }
 }
@@ -504,6 +523,8 @@ __global__ void seed_kernel(SeedArgs a) {
       } else if (len >= 2) {
         if (!a.no_finish && len <= a.l.t_fin) {
           ch[0].kind = KIND_FINISH;
+        } else if (a.l.tiny_next && len <= TINY_MAX) {
+          ch[0].kind = KIND_TINY;
         } else {
           ch[0].kind = KIND_LIVE;
           ch[0].tiles = (uint32_t)((len + a.l.tile - 1) / a.l.tile);
@@ -616,6 +637,9 @@ __device__ __forceinline__ void plan_body(const PlanArgs &a) {
         } else if (!a.no_finish && len <= a.l.t_fin) {
           ch[c].meta = meta | (uint32_t)nb;
           ch[c].kind = KIND_FINISH;
+        } else if (a.l.tiny_next && len <= TINY_MAX) {
+          ch[c].meta = meta | (uint32_t)nb;
+          ch[c].kind = KIND_TINY;
         } else {
           // the level counted this child's front keys on bit - 1 per tile;
           // a child that skipped to a lower bit is counted by the prep pass
@@ -1377,6 +1401,128 @@ __global__ __launch_bounds__(256) void tail_kernel(TailArgs<KT> a) {
     if (!tail_level<KT, IDX, IPT>(odd ? a.prep1 : a.prep0, odd ? a.lvl1 : a.lvl0,
                                   odd ? a.plan1 : a.plan0, a.hdr, lvl, epoch))
       break;
+  }
+}
+
+// ------------------------------------------------------------ tiny segments
+//
+// Without the LDS finish every bit is a global level, and late levels hold
+// many segments of a few keys: giving each one a whole level tile would
+// make such a level cost a tile per segment.  A segment of at most TINY_MAX
+// keys is split by one thread instead: its keys in registers, the same
+// stable split on its bit as a level tile makes (front keys, then back
+// keys, both in input order, into the other buffer; a split with an empty
+// side moves nothing), and its children go to the next level's tiny list,
+// or, once done (one key, or bit 0 split), straight to the caller's
+// buffers.  With `snapshot` set the segments are only written out as they
+// stand (a sort stopped at this level).
+template <typename KT>
+struct TinyArgs {
+  KT *keys[2];
+  uint32_t *idx[2];
+  KT *keys_final;
+  void *idx_final;
+  const Seg *list;  // this level's tiny segments
+  ListArgs l;       // the next level's tiny list (tiny_next, next_level, hdr)
+  int level, w, mode, desc, idx64, snapshot;
+};
+
+// A tiny segment's keys (its first `len` registers) whose side is `side`
+// (front 0 / back 1; all of them with side < 0), in order, to the caller's
+// buffers at [at, ...): keys when they are not there already (buf 1),
+// indices when they are not there as they stand.  An identity index is the
+// key's place in its user segment, which an identity segment starts (it
+// has never moved): ibase + its rank here.
+template <typename KT, bool IDX>
+__device__ __forceinline__ void tiny_write_out(const TinyArgs<KT> &a, const KT (&k)[TINY_MAX],
+                                               const uint32_t (&x)[TINY_MAX], uint32_t len,
+                                               int bit, uint32_t f, int side, uint64_t at,
+                                               uint32_t ibase, int buf, bool iota) {
+  uint32_t o = 0;
+#pragma unroll
+  for (uint32_t j = 0; j < TINY_MAX; ++j) {
+    if (j >= len) break;
+    if (side >= 0 && (int)((((uint64_t)k[j] >> bit) & 1u) ^ f) != side) continue;
+    if (buf) a.keys_final[at + o] = k[j];
+    if (IDX && (buf || iota || a.idx64)) {
+      const uint32_t v = iota ? ibase + o : x[j];
+      if (a.idx64) static_cast<int64_t *>(a.idx_final)[at + o] = (int64_t)v;
+      else static_cast<uint32_t *>(a.idx_final)[at + o] = v;
+    }
+    ++o;
+  }
+}
+
+template <typename KT, bool IDX>
+__global__ __launch_bounds__(256) void tiny_kernel(TinyArgs<KT> a) {
+  const uint32_t nt = ld_relaxed_u32(&a.l.hdr->n_tiny[a.level]);
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t base = blockIdx.x * blockDim.x; base < nt; base += stride) {
+    const uint32_t q = base + threadIdx.x;
+    Child ch[2];
+    ch[0].kind = ch[1].kind = KIND_NONE;
+    ch[0].tiles = ch[1].tiles = 0;
+    ch[0].cbase = ch[1].cbase = 0;
+    if (q < nt) {
+      const Seg sg = a.list[q];
+      const uint32_t len = (uint32_t)sg.len;  // 2 .. TINY_MAX
+      const int bit = (int)(sg.meta & BIT_MASK);
+      const int buf = (sg.meta & META_BUF) ? 1 : 0;
+      const bool iota = (sg.meta & META_IOTA) != 0;
+      KT k[TINY_MAX];
+      uint32_t x[TINY_MAX];
+#pragma unroll
+      for (uint32_t j = 0; j < TINY_MAX; ++j) {
+        k[j] = 0;
+        x[j] = 0;
+        if (j < len) {
+          k[j] = a.keys[buf][sg.start + j];
+          if (IDX) x[j] = iota ? j : a.idx[buf][sg.start + j];
+        }
+      }
+      if (a.snapshot) {
+        tiny_write_out<KT, IDX>(a, k, x, len, 0, 0u, -1, sg.start, 0u, buf, iota);
+      } else {
+        const uint32_t f = (uint32_t)flip_of(bit, a.w, a.mode, a.desc, (sg.meta & META_SIGN) ? 1 : 0);
+        uint32_t F = 0;
+#pragma unroll
+        for (uint32_t j = 0; j < TINY_MAX; ++j)
+          if (j < len) F += ((((uint64_t)k[j] >> bit) & 1u) ^ f) == 0u ? 1u : 0u;
+        const bool moved = F != 0 && F != len;
+        const int cb = moved ? 1 - buf : buf;
+        if (moved) {
+          uint32_t rf = 0, rb = F;
+#pragma unroll
+          for (uint32_t j = 0; j < TINY_MAX; ++j) {
+            if (j >= len) break;
+            const bool front = ((((uint64_t)k[j] >> bit) & 1u) ^ f) == 0u;
+            const uint32_t dst = front ? rf++ : rb++;
+            a.keys[cb][sg.start + dst] = k[j];
+            if (IDX) a.idx[cb][sg.start + dst] = x[j];
+          }
+        }
+        const bool ciota = !moved && iota;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          const uint32_t clen = c ? len - F : F;
+          const uint64_t cstart = sg.start + (c ? F : 0u);
+          ch[c].start = cstart;
+          ch[c].len = clen;
+          if (clen == 0) continue;
+          if (clen < 2 || bit == 0) {
+            // done: to the caller's buffers (only this side's keys)
+            tiny_write_out<KT, IDX>(a, k, x, len, bit, f, c, cstart, c ? F : 0u, cb, ciota);
+            continue;
+          }
+          // the child's sign: the side's after the sign split, else the parent's
+          uint32_t sign = (sg.meta & META_SIGN) ? META_SIGN : 0u;
+          if (bit == a.w - 1) sign = ((uint32_t)c ^ f) ? META_SIGN : 0u;
+          ch[c].meta = sign | (cb ? META_BUF : 0u) | (ciota ? META_IOTA : 0u) | (uint32_t)(bit - 1);
+          ch[c].kind = KIND_TINY;
+        }
+      }
+    }
+    emit_children(a.l, ch);
   }
 }
 
