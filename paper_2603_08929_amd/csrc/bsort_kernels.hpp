@@ -321,7 +321,7 @@ constexpr int KIND_NONE = 0, KIND_LIVE = 1, KIND_FINISH = 2, KIND_COPY = 3, KIND
 // Without the LDS finish (every bit a global level), a live segment of at
 // most this many keys is split by one thread per level instead of taking a
 // whole level tile.
-constexpr uint32_t TINY_MAX = 32;
+constexpr uint32_t TINY_MAX = 256;
 
 struct ListArgs {
   Header *hdr;
@@ -1408,14 +1408,19 @@ __global__ __launch_bounds__(256) void tail_kernel(TailArgs<KT> a) {
 //
 // Without the LDS finish every bit is a global level, and late levels hold
 // many segments of a few keys: giving each one a whole level tile would
-// make such a level cost a tile per segment.  A segment of at most TINY_MAX
-// keys is split by one thread instead: its keys in registers, the same
-// stable split on its bit as a level tile makes (front keys, then back
-// keys, both in input order, into the other buffer; a split with an empty
-// side moves nothing), and its children go to the next level's tiny list,
-// or, once done (one key, or bit 0 split), straight to the caller's
-// buffers.  With `snapshot` set the segments are only written out as they
-// stand (a sort stopped at this level).
+// make such a level cost a tile per segment.  Segments of at most TINY_MAX
+// keys go to a list of their own instead, and a wave packs consecutive
+// entries of it, whole, into one batch of 64 x TINY_IPT positions (key
+// position q at lane q % 64, item q / 64, as in a level tile).  A key finds
+// its segment from the batch's segment starts (one mask per item), and the
+// same stable split as a level tile's follows with ranks counted within the
+// segment: front keys, then back keys, both in input order, into the other
+// buffer (a split with an empty side moves nothing).  Children go to the
+// next level's tiny list, or, once done (one key, or bit 0 split), straight
+// to the caller's buffers.  With `snapshot` set the segments are only
+// written out as they stand (a sort stopped at this level).
+constexpr int TINY_IPT = 4;
+
 template <typename KT>
 struct TinyArgs {
   KT *keys[2];
@@ -1427,102 +1432,228 @@ struct TinyArgs {
   int level, w, mode, desc, idx64, snapshot;
 };
 
-// A tiny segment's keys (its first `len` registers) whose side is `side`
-// (front 0 / back 1; all of them with side < 0), in order, to the caller's
-// buffers at [at, ...): keys when they are not there already (buf 1),
-// indices when they are not there as they stand.  An identity index is the
-// key's place in its user segment, which an identity segment starts (it
-// has never moved): ibase + its rank here.
-template <typename KT, bool IDX>
-__device__ __forceinline__ void tiny_write_out(const TinyArgs<KT> &a, const KT (&k)[TINY_MAX],
-                                               const uint32_t (&x)[TINY_MAX], uint32_t len,
-                                               int bit, uint32_t f, int side, uint64_t at,
-                                               uint32_t ibase, int buf, bool iota) {
-  uint32_t o = 0;
+// Front keys of a batch at positions below x, from the items' ballots.
+__device__ __forceinline__ uint32_t batch_fronts_below(const uint64_t (&b)[TINY_IPT], uint32_t x) {
+  uint32_t c = 0;
 #pragma unroll
-  for (uint32_t j = 0; j < TINY_MAX; ++j) {
-    if (j >= len) break;
-    if (side >= 0 && (int)((((uint64_t)k[j] >> bit) & 1u) ^ f) != side) continue;
-    if (buf) a.keys_final[at + o] = k[j];
-    if (IDX && (buf || iota || a.idx64)) {
-      const uint32_t v = iota ? ibase + o : x[j];
-      if (a.idx64) static_cast<int64_t *>(a.idx_final)[at + o] = (int64_t)v;
-      else static_cast<uint32_t *>(a.idx_final)[at + o] = v;
-    }
-    ++o;
+  for (int i = 0; i < TINY_IPT; ++i) {
+    const uint32_t lo = (uint32_t)i * 64u;
+    if (x >= lo + 64u) c += (uint32_t)__popcll(b[i]);
+    else if (x > lo) c += (uint32_t)__popcll(b[i] & (~0ull >> (64u - (x - lo))));
   }
+  return c;
+}
+
+// The tiny-list children of a workgroup's TINY_WIN windows (each lane's
+// ch[v][c]), listed with one list atomic for the whole workgroup: at the
+// deepest levels nearly every entry has children, and one atomic per wave
+// and window would be the level's serial bottleneck.
+constexpr int TINY_WIN = 4;
+
+__device__ __forceinline__ void emit_tiny_block(const ListArgs &a, const Child (&ch)[TINY_WIN][2],
+                                                uint32_t (&s_n)[4], uint64_t (&s_k)[2][4],
+                                                uint32_t &s_base) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t n = 0;
+  uint64_t klive = 0, kiota = 0;
+#pragma unroll
+  for (int v = 0; v < TINY_WIN; ++v)
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+      if (ch[v][c].kind == KIND_TINY) {
+        ++n;
+        klive += ch[v][c].len;
+        if (ch[v][c].meta & META_IOTA) kiota += ch[v][c].len;
+      }
+  const uint32_t inc = wave_incl_scan_dpp(n);
+  klive = wave_sum_u64(klive);
+  kiota = wave_sum_u64(kiota);
+  if (lane == 63) s_n[wave] = inc;
+  if (lane == 0) {
+    s_k[0][wave] = klive;
+    s_k[1][wave] = kiota;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t tot = s_n[0] + s_n[1] + s_n[2] + s_n[3];
+    s_base = tot ? atomic_add_u32(&a.hdr->n_tiny[a.next_level], tot) : 0u;
+    const uint64_t kl = s_k[0][0] + s_k[0][1] + s_k[0][2] + s_k[0][3];
+    const uint64_t ki = s_k[1][0] + s_k[1][1] + s_k[1][2] + s_k[1][3];
+    if (kl) atomic_add_u64(&a.hdr->live_keys[a.next_level], kl);
+    if (ki) atomic_add_u64(&a.hdr->iota_keys[a.next_level], ki);
+  }
+  __syncthreads();
+  uint32_t pos = s_base + inc - n;
+  for (int w2 = 0; w2 < wave; ++w2) pos += s_n[w2];
+#pragma unroll
+  for (int v = 0; v < TINY_WIN; ++v)
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+      if (ch[v][c].kind == KIND_TINY) {
+        Seg sg;
+        sg.start = ch[v][c].start;
+        sg.len = ch[v][c].len;
+        sg.meta = ch[v][c].meta;
+        sg.tile0 = 0;
+        sg.cbase = 0;
+        sg.slot = 0;
+        a.tiny_next[pos++] = sg;
+      }
+  __syncthreads();  // the counts in LDS are reused by the next call
 }
 
 template <typename KT, bool IDX>
 __global__ __launch_bounds__(256) void tiny_kernel(TinyArgs<KT> a) {
+  constexpr uint32_t BATCH = 64u * TINY_IPT;
+  static_assert(TINY_MAX <= BATCH, "a tiny segment fits one batch");
+  __shared__ uint32_t s_n[4], s_base;
+  __shared__ uint64_t s_k[2][4];
+  const uint32_t lane = threadIdx.x & 63;
   const uint32_t nt = ld_relaxed_u32(&a.l.hdr->n_tiny[a.level]);
-  const uint32_t stride = gridDim.x * blockDim.x;
-  for (uint32_t base = blockIdx.x * blockDim.x; base < nt; base += stride) {
-    const uint32_t q = base + threadIdx.x;
+  // waves take equal runs of list entries, 64 at a time (a window), and
+  // list the children of TINY_WIN windows with the rest of the workgroup;
+  // every wave of a workgroup takes the same number of steps
+  const uint32_t G = gridDim.x * (blockDim.x / 64u);
+  const uint32_t g = blockIdx.x * (blockDim.x / 64u) + (threadIdx.x >> 6);
+  const uint32_t per = (nt + G - 1) / G;
+  const uint32_t e_end = (g + 1) * per < nt ? (g + 1) * per : nt;
+  const uint32_t steps = (per + 64u * TINY_WIN - 1) / (64u * TINY_WIN);
+  for (uint32_t step = 0; step < steps; ++step) {
+   Child chw[TINY_WIN][2];
+#pragma unroll
+   for (int v = 0; v < TINY_WIN; ++v) {
+    const uint32_t e = g * per + (step * TINY_WIN + (uint32_t)v) * 64u;
+    const uint32_t nwin = e < e_end ? (e_end - e < 64u ? e_end - e : 64u) : 0u;
+    const bool have = lane < nwin;
+    Seg sg = {};
+    if (have) sg = a.list[e + lane];
+    const uint32_t len = have ? (uint32_t)sg.len : 0u;
+    const uint32_t cum = wave_incl_scan_dpp(len);  // over the window
+    const uint32_t s0w = cum - len;                  // the entry's first window position
+    const int bit = (int)(sg.meta & BIT_MASK);
+    const uint32_t f = (uint32_t)flip_of(bit, a.w, a.mode, a.desc, (sg.meta & META_SIGN) ? 1 : 0);
     Child ch[2];
     ch[0].kind = ch[1].kind = KIND_NONE;
     ch[0].tiles = ch[1].tiles = 0;
     ch[0].cbase = ch[1].cbase = 0;
-    if (q < nt) {
-      const Seg sg = a.list[q];
-      const uint32_t len = (uint32_t)sg.len;  // 2 .. TINY_MAX
-      const int bit = (int)(sg.meta & BIT_MASK);
-      const int buf = (sg.meta & META_BUF) ? 1 : 0;
-      const bool iota = (sg.meta & META_IOTA) != 0;
-      KT k[TINY_MAX];
-      uint32_t x[TINY_MAX];
+    // batches: successive runs of the window's entries whose keys fit BATCH
+    for (uint32_t b0 = 0; b0 < nwin;) {
+      const uint32_t base = b0 ? (uint32_t)__shfl((int)cum, (int)b0 - 1) : 0u;
+      const uint64_t fits = __ballot(lane >= b0 && lane < nwin && cum - base <= BATCH);
+      const uint32_t m = (uint32_t)__popcll(fits);  // >= 1: every entry fits alone
+      const bool mine = lane >= b0 && lane < b0 + m;
+      const uint32_t s0 = s0w - base;                // batch positions of the lane's entry
+      const uint32_t s1 = cum - base;
+      // per item, a bit at every segment start inside it
+      uint64_t starts[TINY_IPT];
 #pragma unroll
-      for (uint32_t j = 0; j < TINY_MAX; ++j) {
-        k[j] = 0;
-        x[j] = 0;
-        if (j < len) {
-          k[j] = a.keys[buf][sg.start + j];
-          if (IDX) x[j] = iota ? j : a.idx[buf][sg.start + j];
+      for (int i = 0; i < TINY_IPT; ++i) {
+        const uint32_t d = s0 - (uint32_t)i * 64u;
+        starts[i] = wave_or_dpp(mine && d < 64u ? 1ull << d : 0ull);
+      }
+      const uint32_t total = (uint32_t)__shfl((int)cum, (int)(b0 + m) - 1) - base;
+      // every key: its segment (a lane of the batch), its key, its side
+      KT k[TINY_IPT];
+      uint32_t x[TINY_IPT], segi[TINY_IPT];
+      uint64_t fb[TINY_IPT];
+      uint32_t before = 0;  // segment starts in earlier items
+#pragma unroll
+      for (int i = 0; i < TINY_IPT; ++i) {
+        const uint32_t q = (uint32_t)i * 64u + lane;
+        const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1);
+        const uint32_t si = b0 + before + (uint32_t)__popcll(starts[i] & upto) - 1u;
+        before += (uint32_t)__popcll(starts[i]);
+        const bool valid = q < total;
+        const int sl = valid ? (int)si : 0;
+        segi[i] = (uint32_t)sl;
+        const uint64_t st = (uint64_t)(uint32_t)__shfl((int)(uint32_t)sg.start, sl) |
+                            ((uint64_t)(uint32_t)__shfl((int)(uint32_t)(sg.start >> 32), sl) << 32);
+        const uint32_t mt = (uint32_t)__shfl((int)sg.meta, sl);
+        const uint32_t j = q - (uint32_t)__shfl((int)s0, sl);
+        const uint32_t ff = (uint32_t)__shfl((int)f, sl);
+        const int kb = (mt & META_BUF) ? 1 : 0;
+        const bool io = (mt & META_IOTA) != 0;
+        k[i] = valid ? a.keys[kb][st + j] : (KT)0;
+        x[i] = 0;
+        if (IDX) x[i] = !valid ? 0u : (io ? j : a.idx[kb][st + j]);
+        const int bb = (int)(mt & BIT_MASK);
+        fb[i] = __ballot(valid && ((((uint64_t)k[i] >> bb) & 1u) ^ ff) == 0u);
+      }
+      // per entry of the batch: its front keys before it and in it
+      const uint32_t Ps = batch_fronts_below(fb, mine ? s0 : 0u);
+      const uint32_t Fs = batch_fronts_below(fb, mine ? s1 : 0u) - Ps;
+#pragma unroll
+      for (int i = 0; i < TINY_IPT; ++i) {
+        const uint32_t q = (uint32_t)i * 64u + lane;
+        // the lane exchanges first, with every lane active; then the keys
+        const int sl = (int)segi[i];
+        const uint64_t st = (uint64_t)(uint32_t)__shfl((int)(uint32_t)sg.start, sl) |
+                            ((uint64_t)(uint32_t)__shfl((int)(uint32_t)(sg.start >> 32), sl) << 32);
+        const uint32_t mt = (uint32_t)__shfl((int)sg.meta, sl);
+        const uint32_t sq = (uint32_t)__shfl((int)s0, sl);
+        const uint32_t F = (uint32_t)__shfl((int)Fs, sl);
+        const uint32_t P0 = (uint32_t)__shfl((int)Ps, sl);
+        const uint32_t ln = (uint32_t)__shfl((int)len, sl);
+        if (q >= total) continue;
+        const int kb = (mt & META_BUF) ? 1 : 0;
+        const bool io = (mt & META_IOTA) != 0;
+        const int bb = (int)(mt & BIT_MASK);
+        const uint32_t j = q - sq;
+        if (a.snapshot) {
+          // as it stands: to the caller's buffers
+          if (kb) a.keys_final[st + j] = k[i];
+          if (IDX && (kb || io || a.idx64)) {
+            if (a.idx64) static_cast<int64_t *>(a.idx_final)[st + j] = (int64_t)x[i];
+            else static_cast<uint32_t *>(a.idx_final)[st + j] = x[i];
+          }
+          continue;
+        }
+        const bool front = (fb[i] >> lane) & 1u;
+        const uint32_t r = batch_fronts_below(fb, q) - P0;  // front keys before it in its segment
+        const bool mv = F != 0 && F != ln;
+        const uint32_t dst = mv ? (front ? r : F + (j - r)) : j;
+        const int cb = mv ? 1 - kb : kb;
+        if (mv) {
+          a.keys[cb][st + dst] = k[i];
+          if (IDX) a.idx[cb][st + dst] = x[i];
+        }
+        // a key whose child is done goes to the caller's buffers now
+        const uint32_t clen = front ? F : ln - F;
+        if (clen < 2 || bb == 0) {
+          const bool cio = !mv && io;
+          if (cb) a.keys_final[st + dst] = k[i];
+          if (IDX && (cb || cio || a.idx64)) {
+            // an identity index is the key's place in its user segment,
+            // which a segment that has never moved starts
+            const uint32_t v = cio ? dst : x[i];
+            if (a.idx64) static_cast<int64_t *>(a.idx_final)[st + dst] = (int64_t)v;
+            else static_cast<uint32_t *>(a.idx_final)[st + dst] = v;
+          }
         }
       }
-      if (a.snapshot) {
-        tiny_write_out<KT, IDX>(a, k, x, len, 0, 0u, -1, sg.start, 0u, buf, iota);
-      } else {
-        const uint32_t f = (uint32_t)flip_of(bit, a.w, a.mode, a.desc, (sg.meta & META_SIGN) ? 1 : 0);
-        uint32_t F = 0;
-#pragma unroll
-        for (uint32_t j = 0; j < TINY_MAX; ++j)
-          if (j < len) F += ((((uint64_t)k[j] >> bit) & 1u) ^ f) == 0u ? 1u : 0u;
-        const bool moved = F != 0 && F != len;
-        const int cb = moved ? 1 - buf : buf;
-        if (moved) {
-          uint32_t rf = 0, rb = F;
-#pragma unroll
-          for (uint32_t j = 0; j < TINY_MAX; ++j) {
-            if (j >= len) break;
-            const bool front = ((((uint64_t)k[j] >> bit) & 1u) ^ f) == 0u;
-            const uint32_t dst = front ? rf++ : rb++;
-            a.keys[cb][sg.start + dst] = k[j];
-            if (IDX) a.idx[cb][sg.start + dst] = x[j];
-          }
-        }
-        const bool ciota = !moved && iota;
+      // the batch's entries' children (lane l: entry l of the window)
+      if (mine && !a.snapshot) {
+        const bool moved_s = Fs != 0 && Fs != len;
+        const bool cio = !moved_s && ((sg.meta & META_IOTA) != 0);
+        const uint32_t cbuf = moved_s ? ((sg.meta & META_BUF) ^ META_BUF) : (sg.meta & META_BUF);
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
-          const uint32_t clen = c ? len - F : F;
-          const uint64_t cstart = sg.start + (c ? F : 0u);
-          ch[c].start = cstart;
+          const uint32_t clen = c ? len - Fs : Fs;
+          ch[c].start = sg.start + (c ? Fs : 0u);
           ch[c].len = clen;
-          if (clen == 0) continue;
-          if (clen < 2 || bit == 0) {
-            // done: to the caller's buffers (only this side's keys)
-            tiny_write_out<KT, IDX>(a, k, x, len, bit, f, c, cstart, c ? F : 0u, cb, ciota);
-            continue;
-          }
-          // the child's sign: the side's after the sign split, else the parent's
+          if (clen < 2 || bit == 0) continue;  // empty, or done above
           uint32_t sign = (sg.meta & META_SIGN) ? META_SIGN : 0u;
           if (bit == a.w - 1) sign = ((uint32_t)c ^ f) ? META_SIGN : 0u;
-          ch[c].meta = sign | (cb ? META_BUF : 0u) | (ciota ? META_IOTA : 0u) | (uint32_t)(bit - 1);
+          ch[c].meta = sign | cbuf | (cio ? META_IOTA : 0u) | (uint32_t)(bit - 1);
           ch[c].kind = KIND_TINY;
         }
       }
+      b0 += m;
     }
-    emit_children(a.l, ch);
+    chw[v][0] = ch[0];
+    chw[v][1] = ch[1];
+   }
+   emit_tiny_block(a.l, chw, s_n, s_k, s_base);
   }
 }
 
