@@ -397,7 +397,10 @@ int launch_all(KT *keys, uint64_t n, const int64_t *offsets, uint64_t B, int mod
     ta.snapshot = snap;
     return ta;
   };
-  const uint32_t tsgrid = clamp_grid((L.smax + 255) / 256, (uint64_t)cus * 8);
+  // the tiny pass: one resident round of workgroups (a second, partial
+  // round would leave most of the chip idle at its end)
+  static const int occ_tsp = occupancy(tiny_kernel<KT, IDX>, 256);
+  const uint32_t tsgrid = clamp_grid((L.smax + 255) / 256, (uint64_t)cus * occ_tsp);
 
   // Levels below `first_tail` are launched one kernel per phase; the rest
   // run in one tail launch, which ends at the first empty level (its live

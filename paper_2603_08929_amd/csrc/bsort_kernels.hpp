@@ -1444,32 +1444,75 @@ __device__ __forceinline__ uint32_t batch_fronts_below(const uint64_t (&b)[TINY_
   return c;
 }
 
-// The tiny-list children of a workgroup's TINY_WIN windows (each lane's
-// ch[v][c]), listed with one list atomic for the whole workgroup: at the
+// A split tiny segment's part c (0: front, F keys; 1: back, len - F keys)
+// as a segment of the next level, if it has two keys or more and bits remain
+// (a part of one key, or split on bit 0, is in its final place already).
+__device__ __forceinline__ bool tiny_child(uint64_t start, uint32_t meta, uint32_t len, uint32_t F, int c,
+                                           int w, int mode, int desc, uint64_t &cst, uint32_t &clen,
+                                           uint32_t &cmeta) {
+  const int bit = (int)(meta & BIT_MASK);
+  clen = c ? len - F : F;
+  cst = start + (c ? F : 0u);
+  if (clen < 2 || bit == 0) return false;
+  const bool moved = F != 0 && F != len;
+  const bool cio = !moved && (meta & META_IOTA) != 0;
+  const uint32_t cbuf = moved ? ((meta & META_BUF) ^ META_BUF) : (meta & META_BUF);
+  uint32_t sign = meta & META_SIGN;
+  if (bit == w - 1)
+    sign = ((uint32_t)c ^ (uint32_t)flip_of(bit, w, mode, desc, sign ? 1 : 0)) ? META_SIGN : 0u;
+  cmeta = sign | cbuf | (cio ? META_IOTA : 0u) | (uint32_t)(bit - 1);
+  return true;
+}
+
+// The next level's tiny segments made by a workgroup's TINY_WIN windows
+// (per wave, window and lane, in LDS: the entry's start, and its meta,
+// length and front count packed in a word, length 0 for none), listed with one list atomic for the whole workgroup: at the
 // deepest levels nearly every entry has children, and one atomic per wave
-// and window would be the level's serial bottleneck.
+// and window would be the level's serial bottleneck.  The key counts add up
+// in thread 0 (klive_wg, kiota_wg) until the workgroup ends.
 constexpr int TINY_WIN = 4;
 
-__device__ __forceinline__ void emit_tiny_block(const ListArgs &a, const Child (&ch)[TINY_WIN][2],
-                                                uint32_t (&s_n)[4], uint64_t (&s_k)[2][4],
-                                                uint32_t &s_base) {
+struct TinyRecs {
+  uint64_t st[4][TINY_WIN][64];
+  uint32_t pk[4][TINY_WIN][64];  // meta bits 0-10 | len << 11 | F << 20
+};
+static_assert(TINY_MAX < 512, "a tiny length and front count take 9 bits each");
+__device__ __forceinline__ uint32_t tiny_pack(uint32_t meta, uint32_t len, uint32_t F) {
+  return (meta & 0x7FFu) | len << 11 | F << 20;
+}
+
+__device__ __forceinline__ void emit_tiny_block(const ListArgs &a, int w, int mode, int desc,
+                                                const TinyRecs &r, uint32_t (&s_n)[4],
+                                                uint64_t (&s_k)[2][4], uint32_t &s_base,
+                                                uint64_t &klive_wg, uint64_t &kiota_wg) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // children in the order of their parents (window, lane, part), so that a
+  // window of the next level covers neighbouring keys
+  uint32_t at[TINY_WIN];  // the lane's first position in window v's run
   uint32_t n = 0;
   uint64_t klive = 0, kiota = 0;
+  for (int v = 0; v < TINY_WIN; ++v) {
+    uint32_t nv = 0;
 #pragma unroll
-  for (int v = 0; v < TINY_WIN; ++v)
-#pragma unroll
-    for (int c = 0; c < 2; ++c)
-      if (ch[v][c].kind == KIND_TINY) {
-        ++n;
-        klive += ch[v][c].len;
-        if (ch[v][c].meta & META_IOTA) kiota += ch[v][c].len;
+    for (int c = 0; c < 2; ++c) {
+      uint64_t cst;
+      uint32_t clen, cmeta;
+      const uint32_t pk = r.pk[wave][v][lane];
+      if (tiny_child(r.st[wave][v][lane], pk & 0x7FFu, (pk >> 11) & 0x1FFu, pk >> 20, c, w, mode, desc,
+                     cst, clen, cmeta)) {
+        ++nv;
+        klive += clen;
+        if (cmeta & META_IOTA) kiota += clen;
       }
-  const uint32_t inc = wave_incl_scan_dpp(n);
+    }
+    const uint32_t inc = wave_incl_scan_dpp(nv);
+    at[v] = n + inc - nv;
+    n += (uint32_t)__shfl((int)inc, 63);
+  }
   klive = wave_sum_u64(klive);
   kiota = wave_sum_u64(kiota);
-  if (lane == 63) s_n[wave] = inc;
   if (lane == 0) {
+    s_n[wave] = n;
     s_k[0][wave] = klive;
     s_k[1][wave] = kiota;
   }
@@ -1477,28 +1520,32 @@ __device__ __forceinline__ void emit_tiny_block(const ListArgs &a, const Child (
   if (threadIdx.x == 0) {
     const uint32_t tot = s_n[0] + s_n[1] + s_n[2] + s_n[3];
     s_base = tot ? atomic_add_u32(&a.hdr->n_tiny[a.next_level], tot) : 0u;
-    const uint64_t kl = s_k[0][0] + s_k[0][1] + s_k[0][2] + s_k[0][3];
-    const uint64_t ki = s_k[1][0] + s_k[1][1] + s_k[1][2] + s_k[1][3];
-    if (kl) atomic_add_u64(&a.hdr->live_keys[a.next_level], kl);
-    if (ki) atomic_add_u64(&a.hdr->iota_keys[a.next_level], ki);
+    klive_wg += s_k[0][0] + s_k[0][1] + s_k[0][2] + s_k[0][3];
+    kiota_wg += s_k[1][0] + s_k[1][1] + s_k[1][2] + s_k[1][3];
   }
   __syncthreads();
-  uint32_t pos = s_base + inc - n;
-  for (int w2 = 0; w2 < wave; ++w2) pos += s_n[w2];
+  uint32_t wbase = s_base;
+  for (int w2 = 0; w2 < wave; ++w2) wbase += s_n[w2];
+  for (int v = 0; v < TINY_WIN; ++v) {
+    uint32_t pos = wbase + at[v];
 #pragma unroll
-  for (int v = 0; v < TINY_WIN; ++v)
-#pragma unroll
-    for (int c = 0; c < 2; ++c)
-      if (ch[v][c].kind == KIND_TINY) {
+    for (int c = 0; c < 2; ++c) {
+      uint64_t cst;
+      uint32_t clen, cmeta;
+      const uint32_t pk = r.pk[wave][v][lane];
+      if (tiny_child(r.st[wave][v][lane], pk & 0x7FFu, (pk >> 11) & 0x1FFu, pk >> 20, c, w, mode, desc,
+                     cst, clen, cmeta)) {
         Seg sg;
-        sg.start = ch[v][c].start;
-        sg.len = ch[v][c].len;
-        sg.meta = ch[v][c].meta;
+        sg.start = cst;
+        sg.len = clen;
+        sg.meta = cmeta;
         sg.tile0 = 0;
         sg.cbase = 0;
         sg.slot = 0;
         a.tiny_next[pos++] = sg;
       }
+    }
+  }
   __syncthreads();  // the counts in LDS are reused by the next call
 }
 
@@ -1508,6 +1555,7 @@ __global__ __launch_bounds__(256) void tiny_kernel(TinyArgs<KT> a) {
   static_assert(TINY_MAX <= BATCH, "a tiny segment fits one batch");
   __shared__ uint32_t s_n[4], s_base;
   __shared__ uint64_t s_k[2][4];
+  __shared__ TinyRecs s_rec;
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t nt = ld_relaxed_u32(&a.l.hdr->n_tiny[a.level]);
   // waves take equal runs of list entries, 64 at a time (a window), and
@@ -1518,24 +1566,40 @@ __global__ __launch_bounds__(256) void tiny_kernel(TinyArgs<KT> a) {
   const uint32_t per = (nt + G - 1) / G;
   const uint32_t e_end = (g + 1) * per < nt ? (g + 1) * per : nt;
   const uint32_t steps = (per + 64u * TINY_WIN - 1) / (64u * TINY_WIN);
+  uint64_t klive_wg = 0, kiota_wg = 0;
+  // window t of the wave: list entries [g * per + 64 t, ...) up to e_end;
+  // the next window's entries load while the wave works on the current one
+  auto window_of = [&](uint32_t t) {
+    const uint32_t e = g * per + t * 64u;
+    return e < e_end ? (e_end - e < 64u ? e_end - e : 64u) : 0u;
+  };
+  auto load_entry = [&](uint32_t t, uint64_t &st, uint32_t &ln, uint32_t &mt) {
+    st = 0;
+    ln = 0;
+    mt = 0;
+    if (lane < window_of(t)) {
+      const Seg &q = a.list[g * per + t * 64u + lane];
+      st = q.start;
+      ln = (uint32_t)q.len;
+      mt = q.meta;
+    }
+  };
+  uint64_t nst;
+  uint32_t nln, nmt;
+  load_entry(0, nst, nln, nmt);
   for (uint32_t step = 0; step < steps; ++step) {
-   Child chw[TINY_WIN][2];
-#pragma unroll
+#pragma unroll 1
    for (int v = 0; v < TINY_WIN; ++v) {
-    const uint32_t e = g * per + (step * TINY_WIN + (uint32_t)v) * 64u;
-    const uint32_t nwin = e < e_end ? (e_end - e < 64u ? e_end - e : 64u) : 0u;
-    const bool have = lane < nwin;
+    const uint32_t t = step * TINY_WIN + (uint32_t)v;
+    const uint32_t nwin = window_of(t);
     Seg sg = {};
-    if (have) sg = a.list[e + lane];
-    const uint32_t len = have ? (uint32_t)sg.len : 0u;
+    sg.start = nst;
+    sg.meta = nmt;
+    const uint32_t len = nln;  // 0 past the window
+    load_entry(t + 1, nst, nln, nmt);
     const uint32_t cum = wave_incl_scan_dpp(len);  // over the window
     const uint32_t s0w = cum - len;                  // the entry's first window position
-    const int bit = (int)(sg.meta & BIT_MASK);
-    const uint32_t f = (uint32_t)flip_of(bit, a.w, a.mode, a.desc, (sg.meta & META_SIGN) ? 1 : 0);
-    Child ch[2];
-    ch[0].kind = ch[1].kind = KIND_NONE;
-    ch[0].tiles = ch[1].tiles = 0;
-    ch[0].cbase = ch[1].cbase = 0;
+    uint32_t myF = 0;  // the entry's front count, from its batch
     // batches: successive runs of the window's entries whose keys fit BATCH
     for (uint32_t b0 = 0; b0 < nwin;) {
       const uint32_t base = b0 ? (uint32_t)__shfl((int)cum, (int)b0 - 1) : 0u;
@@ -1552,10 +1616,11 @@ __global__ __launch_bounds__(256) void tiny_kernel(TinyArgs<KT> a) {
         starts[i] = wave_or_dpp(mine && d < 64u ? 1ull << d : 0ull);
       }
       const uint32_t total = (uint32_t)__shfl((int)cum, (int)(b0 + m) - 1) - base;
-      // every key: its segment (a lane of the batch), its key, its side
+      // every key: its segment (a lane of the batch), its place in it, its
+      // key and index -- every load issued before any is used
       KT k[TINY_IPT];
-      uint32_t x[TINY_IPT], segi[TINY_IPT];
-      uint64_t fb[TINY_IPT];
+      uint32_t x[TINY_IPT], segi[TINY_IPT], jj[TINY_IPT], mts[TINY_IPT];
+      uint64_t sts[TINY_IPT], fb[TINY_IPT];
       uint32_t before = 0;  // segment starts in earlier items
 #pragma unroll
       for (int i = 0; i < TINY_IPT; ++i) {
@@ -1566,18 +1631,34 @@ __global__ __launch_bounds__(256) void tiny_kernel(TinyArgs<KT> a) {
         const bool valid = q < total;
         const int sl = valid ? (int)si : 0;
         segi[i] = (uint32_t)sl;
-        const uint64_t st = (uint64_t)(uint32_t)__shfl((int)(uint32_t)sg.start, sl) |
-                            ((uint64_t)(uint32_t)__shfl((int)(uint32_t)(sg.start >> 32), sl) << 32);
-        const uint32_t mt = (uint32_t)__shfl((int)sg.meta, sl);
-        const uint32_t j = q - (uint32_t)__shfl((int)s0, sl);
-        const uint32_t ff = (uint32_t)__shfl((int)f, sl);
-        const int kb = (mt & META_BUF) ? 1 : 0;
-        const bool io = (mt & META_IOTA) != 0;
-        k[i] = valid ? a.keys[kb][st + j] : (KT)0;
+        sts[i] = (uint64_t)(uint32_t)__shfl((int)(uint32_t)sg.start, sl) |
+                 ((uint64_t)(uint32_t)__shfl((int)(uint32_t)(sg.start >> 32), sl) << 32);
+        mts[i] = (uint32_t)__shfl((int)sg.meta, sl);
+        jj[i] = q - (uint32_t)__shfl((int)s0, sl);
+        const int kb = (mts[i] & META_BUF) ? 1 : 0;
+        const bool io = (mts[i] & META_IOTA) != 0;
+        // the buffer by a select: an index into the argument's array
+        // differs per lane and would load the pointer from memory first
+        const KT *kp = kb ? a.keys[1] : a.keys[0];
+        k[i] = valid ? kp[sts[i] + jj[i]] : (KT)0;
         x[i] = 0;
-        if (IDX) x[i] = !valid ? 0u : (io ? j : a.idx[kb][st + j]);
-        const int bb = (int)(mt & BIT_MASK);
-        fb[i] = __ballot(valid && ((((uint64_t)k[i] >> bb) & 1u) ^ ff) == 0u);
+        if (IDX) {
+          const uint32_t *xp = kb ? a.idx[1] : a.idx[0];
+          x[i] = !valid ? 0u : (io ? jj[i] : xp[sts[i] + jj[i]]);
+        }
+      }
+      // the keys' sides without a branch, so that every later use finds
+      // the loads complete on every path (a wait inside a branch would be
+      // repeated before each store, and a wait there also waits for the
+      // stores already issued)
+#pragma unroll
+      for (int i = 0; i < TINY_IPT; ++i) {
+        const uint32_t valid = (uint32_t)i * 64u + lane < total ? 1u : 0u;
+        const int bb = (int)(mts[i] & BIT_MASK);
+        const uint32_t ff = (uint32_t)flip_of(bb, a.w, a.mode, a.desc, (mts[i] & META_SIGN) ? 1 : 0);
+        const uint32_t side = (uint32_t)(((uint64_t)k[i] >> bb) & 1u) ^ ff;
+        fb[i] = __ballot((valid & (side ^ 1u)) != 0u);
+        if (IDX) asm volatile("" ::"v"(x[i]));
       }
       // per entry of the batch: its front keys before it and in it
       const uint32_t Ps = batch_fronts_below(fb, mine ? s0 : 0u);
@@ -1587,18 +1668,16 @@ __global__ __launch_bounds__(256) void tiny_kernel(TinyArgs<KT> a) {
         const uint32_t q = (uint32_t)i * 64u + lane;
         // the lane exchanges first, with every lane active; then the keys
         const int sl = (int)segi[i];
-        const uint64_t st = (uint64_t)(uint32_t)__shfl((int)(uint32_t)sg.start, sl) |
-                            ((uint64_t)(uint32_t)__shfl((int)(uint32_t)(sg.start >> 32), sl) << 32);
-        const uint32_t mt = (uint32_t)__shfl((int)sg.meta, sl);
-        const uint32_t sq = (uint32_t)__shfl((int)s0, sl);
         const uint32_t F = (uint32_t)__shfl((int)Fs, sl);
         const uint32_t P0 = (uint32_t)__shfl((int)Ps, sl);
         const uint32_t ln = (uint32_t)__shfl((int)len, sl);
+        const uint64_t st = sts[i];
+        const uint32_t mt = mts[i];
         if (q >= total) continue;
         const int kb = (mt & META_BUF) ? 1 : 0;
         const bool io = (mt & META_IOTA) != 0;
         const int bb = (int)(mt & BIT_MASK);
-        const uint32_t j = q - sq;
+        const uint32_t j = jj[i];
         if (a.snapshot) {
           // as it stands: to the caller's buffers
           if (kb) a.keys_final[st + j] = k[i];
@@ -1614,8 +1693,8 @@ __global__ __launch_bounds__(256) void tiny_kernel(TinyArgs<KT> a) {
         const uint32_t dst = mv ? (front ? r : F + (j - r)) : j;
         const int cb = mv ? 1 - kb : kb;
         if (mv) {
-          a.keys[cb][st + dst] = k[i];
-          if (IDX) a.idx[cb][st + dst] = x[i];
+          (cb ? a.keys[1] : a.keys[0])[st + dst] = k[i];
+          if (IDX) (cb ? a.idx[1] : a.idx[0])[st + dst] = x[i];
         }
         // a key whose child is done goes to the caller's buffers now
         const uint32_t clen = front ? F : ln - F;
@@ -1631,29 +1710,19 @@ __global__ __launch_bounds__(256) void tiny_kernel(TinyArgs<KT> a) {
           }
         }
       }
-      // the batch's entries' children (lane l: entry l of the window)
-      if (mine && !a.snapshot) {
-        const bool moved_s = Fs != 0 && Fs != len;
-        const bool cio = !moved_s && ((sg.meta & META_IOTA) != 0);
-        const uint32_t cbuf = moved_s ? ((sg.meta & META_BUF) ^ META_BUF) : (sg.meta & META_BUF);
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-          const uint32_t clen = c ? len - Fs : Fs;
-          ch[c].start = sg.start + (c ? Fs : 0u);
-          ch[c].len = clen;
-          if (clen < 2 || bit == 0) continue;  // empty, or done above
-          uint32_t sign = (sg.meta & META_SIGN) ? META_SIGN : 0u;
-          if (bit == a.w - 1) sign = ((uint32_t)c ^ f) ? META_SIGN : 0u;
-          ch[c].meta = sign | cbuf | (cio ? META_IOTA : 0u) | (uint32_t)(bit - 1);
-          ch[c].kind = KIND_TINY;
-        }
-      }
+      if (mine) myF = Fs;
       b0 += m;
     }
-    chw[v][0] = ch[0];
-    chw[v][1] = ch[1];
+    // lane l: entry l of the window, whose parts the workgroup lists below
+    const uint32_t wv = threadIdx.x >> 6;
+    s_rec.st[wv][v][lane] = sg.start;
+    s_rec.pk[wv][v][lane] = a.snapshot ? 0u : tiny_pack(sg.meta, len, myF);
    }
-   emit_tiny_block(a.l, chw, s_n, s_k, s_base);
+   emit_tiny_block(a.l, a.w, a.mode, a.desc, s_rec, s_n, s_k, s_base, klive_wg, kiota_wg);
+  }
+  if (threadIdx.x == 0) {
+    if (klive_wg) atomic_add_u64(&a.l.hdr->live_keys[a.l.next_level], klive_wg);
+    if (kiota_wg) atomic_add_u64(&a.l.hdr->iota_keys[a.l.next_level], kiota_wg);
   }
 }
 
