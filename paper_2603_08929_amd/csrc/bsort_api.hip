@@ -147,8 +147,9 @@ constexpr uint32_t ALL_FLAGS =
 size_t up256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Scratch layout.  The header sits at offset 0 (bsort_device_status reads
-// it there).  Bounds: a live segment holds more than T keys (at least 2
-// with BSORT_NO_FINISH); a level's tiles are at most n/TILE + segments;
+// it there).  Bounds: a live segment holds more than T keys (more than
+// TINY_MAX with BSORT_NO_FINISH, whose tiny lists hold the parts of 2 to
+// TINY_MAX keys); a level's tiles are at most n/TILE + segments;
 // every parent yields at most two finish entries per level; copy entries
 // hold more than T keys each.  The level kernel reads the per-tile prefix
 // words and the chunk carries through one buffer descriptor with 32-bit
@@ -156,7 +157,7 @@ size_t up256(size_t x) { return (x + 255) & ~(size_t)255; }
 struct Layout {
   size_t hdr, cnts, segs[2], acc[2], split[2], tmap, pc, agg, carry, fin, fins, fint, finm, cpy,
       tiny[2], meta, keys1, idx0, idx1, keys0, total;
-  uint64_t smax, tmax, fmax, cmax, cn, nchunks;
+  uint64_t smax, tnmax, tmax, fmax, cmax, cn, nchunks;
 };
 
 bool make_layout(int key_bytes, uint64_t n, uint64_t B, bool with_idx, uint32_t flags,
@@ -164,7 +165,10 @@ bool make_layout(int key_bytes, uint64_t n, uint64_t B, bool with_idx, uint32_t 
   if (key_bytes != 1 && key_bytes != 2 && key_bytes != 4 && key_bytes != 8) return false;
   const uint64_t w = 8ull * key_bytes;
   const bool no_finish = (flags & BSORT_NO_FINISH) != 0;
-  L->smax = (no_finish ? n / 2 : n / (tfin + 1ull)) + 1;
+  // without the LDS finish, parts of at most TINY_MAX keys go to the tiny
+  // lists (each entry at least 2 keys), so a live segment holds more
+  L->smax = (no_finish ? n / (TINY_MAX + 1ull) : n / (tfin + 1ull)) + 1;
+  L->tnmax = no_finish ? n / 2 + 1 : 0;
   L->tmax = n / tile + L->smax + 1;
   const uint64_t fb = B + 2 * w * L->smax + 1;
   L->fmax = (fb < n + 1 ? fb : n + 1);
@@ -192,7 +196,7 @@ bool make_layout(int key_bytes, uint64_t n, uint64_t B, bool with_idx, uint32_t 
   // without the LDS finish: the tiny-segment lists of two level parities
   L->tiny[0] = L->tiny[1] = 0;
   if (no_finish)
-    for (int i = 0; i < 2; ++i) { L->tiny[i] = off; off = up256(off + L->smax * sizeof(Seg)); }
+    for (int i = 0; i < 2; ++i) { L->tiny[i] = off; off = up256(off + L->tnmax * sizeof(Seg)); }
   L->keys1 = off; off = up256(off + n * (size_t)key_bytes);
   L->idx0 = L->idx1 = 0;
   if (with_idx) {
@@ -366,6 +370,7 @@ int launch_all(KT *keys, uint64_t n, const int64_t *offsets, uint64_t B, int mod
     pa.zero_a = cnt[lvl & 1];  // read by this level's prep, filled by the next level
     pa.zero_b = nullptr;
     pa.zero_n = cn;
+    pa.zero_per_tile = 2;
     pa.level = lvl;
     pa.w = w;
     pa.with_idx = IDX ? 1 : 0;
@@ -400,7 +405,7 @@ int launch_all(KT *keys, uint64_t n, const int64_t *offsets, uint64_t B, int mod
   // the tiny pass: one resident round of workgroups (a second, partial
   // round would leave most of the chip idle at its end)
   static const int occ_tsp = occupancy(tiny_kernel<KT, IDX>, 256);
-  const uint32_t tsgrid = clamp_grid((L.smax + 255) / 256, (uint64_t)cus * occ_tsp);
+  const uint32_t tsgrid = clamp_grid((L.tnmax + 255) / 256, (uint64_t)cus * occ_tsp);
 
   // Levels below `first_tail` are launched one kernel per phase; the rest
   // run in one tail launch, which ends at the first empty level (its live
@@ -1038,6 +1043,7 @@ int launch_inplace(KT *keys, uint64_t n, const int64_t *offsets, uint64_t B, int
     pa.zero_a = tcnt[lvl & 1];  // counted again two levels on
     pa.zero_b = scnt[lvl & 1];
     pa.zero_n = cn;
+    pa.zero_per_tile = 0;
     pa.level = lvl;
     pa.w = w;
     pa.with_idx = 0;

@@ -549,6 +549,10 @@ struct PlanArgs {
   uint32_t *zero_a;  // count arrays the next level accumulates into (zero_b nullable)
   uint32_t *zero_b;
   uint64_t zero_n;
+  // 0: clear zero_n entries; k > 0: only the first k * (T + S) + 1, where T
+  // and S are this level's tiles and segments (the next level's tiles are
+  // at most T + S, and its counts land below 2 * its tiles)
+  uint32_t zero_per_tile;
   int level;
   int w;
   int with_idx;
@@ -559,9 +563,15 @@ struct PlanArgs {
 };
 
 __device__ __forceinline__ void plan_body(const PlanArgs &a) {
-  const uint32_t S = (uint32_t)(ld_relaxed(&a.l.hdr->packed[a.level]) >> 32);
+  const uint64_t packed = ld_relaxed(&a.l.hdr->packed[a.level]);
+  const uint32_t S = (uint32_t)(packed >> 32);
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.zero_n; i += stride) {
+  uint64_t zn = a.zero_n;
+  if (a.zero_per_tile) {
+    const uint64_t need = (uint64_t)a.zero_per_tile * ((uint64_t)(uint32_t)packed + S) + 1;
+    if (need < zn) zn = need;
+  }
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < zn; i += stride) {
     a.zero_a[i] = 0;
     if (a.zero_b) a.zero_b[i] = 0;
   }
@@ -1471,6 +1481,9 @@ __device__ __forceinline__ bool tiny_child(uint64_t start, uint32_t meta, uint32
 // and window would be the level's serial bottleneck.  The key counts add up
 // in thread 0 (klive_wg, kiota_wg) until the workgroup ends.
 constexpr int TINY_WIN = 4;
+// Entries of at most this many keys are split by their own lane, without
+// the batch's lane exchanges.
+constexpr uint32_t TINY_LANE = 8;
 
 struct TinyRecs {
   uint64_t st[4][TINY_WIN][64];
@@ -1591,15 +1604,93 @@ __global__ __launch_bounds__(256) void tiny_kernel(TinyArgs<KT> a) {
 #pragma unroll 1
    for (int v = 0; v < TINY_WIN; ++v) {
     const uint32_t t = step * TINY_WIN + (uint32_t)v;
-    const uint32_t nwin = window_of(t);
-    Seg sg = {};
-    sg.start = nst;
-    sg.meta = nmt;
-    const uint32_t len = nln;  // 0 past the window
+    // the lane's own entry (length 0 past the window)
+    const uint64_t est = nst;
+    const uint32_t emt = nmt, elen = nln;
     load_entry(t + 1, nst, nln, nmt);
+    uint32_t eF = 0;  // its front count
+    // an entry of at most TINY_LANE keys: its lane splits it alone
+    const bool sm = elen <= TINY_LANE;
+    if (__ballot(sm && elen > 0)) {
+      const int bb = (int)(emt & BIT_MASK);
+      const uint32_t ff = (uint32_t)flip_of(bb, a.w, a.mode, a.desc, (emt & META_SIGN) ? 1 : 0);
+      const int kb = (emt & META_BUF) ? 1 : 0;
+      const bool io = (emt & META_IOTA) != 0;
+      const KT *kp = kb ? a.keys[1] : a.keys[0];
+      const uint32_t *xp = kb ? a.idx[1] : a.idx[0];
+      KT kk[TINY_LANE];
+      uint32_t xx[TINY_LANE];
+#pragma unroll
+      for (uint32_t j = 0; j < TINY_LANE; ++j) {
+        kk[j] = 0;
+        xx[j] = 0;
+        if (sm && j < elen) {
+          kk[j] = kp[est + j];
+          if (IDX) xx[j] = io ? j : xp[est + j];
+        }
+      }
+      uint32_t fm = 0;  // bit j: key j goes to the front part
+#pragma unroll
+      for (uint32_t j = 0; j < TINY_LANE; ++j) {
+        const uint32_t side = (uint32_t)(((uint64_t)kk[j] >> bb) & 1u) ^ ff;
+        fm |= ((j < elen ? 1u : 0u) & (side ^ 1u)) << j;
+        if (IDX) asm volatile("" ::"v"(xx[j]));
+      }
+      const uint32_t F = (uint32_t)__popc(fm);
+      if (sm) eF = F;
+      const bool mv = F != 0 && F != elen;
+      const int cb = mv ? 1 - kb : kb;
+#pragma unroll
+      for (uint32_t j = 0; j < TINY_LANE; ++j) {
+        if (!(sm && j < elen)) continue;
+        if (a.snapshot) {
+          // as it stands: to the caller's buffers
+          if (kb) a.keys_final[est + j] = kk[j];
+          if (IDX && (kb || io || a.idx64)) {
+            if (a.idx64) static_cast<int64_t *>(a.idx_final)[est + j] = (int64_t)xx[j];
+            else static_cast<uint32_t *>(a.idx_final)[est + j] = xx[j];
+          }
+          continue;
+        }
+        const bool front = (fm >> j) & 1u;
+        const uint32_t r = (uint32_t)__popc(fm & ((1u << j) - 1u));
+        const uint32_t dst = mv ? (front ? r : F + (j - r)) : j;
+        if (mv) {
+          (cb ? a.keys[1] : a.keys[0])[est + dst] = kk[j];
+          if (IDX) (cb ? a.idx[1] : a.idx[0])[est + dst] = xx[j];
+        }
+        const uint32_t clen = front ? F : elen - F;
+        if (clen < 2 || bb == 0) {
+          const bool cio = !mv && io;
+          if (cb) a.keys_final[est + dst] = kk[j];
+          if (IDX && (cb || cio || a.idx64)) {
+            const uint32_t vv = cio ? dst : xx[j];
+            if (a.idx64) static_cast<int64_t *>(a.idx_final)[est + dst] = (int64_t)vv;
+            else static_cast<uint32_t *>(a.idx_final)[est + dst] = vv;
+          }
+        }
+      }
+    }
+    // the other entries go through batches, moved to the window's first
+    // lanes (a permutation: those entries first, in order, then the rest)
+    const uint64_t bigm = __ballot(!sm);
+    const uint32_t nb = (uint32_t)__popcll(bigm);
+    const uint64_t below = lane ? (~0ull >> (64u - lane)) : 0ull;
+    const uint32_t rk = !sm ? (uint32_t)__popcll(bigm & below) : nb + (uint32_t)__popcll(~bigm & below);
+    Seg sg = {};
+    uint32_t len = 0;
+    uint32_t myF = 0;  // the front count of the batch entry in this lane
+    if (nb) {
+      const int to = (int)(rk * 4u);
+      sg.start = (uint64_t)(uint32_t)__builtin_amdgcn_ds_permute(to, (int)(uint32_t)est) |
+                 ((uint64_t)(uint32_t)__builtin_amdgcn_ds_permute(to, (int)(uint32_t)(est >> 32)) << 32);
+      sg.meta = (uint32_t)__builtin_amdgcn_ds_permute(to, (int)emt);
+      const uint32_t pl = (uint32_t)__builtin_amdgcn_ds_permute(to, (int)elen);
+      len = lane < nb ? pl : 0u;
+    }
+    const uint32_t nwin = nb;
     const uint32_t cum = wave_incl_scan_dpp(len);  // over the window
     const uint32_t s0w = cum - len;                  // the entry's first window position
-    uint32_t myF = 0;  // the entry's front count, from its batch
     // batches: successive runs of the window's entries whose keys fit BATCH
     for (uint32_t b0 = 0; b0 < nwin;) {
       const uint32_t base = b0 ? (uint32_t)__shfl((int)cum, (int)b0 - 1) : 0u;
@@ -1713,10 +1804,13 @@ __global__ __launch_bounds__(256) void tiny_kernel(TinyArgs<KT> a) {
       if (mine) myF = Fs;
       b0 += m;
     }
+    // back to the entry's own lane
+    const uint32_t bF = (uint32_t)__shfl((int)myF, (int)rk);
+    if (!sm) eF = bF;
     // lane l: entry l of the window, whose parts the workgroup lists below
     const uint32_t wv = threadIdx.x >> 6;
-    s_rec.st[wv][v][lane] = sg.start;
-    s_rec.pk[wv][v][lane] = a.snapshot ? 0u : tiny_pack(sg.meta, len, myF);
+    s_rec.st[wv][v][lane] = est;
+    s_rec.pk[wv][v][lane] = a.snapshot ? 0u : tiny_pack(emt, elen, eF);
    }
    emit_tiny_block(a.l, a.w, a.mode, a.desc, s_rec, s_n, s_k, s_base, klive_wg, kiota_wg);
   }
