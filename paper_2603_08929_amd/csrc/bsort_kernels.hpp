@@ -1591,15 +1591,19 @@ __global__ __launch_bounds__(256) void tiny_kernel(TinyArgs<KT> a) {
     ln = 0;
     mt = 0;
     if (lane < window_of(t)) {
-      const Seg &q = a.list[g * per + t * 64u + lane];
-      st = q.start;
-      ln = (uint32_t)q.len;
-      mt = q.meta;
+      // only the fields used, each a load of its own width: a wider load
+      // leaves registers the compiler reuses at once, which makes it wait
+      // for the load on the spot
+      const Seg *q = a.list + (g * per + t * 64u + lane);
+      st = *reinterpret_cast<const uint64_t *>(&q->start);
+      ln = *reinterpret_cast<const uint32_t *>(&q->len);  // a tiny length fits the low word
+      mt = q->meta;
     }
   };
   uint64_t nst;
   uint32_t nln, nmt;
   load_entry(0, nst, nln, nmt);
+  asm volatile("" ::"v"(nst), "v"(nln), "v"(nmt));  // the first window's entries, awaited here
   for (uint32_t step = 0; step < steps; ++step) {
 #pragma unroll 1
    for (int v = 0; v < TINY_WIN; ++v) {
@@ -1655,15 +1659,19 @@ __global__ __launch_bounds__(256) void tiny_kernel(TinyArgs<KT> a) {
         const bool front = (fm >> j) & 1u;
         const uint32_t r = (uint32_t)__popc(fm & ((1u << j) - 1u));
         const uint32_t dst = mv ? (front ? r : F + (j - r)) : j;
-        if (mv) {
-          (cb ? a.keys[1] : a.keys[0])[est + dst] = kk[j];
-          if (IDX) (cb ? a.idx[1] : a.idx[0])[est + dst] = xx[j];
-        }
         const uint32_t clen = front ? F : elen - F;
-        if (clen < 2 || bb == 0) {
+        if (clen >= 2 && bb > 0) {
+          // a live part: its keys to the buffer the next level reads
+          if (mv) {
+            (cb ? a.keys[1] : a.keys[0])[est + dst] = kk[j];
+            if (IDX) (cb ? a.idx[1] : a.idx[0])[est + dst] = xx[j];
+          }
+        } else {
+          // a done part: straight to the caller's buffers (buffer 0 holds
+          // the caller's keys), unless the key is there already
           const bool cio = !mv && io;
-          if (cb) a.keys_final[est + dst] = kk[j];
-          if (IDX && (cb || cio || a.idx64)) {
+          if (mv || kb) a.keys_final[est + dst] = kk[j];
+          if (IDX && (mv || cb || cio || a.idx64)) {
             const uint32_t vv = cio ? dst : xx[j];
             if (a.idx64) static_cast<int64_t *>(a.idx_final)[est + dst] = (int64_t)vv;
             else static_cast<uint32_t *>(a.idx_final)[est + dst] = vv;
@@ -1671,6 +1679,10 @@ __global__ __launch_bounds__(256) void tiny_kernel(TinyArgs<KT> a) {
         }
       }
     }
+    // the next window's entries are complete here when the lane path ran
+    // (its wait covered them); saying so keeps the loop head from waiting
+    // for them behind this window's stores
+    asm volatile("" ::"v"(nst), "v"(nln), "v"(nmt));
     // the other entries go through batches, moved to the window's first
     // lanes (a permutation: those entries first, in order, then the rest)
     const uint64_t bigm = __ballot(!sm);
@@ -1783,16 +1795,19 @@ __global__ __launch_bounds__(256) void tiny_kernel(TinyArgs<KT> a) {
         const bool mv = F != 0 && F != ln;
         const uint32_t dst = mv ? (front ? r : F + (j - r)) : j;
         const int cb = mv ? 1 - kb : kb;
-        if (mv) {
-          (cb ? a.keys[1] : a.keys[0])[st + dst] = k[i];
-          if (IDX) (cb ? a.idx[1] : a.idx[0])[st + dst] = x[i];
-        }
-        // a key whose child is done goes to the caller's buffers now
         const uint32_t clen = front ? F : ln - F;
-        if (clen < 2 || bb == 0) {
+        if (clen >= 2 && bb > 0) {
+          // a live part: its keys to the buffer the next level reads
+          if (mv) {
+            (cb ? a.keys[1] : a.keys[0])[st + dst] = k[i];
+            if (IDX) (cb ? a.idx[1] : a.idx[0])[st + dst] = x[i];
+          }
+        } else {
+          // a done part: straight to the caller's buffers (buffer 0 holds
+          // the caller's keys), unless the key is there already
           const bool cio = !mv && io;
-          if (cb) a.keys_final[st + dst] = k[i];
-          if (IDX && (cb || cio || a.idx64)) {
+          if (mv || kb) a.keys_final[st + dst] = k[i];
+          if (IDX && (mv || cb || cio || a.idx64)) {
             // an identity index is the key's place in its user segment,
             // which a segment that has never moved starts
             const uint32_t v = cio ? dst : x[i];
