@@ -225,6 +225,9 @@ def timed(fn, reps, torch):
 
 # ------------------------------------------------------------------- extras
 
+SWEEP_DTYPES = None  # word-size sweep cases to run (names), None for all of them
+
+
 def extras_word_size(lib, torch, np, dev, stream):
     from paper_2603_08929_amd import workloads as W
     entry = {"u8": lib.bsort_u8, "i8": lib.bsort_i8, "i16": lib.bsort_i16, "f16": lib.bsort_f16,
@@ -236,6 +239,8 @@ def extras_word_size(lib, torch, np, dev, stream):
              ("f16", N28, "normal"), ("bf16", N28, "normal"), ("i32", N27, "uniform"),
              ("f32", N27, "normal"), ("u64", N27, "uniform"), ("i64", N27, "uniform"),
              ("f64", N27, "normal")]
+    if SWEEP_DTYPES is not None:
+        cases = [c for c in cases if c[0] in SWEEP_DTYPES]
     out = []
     for name, n, dist in cases:
         log(f"word-size sweep {name} n={n}")
@@ -814,7 +819,12 @@ def main() -> int:
     ap.add_argument("--event-steps", type=int, default=1,
                     help="timed steps whose level launches carry hipEvents (the first ones)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
+    ap.add_argument("--sweep-dtypes", default=None,
+                    help="comma-separated dtypes of the word-size sweep (default: all ten)")
     args = ap.parse_args()
+    global SWEEP_DTYPES
+    if args.sweep_dtypes:
+        SWEEP_DTYPES = set(args.sweep_dtypes.split(","))
     if args.summarize_pmc:
         sys.stdout.write(summarize_pmc(*args.summarize_pmc))
         return 0

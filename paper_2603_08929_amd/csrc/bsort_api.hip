@@ -196,7 +196,7 @@ bool make_layout(int key_bytes, uint64_t n, uint64_t B, bool with_idx, uint32_t 
   // without the LDS finish: the tiny-segment lists of two level parities
   L->tiny[0] = L->tiny[1] = 0;
   if (no_finish)
-    for (int i = 0; i < 2; ++i) { L->tiny[i] = off; off = up256(off + L->tnmax * sizeof(Seg)); }
+    for (int i = 0; i < 2; ++i) { L->tiny[i] = off; off = up256(off + L->tnmax * sizeof(TinySeg)); }
   L->keys1 = off; off = up256(off + n * (size_t)key_bytes);
   L->idx0 = L->idx1 = 0;
   if (with_idx) {
@@ -286,10 +286,10 @@ int launch_all(KT *keys, uint64_t n, const int64_t *offsets, uint64_t B, int mod
   la.t_med = FS::TFIN / 2;
   la.recount = (uint32_t)(2 * L.tmax);  // never read: the prep pass counts such segments
   la.tiny_next = nullptr;
-  Seg *tiny[2] = {nullptr, nullptr};
+  TinySeg *tiny[2] = {nullptr, nullptr};
   if (no_finish) {
-    tiny[0] = reinterpret_cast<Seg *>(scr + L.tiny[0]);
-    tiny[1] = reinterpret_cast<Seg *>(scr + L.tiny[1]);
+    tiny[0] = reinterpret_cast<TinySeg *>(scr + L.tiny[0]);
+    tiny[1] = reinterpret_cast<TinySeg *>(scr + L.tiny[1]);
   }
 
   SeedArgs sa;

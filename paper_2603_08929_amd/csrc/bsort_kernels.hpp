@@ -63,6 +63,15 @@ struct Seg {
 };
 static_assert(sizeof(Seg) == 32, "Seg layout");
 
+// A segment of the tiny lists (2 to TINY_MAX keys, no tiles): the fields a
+// tiny pass reads, in half the bytes of a Seg.
+struct TinySeg {
+  uint64_t start;
+  uint32_t len;
+  uint32_t meta;
+};
+static_assert(sizeof(TinySeg) == 16, "TinySeg layout");
+
 // Per live segment: AND/OR of the keys that went to the front (lo) and back
 // (hi) child, written by the level's tiles, and the split (number of front
 // keys, one word per segment slot).  The AND/OR words are replicated (with a
@@ -340,7 +349,7 @@ struct ListArgs {
   uint32_t t_tiny;      // ... and up to this size, one key per lane
   uint32_t t_med;       // ... and up to this size, half the full finish shape
   uint32_t recount;     // count base of segments whose counts the level did not make
-  Seg *tiny_next;       // level (lvl+1) tiny-segment list (nullptr: none)
+  TinySeg *tiny_next;   // level (lvl+1) tiny-segment list (nullptr: none)
 };
 
 struct Child {
@@ -471,7 +480,7 @@ __device__ void emit_children(const ListArgs &a, Child (&ch)[2]) {
     } else if (ch[c].kind == KIND_COPY) {
       a.cpy[cpos++] = s;
     } else if (ch[c].kind == KIND_TINY) {
-      a.tiny_next[tpos++] = s;
+      a.tiny_next[tpos++] = TinySeg{s.start, (uint32_t)s.len, s.meta};
     }
   }
 }
@@ -1437,7 +1446,7 @@ struct TinyArgs {
   uint32_t *idx[2];
   KT *keys_final;
   void *idx_final;
-  const Seg *list;  // this level's tiny segments
+  const TinySeg *list;  // this level's tiny segments
   ListArgs l;       // the next level's tiny list (tiny_next, next_level, hdr)
   int level, w, mode, desc, idx64, snapshot;
 };
@@ -1548,14 +1557,7 @@ __device__ __forceinline__ void emit_tiny_block(const ListArgs &a, int w, int mo
       const uint32_t pk = r.pk[wave][v][lane];
       if (tiny_child(r.st[wave][v][lane], pk & 0x7FFu, (pk >> 11) & 0x1FFu, pk >> 20, c, w, mode, desc,
                      cst, clen, cmeta)) {
-        Seg sg;
-        sg.start = cst;
-        sg.len = clen;
-        sg.meta = cmeta;
-        sg.tile0 = 0;
-        sg.cbase = 0;
-        sg.slot = 0;
-        a.tiny_next[pos++] = sg;
+        a.tiny_next[pos++] = TinySeg{cst, clen, cmeta};
       }
     }
   }
@@ -1591,13 +1593,13 @@ __global__ __launch_bounds__(256) void tiny_kernel(TinyArgs<KT> a) {
     ln = 0;
     mt = 0;
     if (lane < window_of(t)) {
-      // only the fields used, each a load of its own width: a wider load
-      // leaves registers the compiler reuses at once, which makes it wait
-      // for the load on the spot
-      const Seg *q = a.list + (g * per + t * 64u + lane);
-      st = *reinterpret_cast<const uint64_t *>(&q->start);
-      ln = *reinterpret_cast<const uint32_t *>(&q->len);  // a tiny length fits the low word
-      mt = q->meta;
+      // one 16-byte load whose every word is used (a loaded word left
+      // unused is a register the compiler reuses at once, which makes it
+      // wait for the load on the spot)
+      const TinySeg q = a.list[g * per + t * 64u + lane];
+      st = q.start;
+      ln = q.len;
+      mt = q.meta;
     }
   };
   uint64_t nst;
