@@ -68,9 +68,9 @@ def check_properties(name, src, keys, idx, desc, seg_id=None, seg_start=None):
     assert bool((idx[1:][ties] > idx[:-1][ties]).all()), "equal keys out of input order"
 
 
-def sort_call(name, t, desc, idx=True):
+def sort_call(name, t, desc, idx=True, flags=0):
     n = t.numel()
-    fl = _lib.DESCENDING if desc else 0
+    fl = flags | (_lib.DESCENDING if desc else 0)
     ind = torch.empty(n, dtype=torch.int32, device="cuda") if idx else None
     need = _lib.bsort_scratch_bytes(key_bytes(name), n, 1, int(idx), fl)
     scratch = torch.empty(need, dtype=torch.uint8, device="cuda")
@@ -199,6 +199,26 @@ def test_word_size_sweep(case):
         check_properties(name, src, t, idx, flags_desc)
         check_samples(name, bits, t.cpu().numpy().view(DTYPES[name][2]), idx.cpu().numpy(),
                       flags_desc, sample_ranks(n, 0, 8))
+        del t, idx
+
+
+@pytest.mark.parametrize("case", [("i32", 1 << 27, lambda: W.uniform_bits("i32", 1 << 27, 0)),
+                                  ("f32", 1 << 27, lambda: W.normal_bits("f32", 1 << 27, 0)),
+                                  ("u64", 1 << 27, lambda: W.uniform_bits("u64", 1 << 27, 0))],
+                         ids=lambda c: c[0])
+def test_word_size_sweep_plain(case):
+    """Plain mode (every bit a global level, the late ones in the tiny-segment
+    pass) at the sweep's full sizes, both directions."""
+    name, n, make = case
+    print(f"full size plain {name} n={n}", flush=True)
+    bits = make()
+    src = to_device(bits, name)
+    for flags_desc in (False, True):
+        t = src.clone()
+        idx = sort_call(name, t, flags_desc, flags=_lib.PLAIN)
+        check_properties(name, src, t, idx, flags_desc)
+        check_samples(name, bits, t.cpu().numpy().view(DTYPES[name][2]), idx.cpu().numpy(),
+                      flags_desc, sample_ranks(n, 0, 9))
         del t, idx
 
 
