@@ -327,9 +327,9 @@ __global__ void validate_kernel(const int64_t *offsets, uint64_t B, uint64_t n, 
 
 constexpr int KIND_NONE = 0, KIND_LIVE = 1, KIND_FINISH = 2, KIND_COPY = 3, KIND_TINY = 4;
 
-// Without the LDS finish (every bit a global level), a live segment of at
-// most this many keys is split by one thread per level instead of taking a
-// whole level tile.
+// Without the LDS finish (every bit a global level), a segment of at most
+// this many keys leaves the level tiles for the tiny-segment pass, which
+// splits many such segments per wave instead of one per level tile.
 constexpr uint32_t TINY_MAX = 256;
 
 struct ListArgs {
@@ -1428,16 +1428,20 @@ __global__ __launch_bounds__(256) void tail_kernel(TailArgs<KT> a) {
 // Without the LDS finish every bit is a global level, and late levels hold
 // many segments of a few keys: giving each one a whole level tile would
 // make such a level cost a tile per segment.  Segments of at most TINY_MAX
-// keys go to a list of their own instead, and a wave packs consecutive
-// entries of it, whole, into one batch of 64 x TINY_IPT positions (key
-// position q at lane q % 64, item q / 64, as in a level tile).  A key finds
-// its segment from the batch's segment starts (one mask per item), and the
-// same stable split as a level tile's follows with ranks counted within the
-// segment: front keys, then back keys, both in input order, into the other
-// buffer (a split with an empty side moves nothing).  Children go to the
-// next level's tiny list, or, once done (one key, or bit 0 split), straight
-// to the caller's buffers.  With `snapshot` set the segments are only
-// written out as they stand (a sort stopped at this level).
+// keys go to a list of their own instead (16-byte entries), which a wave
+// takes 64 entries (a window) at a time.  An entry of at most TINY_LANE
+// keys is split by its own lane: its keys in registers, a front mask, ranks
+// by popcount.  The longer entries are moved to the window's first lanes
+// and packed, whole, into batches of 64 x TINY_IPT positions (key position
+// q at lane q % 64, item q / 64, as in a level tile); a key finds its
+// segment from the batch's segment starts (one mask per item) and ranks are
+// counted within the segment from the items' ballots.  Either way the split
+// is a level tile's: front keys, then back keys, both in input order, into
+// the other buffer (a split with an empty side moves nothing).  Children go
+// to the next level's tiny list in the order of their parents, or, once
+// done (one key, or bit 0 split), straight to the caller's buffers.  With
+// `snapshot` set the segments are only written out as they stand (a sort
+// stopped at this level).
 constexpr int TINY_IPT = 4;
 
 template <typename KT>
