@@ -1289,7 +1289,13 @@ __device__ __forceinline__ void level_body(const LevelArgs<KT> &a) {
   const uint32_t ntiles = (uint32_t)(ld_relaxed(&a.hdr->packed[a.level]) & 0xffffffffu);
   const rsrc_t mr = make_rsrc(a.meta, a.off.range);
   const uint32_t G = gridDim.x * 4u;
-  const uint32_t g = uni(blockIdx.x * 4u + (threadIdx.x >> 6));
+  // Workgroups go to the eight XCDs in turn (block b to XCD b % 8), each
+  // with its own L2.  Numbering the waves XCD by XCD gives every XCD runs of
+  // G/8 consecutive tiles per round, so the cache lines that two adjacent
+  // tiles' output runs share are mostly written through one L2.
+  const uint32_t nb = gridDim.x;
+  const uint32_t bx = (nb & 7u) ? blockIdx.x : (blockIdx.x & 7u) * (nb >> 3) + (blockIdx.x >> 3);
+  const uint32_t g = uni(bx * 4u + (threadIdx.x >> 6));
   uint32_t t = g;
   WaveAcc<RT> acc;
   acc.slot = ~0u;
