@@ -68,6 +68,22 @@ def test_log_uniform_batch(name):
     check_segments(name, bits, lengths, True, keys, idx, offs)
 
 
+@pytest.mark.parametrize("name", ["u8", "i8", "i16", "f16", "i32", "f64", "u64"])
+def test_plain_small_segments(name):
+    """Plain mode over many small user segments (0 to 300 keys): most start in
+    the tiny-segment pass at the top bit, where the sign rules of signed and
+    float keys apply, some in its lane path, some in its batches."""
+    rng = np.random.default_rng(21)
+    lengths = rng.integers(0, 301, size=1500)
+    lengths[rng.integers(0, lengths.size, size=200)] = rng.integers(0, 9, size=200)
+    bits = W.mixed_bits(name, int(lengths.sum()), 21)
+    print(f"segmented plain {name} n={bits.size}", flush=True)
+    for asc in (True, False):
+        for idx in ("u32", "i64", None):
+            keys, ind, offs = gpu_segmented(name, bits, lengths, asc=asc, flags=_lib.PLAIN, idx=idx)
+            check_segments(name, bits, lengths, asc, keys, ind, offs)
+
+
 def test_equals_single_array_calls():
     name = "i32"
     lengths = [5000, 1, 9000, 70000, 0, 8192, 33]
